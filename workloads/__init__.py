@@ -1,0 +1,99 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only draws random numbers and names workload shapes.  It holds
+none of the method's arithmetic, so both the oracle and the HIP path may use
+it without sharing any computation.
+
+Point sets follow the workload descriptions used for the experiments: points
+uniform in the unit cube, or uniform on the unit sphere surface (normalised
+standard-normal triples).  The paper itself uses constant-density balls and
+spheres (Section 6); the unit cube/sphere recipes stand in for them.
+
+Array conventions
+-----------------
+* points: float64, shape (N, 3), C-contiguous, in ORIGINAL order.
+* rhs / omega: float64, shape (N, ncols), Fortran (column-major) order, rows
+  indexed by ORIGINAL point index.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+KERNELS = ("gaussian", "matern32", "exponential", "imq")
+
+
+def points(kind: str, n: int, seed: int) -> np.ndarray:
+    """Seeded point set: 'cube' = iid U[0,1)^3, 'sphere' = unit-sphere surface."""
+    rng = np.random.default_rng(seed)
+    if kind == "cube":
+        x = rng.random((n, 3))
+    elif kind == "sphere":
+        g = rng.standard_normal((n, 3))
+        x = g / np.linalg.norm(g, axis=1, keepdims=True)
+    else:
+        raise ValueError(f"unknown point set {kind!r}")
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def gaussian_matrix(n: int, ncols: int, seed: int) -> np.ndarray:
+    """iid N(0,1) matrix, column-major; used for right-hand sides and Omega."""
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.standard_normal((n, ncols)))
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One synthetic problem: points, kernel, shift and solver tolerances."""
+    name: str
+    n: int
+    point_set: str
+    kernel: str
+    ell: float
+    shift: float
+    leaf: int
+    h2_tol: float
+    hss_tol: float
+    max_rank: int
+    oversample: int
+    nrhs: int
+    pcg_tol: float
+    eta: float = 1.0
+    seed_base: int = 0
+
+    @property
+    def s(self) -> int:
+        return self.max_rank + self.oversample
+
+    def points(self) -> np.ndarray:
+        return points(self.point_set, self.n, 1000 + self.seed_base)
+
+    def rhs(self) -> np.ndarray:
+        return gaussian_matrix(self.n, self.nrhs, 2000 + self.seed_base)
+
+    def omega(self) -> np.ndarray:
+        return gaussian_matrix(self.n, self.s, 3000 + self.seed_base)
+
+    def with_(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+# Small case: Gaussian exp(-r^2/0.5^2) + 1e-2 I on 2,000 cube points.
+SMALL = Workload(name="gaussian-l0.5-N2000-cube", n=2000, point_set="cube",
+                 kernel="gaussian", ell=0.5, shift=1e-2, leaf=64, h2_tol=1e-8,
+                 hss_tol=1e-2, max_rank=100, oversample=10, nrhs=1,
+                 pcg_tol=1e-8, seed_base=0)
+
+# Matern-3/2, l = 0.1, + 1e-4 I on 100,000 cube points.
+MEDIUM = Workload(name="matern32-l0.1-N100k-cube", n=100_000, point_set="cube",
+                  kernel="matern32", ell=0.1, shift=1e-4, leaf=200,
+                  h2_tol=1e-8, hss_tol=1e-2, max_rank=100, oversample=10,
+                  nrhs=1, pcg_tol=1e-8, seed_base=1)
+
+# Gaussian l = 0.2 + 1e-3 I on 1,000,000 cube points, 16 right-hand sides.
+LARGE = Workload(name="gaussian-l0.2-N1M-cube", n=1_000_000, point_set="cube",
+                 kernel="gaussian", ell=0.2, shift=1e-3, leaf=400, h2_tol=1e-6,
+                 hss_tol=1e-1, max_rank=100, oversample=10, nrhs=16,
+                 pcg_tol=1e-8, seed_base=3)
+
+BY_NAME = {w.name: w for w in (SMALL, MEDIUM, LARGE)}
