@@ -1,0 +1,205 @@
+/*
+ * spdhss.h -- C ABI of the MI355X library that builds an SPD HSS
+ * preconditioner from an H^2 representation of a dense SPD kernel matrix and
+ * solves sigma*I + K(X, X) with preconditioned CG.
+ *
+ * The method is that of "Efficient construction of an HSS preconditioner for
+ * symmetric positive definite H^2 matrices" (Xing, Huang, Chow):
+ *   - the problem: SPD kernel systems sigma*I + K(X, X) on 3-D points, solved
+ *     by PCG with an SPD HSS preconditioner (Section 6, kernel list and
+ *     Section 6.2 diagonal shift);
+ *   - H^2 representation and block types: Section 5.1 (eq. uniformbasis_h2),
+ *     Section 5.2.2 (Type-1/2/3 blocks);
+ *   - the construction: Algorithm 5.3 with Algorithms 5.1 and 5.2;
+ *   - the HSS form and its nested factors: Sections 2 and 4 (eqs. nested,
+ *     Aii0, Si0, Si, Cij, Mijk, Rik).
+ *
+ * Conventions shared by every entry point
+ *   - Ownership: the caller owns every pointer argument.  The library copies
+ *     what it keeps and never retains a caller pointer after returning.
+ *     Handles are self-contained (an HSS handle does not borrow the H^2 handle,
+ *     a ULV handle does not borrow the HSS handle).
+ *   - Memory: unless stated otherwise, array arguments are DEVICE pointers on
+ *     the current HIP device.  Vectors are column-major, N x nrhs with leading
+ *     dimension ld >= N, rows in the ORIGINAL point order.
+ *   - Streams: `stream` is a hipStream_t (NULL = default stream).  Work is
+ *     ordered on it; functions that produce host-visible results (handles,
+ *     iteration counts) synchronize it before returning.
+ *   - Errors: every function returns an spd_status; nothing throws or aborts
+ *     across the ABI.  On failure *out is set to NULL and spd_last_error()
+ *     returns a thread-local message (for SPD_E_NOT_SPD it names the node and
+ *     level whose factorization failed).
+ *   - Determinism: results are bitwise reproducible for identical inputs on
+ *     the same device (no floating-point atomics).
+ *   - Precision: all arithmetic is IEEE FP64.
+ */
+#ifndef SPDHSS_H
+#define SPDHSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPD_OK = 0,
+  SPD_E_INVALID = -1,       /* bad argument (null pointer, size, option) */
+  SPD_E_NOMEM = -2,         /* device allocation failed */
+  SPD_E_NOT_SPD = -3,       /* a Cholesky factorization met a non-positive pivot */
+  SPD_E_NOT_CONVERGED = -4, /* PCG reached maxit before rtol on some column */
+  SPD_E_DEVICE = -5         /* a HIP runtime call failed */
+} spd_status;
+
+/* Kernel functions, length-scale form (r = |x - y|):
+ *   GAUSSIAN     exp(-r^2 / ell^2)
+ *   MATERN32     (1 + sqrt(3) r / ell) exp(-sqrt(3) r / ell)
+ *   EXPONENTIAL  exp(-r / ell)
+ *   IMQ          1 / sqrt(r^2 + ell^2)
+ * The matrix is shift * I + K(X, X) (Section 6 kernels, Section 6.2 shift). */
+typedef enum {
+  SPD_K_GAUSSIAN = 0,
+  SPD_K_MATERN32 = 1,
+  SPD_K_EXPONENTIAL = 2,
+  SPD_K_IMQ = 3
+} spd_kernel_kind;
+
+typedef struct {
+  int32_t kind;   /* spd_kernel_kind */
+  double ell;     /* length scale (> 0) */
+  double shift;   /* diagonal shift sigma (>= 0) */
+} spd_kernel;
+
+/* H^2 construction options (Section 5.1; construction method: proxy-point
+ * interpolative decomposition, this library's choice since the paper does not
+ * describe one). */
+typedef struct {
+  int32_t leaf_size;        /* max points per leaf of the binary kd-tree */
+  double eta;               /* admissibility: r_i + r_j <= eta * |c_i - c_j| */
+  double tol;               /* relative truncation of the ID (|R_tt| > tol |R_00|) */
+  int32_t proxy_shells;     /* proxy spheres per node (>= 1) */
+  int32_t proxy_per_shell;  /* Fibonacci points per sphere (>= 4) */
+} spd_h2_opts;
+
+/* SPD HSS construction options (Algorithm 5.3, Algorithm 5.1). */
+typedef struct {
+  double tol;           /* relative CPQR threshold, 0 = fixed rank max_rank */
+  int32_t max_rank;     /* rank cap r (>= 0; 0 gives block Jacobi) */
+  int32_t oversample;   /* p; Omega has max_rank + oversample columns */
+  uint64_t seed;        /* seed of the internal Gaussian generator */
+  const double* omega;  /* optional DEVICE N x (max_rank+oversample), column-
+                           major, ld = N, ORIGINAL point order; NULL = internal
+                           generator */
+} spd_hss_opts;
+
+typedef struct spd_h2* spd_h2_t;
+typedef struct spd_hss* spd_hss_t;
+typedef struct spd_ulv* spd_ulv_t;
+
+/* Build the H^2 representation of shift*I + K(X, X).
+ * points: DEVICE, n x 3 row-major (x0 y0 z0 x1 ...), original order; n >= 1.
+ * Builds the kd-tree, the near/coupling lists, the proxy-point ID bases and
+ * stores the dense near blocks and the coupling blocks on the device. */
+spd_status h2_build(const double* points, int64_t n, spd_kernel kernel,
+                    const spd_h2_opts* opts, void* stream, spd_h2_t* out);
+
+/* Algorithm 5.3: build the SPD HSS approximation of the H^2 matrix A.
+ * Fails with SPD_E_NOT_SPD when a leaf block or an I + bold B_ii block is not
+ * positive definite (which cannot happen when A is SPD, Section 3.2). */
+spd_status spdhss_build(spd_h2_t A, const spd_hss_opts* opts, void* stream,
+                        spd_hss_t* out);
+
+/* Nested symmetric factorization of the HSS matrix for solves: keeps the leaf
+ * Cholesky factors S_i, bases V_i, factors F_i of I + bold B_ii and V-bar_i,
+ * and factors the root block I + bold B_root (eqs. Aii0, Si0, Si). */
+spd_status ulv_factor(spd_hss_t M, void* stream, spd_ulv_t* out);
+
+/* x = M^{-1} b for the factored HSS matrix; b, x: DEVICE N x nrhs, ld >= N,
+ * original order.  b and x may alias. */
+spd_status ulv_apply(spd_ulv_t F, const double* b, double* x, int32_t nrhs,
+                     int64_t ld, void* stream);
+
+/* y = A x with the H^2 representation (upward, coupling, downward and
+ * near-field passes); x, y: DEVICE N x nrhs, ld >= N, original order; must not
+ * alias. */
+spd_status h2_matvec(spd_h2_t A, const double* x, double* y, int32_t nrhs,
+                     int64_t ld, void* stream);
+
+/* Solve A x = b column by column with PCG preconditioned by M (M = NULL: plain
+ * CG), x0 = 0, stopping column c when ||r_c|| <= rtol * ||b_c||.
+ * b, x: DEVICE N x nrhs (ld >= N, original order).
+ * iters, relres: HOST arrays of nrhs entries (may be NULL): iterations taken
+ * and the true relative residual ||b - A x|| / ||b|| at exit.
+ * Returns SPD_E_NOT_CONVERGED if some column did not reach rtol in maxit. */
+spd_status pcg_solve(spd_h2_t A, spd_ulv_t M, const double* b, double* x,
+                     int32_t nrhs, int64_t ld, double rtol, int32_t maxit,
+                     void* stream, int32_t* iters, double* relres);
+
+void h2_destroy(spd_h2_t A);
+void spdhss_destroy(spd_hss_t M);
+void ulv_destroy(spd_ulv_t F);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char* spd_last_error(void);
+
+/* ---- introspection (tests, statistics).  Output buffers are HOST memory;
+ * `bytes` is their capacity; SPD_E_INVALID if too small. ------------------- */
+typedef enum {
+  SPD_Q_N = 0,            /* int64[1]: number of points */
+  SPD_Q_LEVELS = 1,       /* int64[1]: L */
+  SPD_Q_PERM = 2,         /* int64[N]: tree position -> original index */
+  SPD_Q_NODE_START = 3,   /* int64[nnodes+1]-style: start of every node, heap order */
+  SPD_Q_H2_RANK = 4,      /* int32[nnodes]: skeleton size k_v */
+  SPD_Q_SKELETON = 5,     /* int64[sum k_v]: skeleton original indices, node by node */
+  SPD_Q_NEAR_PTR = 6,     /* int64[nnodes+1]: CSR of near lists */
+  SPD_Q_NEAR_IDX = 7,     /* int32[..] */
+  SPD_Q_COUP_PTR = 8,     /* int64[nnodes+1]: CSR of coupling lists */
+  SPD_Q_COUP_IDX = 9,     /* int32[..] */
+  SPD_Q_NNODES = 10,      /* int64[1] */
+  SPD_Q_BYTES = 11,       /* int64[1]: device bytes held by the handle */
+  SPD_Q_H2_TIMES = 12     /* double[4]: seconds for tree+lists, bases, blocks, total */
+} spd_h2_query;
+
+spd_status spd_h2_query_get(spd_h2_t A, int32_t what, void* host_out, int64_t bytes);
+
+typedef enum {
+  SPD_HQ_RANK = 0,       /* int32[nnodes]: HSS rank r_v (root: 0) */
+  SPD_HQ_PIVOTS = 1,     /* int32[r_v] of node `node`: CPQR pivot columns */
+  SPD_HQ_BASIS = 2,      /* double[rows x r_v]: V_v (leaf) or V-bar_v, col-major */
+  SPD_HQ_TRANSFER = 3,   /* double[rho x r_v]: R_v = F_v V-bar_v (nonleaf) */
+  SPD_HQ_PHIU = 4,       /* double[r_v x k_v]: Phi_v U_v^H2 */
+  SPD_HQ_COUPLING = 5,   /* double[r_v x r_node2]: B_{v,node2} (a near or coupling pair) */
+  SPD_HQ_FACTOR = 6,     /* double[n x n]: S_v (leaf) or F_v (nonleaf, root), lower */
+  SPD_HQ_ROWS = 7,       /* int64[1]: row count of the node's basis (n_v or rho_v) */
+  SPD_HQ_BYTES = 8,      /* int64[1]: device bytes held */
+  SPD_HQ_TIMES = 9,      /* double[8]: seconds per phase of the build */
+  SPD_HQ_FLOPS = 10      /* double[4]: algorithmic flops of the build phases */
+} spd_hss_query;
+
+spd_status spd_hss_query_get(spd_hss_t M, int32_t what, int32_t node,
+                             int32_t node2, void* host_out, int64_t bytes);
+
+/* ---- kernel test hooks: run one batched device kernel on caller buffers.
+ * All pointers are DEVICE pointers; shapes are uniform across the batch.
+ * They exist so that each kernel can be compared on its own against the
+ * CPU oracle; the solver never needs them. ---------------------------------- */
+/* C_b = beta C_b + alpha op(A_b) op(B_b), batch stride = matrix size */
+spd_status spd_test_gemm(const double* A, const double* B, double* C, int32_t batch,
+                         int32_t m, int32_t n, int32_t k, int32_t transA,
+                         int32_t transB, double alpha, double beta, void* stream);
+/* in-place lower Cholesky of batch n x n matrices; fail[b] = 1 if not SPD */
+spd_status spd_test_chol(double* A, int32_t batch, int32_t n, int32_t* fail, void* stream);
+/* B_b <- op(L_b)^{-1} B_b (lower L; upper = 1 reads L as upper triangular) */
+spd_status spd_test_trsm(const double* L, double* B, int32_t batch, int32_t n,
+                         int32_t nrhs, int32_t trans, int32_t upper, void* stream);
+/* column-pivoted QR of batch m x n matrices (A destroyed): Q (m x maxrank),
+ * piv, rank, diag; which = 0 register kernel, 1 global-memory kernel */
+spd_status spd_test_cpqr(double* A, double* Q, int32_t* piv, int32_t* rank,
+                         double* diag, int32_t batch, int32_t m, int32_t n,
+                         int32_t maxrank, double tol, int32_t which, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPDHSS_H */

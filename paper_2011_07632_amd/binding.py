@@ -1,0 +1,359 @@
+"""ctypes binding of libspdhss.so: argument marshalling only.
+
+Names follow the C ABI: h2_build, spdhss_build, ulv_factor, ulv_apply,
+h2_matvec, pcg_solve.  Arrays are torch tensors on the HIP device; vectors are
+(N, ncols) column-major (``stride(0) == 1``) or 1-D, rows in the original point
+order, FP64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspdhss.so")
+
+KERNELS = {"gaussian": 0, "matern32": 1, "exponential": 2, "imq": 3}
+
+SPD_OK, SPD_E_INVALID, SPD_E_NOMEM, SPD_E_NOT_SPD, SPD_E_NOT_CONVERGED, SPD_E_DEVICE = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "SPD_OK", -1: "SPD_E_INVALID", -2: "SPD_E_NOMEM", -3: "SPD_E_NOT_SPD",
+                -4: "SPD_E_NOT_CONVERGED", -5: "SPD_E_DEVICE"}
+
+# query ids (include/spdhss.h)
+Q = dict(N=0, LEVELS=1, PERM=2, NODE_START=3, H2_RANK=4, SKELETON=5, NEAR_PTR=6, NEAR_IDX=7,
+         COUP_PTR=8, COUP_IDX=9, NNODES=10, BYTES=11, H2_TIMES=12)
+HQ = dict(RANK=0, PIVOTS=1, BASIS=2, TRANSFER=3, PHIU=4, COUPLING=5, FACTOR=6, ROWS=7, BYTES=8,
+          TIMES=9, FLOPS=10)
+
+
+class SpdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Kernel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("ell", C.c_double), ("shift", C.c_double)]
+
+
+class _H2Opts(C.Structure):
+    _fields_ = [("leaf_size", C.c_int32), ("eta", C.c_double), ("tol", C.c_double),
+                ("proxy_shells", C.c_int32), ("proxy_per_shell", C.c_int32)]
+
+
+class _HSSOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_rank", C.c_int32), ("oversample", C.c_int32),
+                ("seed", C.c_uint64), ("omega", C.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2011_07632_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "h2_build": [vp, i64, _Kernel, C.POINTER(_H2Opts), vp, C.POINTER(vp)],
+        "spdhss_build": [vp, C.POINTER(_HSSOpts), vp, C.POINTER(vp)],
+        "ulv_factor": [vp, vp, C.POINTER(vp)],
+        "ulv_apply": [vp, vp, vp, i32, i64, vp],
+        "h2_matvec": [vp, vp, vp, i32, i64, vp],
+        "pcg_solve": [vp, vp, vp, vp, i32, i64, dbl, i32, vp, vp, vp],
+        "spd_h2_query_get": [vp, i32, vp, i64],
+        "spd_hss_query_get": [vp, i32, i32, i32, vp, i64],
+        "spd_test_gemm": [vp, vp, vp, i32, i32, i32, i32, i32, i32, dbl, dbl, vp],
+        "spd_test_chol": [vp, i32, i32, vp, vp],
+        "spd_test_trsm": [vp, vp, i32, i32, i32, i32, i32, vp],
+        "spd_test_cpqr": [vp, vp, vp, vp, vp, i32, i32, i32, i32, dbl, i32, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    for name in ("h2_destroy", "spdhss_destroy", "ulv_destroy"):
+        f = getattr(L, name)
+        f.argtypes = [vp]
+        f.restype = None
+    L.spd_last_error.argtypes = []
+    L.spd_last_error.restype = C.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def _check(code: int):
+    if code != SPD_OK:
+        raise SpdError(code, lib.spd_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _as_cols(t: torch.Tensor, n: int) -> tuple[torch.Tensor, int, int]:
+    """(tensor, ncols, ld) of a device FP64 vector block in column-major form."""
+    if not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("expected a float64 device tensor")
+    if t.dim() == 1:
+        if t.shape[0] != n or t.stride(0) != 1:
+            raise ValueError("vector length / stride mismatch")
+        return t, 1, n
+    if t.dim() != 2 or t.shape[0] != n or t.stride(0) != 1 or t.stride(1) < n:
+        raise ValueError("expected an (N, ncols) column-major tensor")
+    return t, t.shape[1], t.stride(1)
+
+
+def cols_like(n: int, ncols: int, device) -> torch.Tensor:
+    """An uninitialised (n, ncols) column-major FP64 device tensor."""
+    return torch.empty((ncols, n), dtype=torch.float64, device=device).t()
+
+
+class H2Matrix:
+    """H^2 representation of shift*I + K(X, X) (handle)."""
+
+    def __init__(self, handle: int, n: int, device):
+        self._h = C.c_void_p(handle)
+        self.n = n
+        self.device = device
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            try:
+                lib.h2_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def _get(self, what: str, dtype, count: int) -> np.ndarray:
+        out = np.empty(count, dtype=dtype)
+        _check(lib.spd_h2_query_get(self._h, Q[what], out.ctypes.data, out.nbytes))
+        return out
+
+    def scalar(self, what: str) -> int:
+        return int(self._get(what, np.int64, 1)[0])
+
+    @property
+    def levels(self) -> int:
+        return self.scalar("LEVELS")
+
+    @property
+    def nnodes(self) -> int:
+        return self.scalar("NNODES")
+
+    def perm(self) -> np.ndarray:
+        return self._get("PERM", np.int64, self.n)
+
+    def node_start(self) -> np.ndarray:
+        return self._get("NODE_START", np.int64, self.nnodes + 1)
+
+    def ranks(self) -> np.ndarray:
+        return self._get("H2_RANK", np.int32, self.nnodes)
+
+    def skeletons(self) -> dict[int, np.ndarray]:
+        k = self.ranks()
+        flat = self._get("SKELETON", np.int64, int(k[1:].sum()))
+        out, pos = {}, 0
+        for v in range(1, self.nnodes):
+            out[v] = flat[pos:pos + k[v]]
+            pos += k[v]
+        return out
+
+    def lists(self):
+        nn = self.nnodes
+        npt = self._get("NEAR_PTR", np.int64, nn + 1)
+        nid = self._get("NEAR_IDX", np.int32, int(npt[-1]))
+        cpt = self._get("COUP_PTR", np.int64, nn + 1)
+        cid = self._get("COUP_IDX", np.int32, int(cpt[-1]))
+        near = {v: nid[npt[v]:npt[v + 1]].tolist() for v in range(nn)}
+        coup = {v: cid[cpt[v]:cpt[v + 1]].tolist() for v in range(nn)}
+        return near, coup
+
+    def times(self) -> np.ndarray:
+        return self._get("H2_TIMES", np.float64, 4)
+
+    def device_bytes(self) -> int:
+        return self.scalar("BYTES")
+
+
+class HSSMatrix:
+    """SPD HSS approximation built by Algorithm 5.3 (handle)."""
+
+    def __init__(self, handle: int, h2: H2Matrix, s: int):
+        self._h = C.c_void_p(handle)
+        self.n = h2.n
+        self.nnodes = h2.nnodes
+        self.s = s
+        self.device = h2.device
+        self._hk = h2.ranks()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            try:
+                lib.spdhss_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def _q(self, what, node, node2, dtype, count):
+        out = np.empty(max(count, 1), dtype=dtype)
+        _check(lib.spd_hss_query_get(self._h, HQ[what], node, node2, out.ctypes.data, out.nbytes))
+        return out[:count]
+
+    def ranks(self) -> np.ndarray:
+        return self._q("RANK", 0, 0, np.int32, self.nnodes)
+
+    def rows(self, v: int) -> int:
+        return int(self._q("ROWS", v, 0, np.int64, 1)[0])
+
+    def pivots(self, v: int) -> np.ndarray:
+        return self._q("PIVOTS", v, 0, np.int32, int(self.ranks()[v]))
+
+    def basis(self, v: int) -> np.ndarray:
+        r, m = int(self.ranks()[v]), self.rows(v)
+        return self._q("BASIS", v, 0, np.float64, m * r).reshape(r, m).T
+
+    def transfer(self, v: int) -> np.ndarray:
+        r, m = int(self.ranks()[v]), self.rows(v)
+        return self._q("TRANSFER", v, 0, np.float64, m * r).reshape(r, m).T
+
+    def phiu(self, v: int) -> np.ndarray:
+        r, k = int(self.ranks()[v]), int(self._hk[v])
+        return self._q("PHIU", v, 0, np.float64, r * k).reshape(k, r).T
+
+    def coupling(self, i: int, j: int) -> np.ndarray:
+        rk = self.ranks()
+        ri, rj = int(rk[i]), int(rk[j])
+        return self._q("COUPLING", i, j, np.float64, ri * rj).reshape(rj, ri).T
+
+    def factor(self, v: int) -> np.ndarray:
+        m = self.rows(v)
+        return self._q("FACTOR", v, 0, np.float64, m * m).reshape(m, m).T
+
+    def times(self) -> np.ndarray:
+        return self._q("TIMES", 0, 0, np.float64, 8)
+
+    def device_bytes(self) -> int:
+        return int(self._q("BYTES", 0, 0, np.int64, 1)[0])
+
+
+class ULVFactor:
+    def __init__(self, handle: int, n: int, device):
+        self._h = C.c_void_p(handle)
+        self.n = n
+        self.device = device
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            try:
+                lib.ulv_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+# ------------------------------------------------------------------ entry points --
+def h2_build(points: torch.Tensor, kernel: str, ell: float, shift: float, leaf: int = 64,
+             tol: float = 1e-8, eta: float = 1.0, proxy_shells: int = 8, proxy_per_shell: int = 128,
+             stream=None) -> H2Matrix:
+    if not points.is_cuda or points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be an (N, 3) float64 device tensor")
+    points = points.contiguous()
+    k = _Kernel(KERNELS[kernel], float(ell), float(shift))
+    o = _H2Opts(int(leaf), float(eta), float(tol), int(proxy_shells), int(proxy_per_shell))
+    out = C.c_void_p()
+    _check(lib.h2_build(points.data_ptr(), points.shape[0], k, C.byref(o), _stream(stream), C.byref(out)))
+    return H2Matrix(out.value, points.shape[0], points.device)
+
+
+def spdhss_build(A: H2Matrix, tol: float, max_rank: int = 100, oversample: int = 10, seed: int = 0,
+                 omega: torch.Tensor | None = None, stream=None) -> HSSMatrix:
+    s = max_rank + oversample
+    if omega is not None:
+        omega, nc, ld = _as_cols(omega, A.n)
+        if nc != s or ld != A.n:
+            raise ValueError("omega must be (N, max_rank + oversample) with ld = N")
+    o = _HSSOpts(float(tol), int(max_rank), int(oversample), int(seed), _ptr(omega))
+    out = C.c_void_p()
+    _check(lib.spdhss_build(A._h, C.byref(o), _stream(stream), C.byref(out)))
+    return HSSMatrix(out.value, A, s)
+
+
+def ulv_factor(M: HSSMatrix, stream=None) -> ULVFactor:
+    out = C.c_void_p()
+    _check(lib.ulv_factor(M._h, _stream(stream), C.byref(out)))
+    return ULVFactor(out.value, M.n, M.device)
+
+
+def ulv_apply(F: ULVFactor, b: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    b, nc, ld = _as_cols(b, F.n)
+    if out is None:
+        out = cols_like(F.n, nc, b.device) if b.dim() == 2 else torch.empty_like(b)
+    out_, nc2, ld2 = _as_cols(out, F.n)
+    if nc2 != nc or ld2 != ld:
+        raise ValueError("output shape / leading dimension must match the input")
+    _check(lib.ulv_apply(F._h, b.data_ptr(), out.data_ptr(), nc, ld, _stream(stream)))
+    return out
+
+
+def h2_matvec(A: H2Matrix, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    x, nc, ld = _as_cols(x, A.n)
+    if out is None:
+        out = cols_like(A.n, nc, x.device) if x.dim() == 2 else torch.empty_like(x)
+    out_, nc2, ld2 = _as_cols(out, A.n)
+    if nc2 != nc or ld2 != ld:
+        raise ValueError("output shape / leading dimension must match the input")
+    _check(lib.h2_matvec(A._h, x.data_ptr(), out.data_ptr(), nc, ld, _stream(stream)))
+    return out
+
+
+def pcg_solve(A: H2Matrix, M: ULVFactor | None, b: torch.Tensor, rtol: float = 1e-8, maxit: int = 1000,
+              out: torch.Tensor | None = None, stream=None, raise_on_nonconvergence: bool = True):
+    """Returns (x, iterations per column, true relative residual per column)."""
+    b, nc, ld = _as_cols(b, A.n)
+    if out is None:
+        out = cols_like(A.n, nc, b.device) if b.dim() == 2 else torch.empty_like(b)
+    _as_cols(out, A.n)
+    iters = np.zeros(nc, dtype=np.int32)
+    relres = np.zeros(nc, dtype=np.float64)
+    code = lib.pcg_solve(A._h, None if M is None else M._h, b.data_ptr(), out.data_ptr(), nc, ld,
+                         float(rtol), int(maxit), _stream(stream), iters.ctypes.data, relres.ctypes.data)
+    if code == SPD_E_NOT_CONVERGED and not raise_on_nonconvergence:
+        return out, iters, relres
+    _check(code)
+    return out, iters, relres
+
+
+# ------------------------------------------------------------------ kernel hooks --
+# Matrices are passed as (batch, cols, rows) contiguous tensors, i.e. a batch
+# of column-major rows x cols matrices.
+def test_gemm(A, B, C_, transA=0, transB=0, alpha=1.0, beta=0.0):
+    batch, n, m = C_.shape
+    k = A.shape[1] if not transA else A.shape[2]
+    _check(lib.spd_test_gemm(A.data_ptr(), B.data_ptr(), C_.data_ptr(), batch, m, n, k, transA, transB,
+                             alpha, beta, _stream()))
+
+
+def test_chol(A, fail):
+    _check(lib.spd_test_chol(A.data_ptr(), A.shape[0], A.shape[1], fail.data_ptr(), _stream()))
+
+
+def test_trsm(L, B, trans=0, upper=0):
+    _check(lib.spd_test_trsm(L.data_ptr(), B.data_ptr(), L.shape[0], L.shape[1], B.shape[1], trans, upper,
+                             _stream()))
+
+
+def test_cpqr(A, Q, piv, rank, diag, maxrank, tol, which):
+    batch, n, m = A.shape
+    _check(lib.spd_test_cpqr(A.data_ptr(), _ptr(Q), piv.data_ptr(), rank.data_ptr(), _ptr(diag),
+                             batch, m, n, maxrank, tol, which, _stream()))

@@ -1,0 +1,186 @@
+// Shared declarations of the spdhss library: descriptor structs for the batched
+// kernels, launch wrappers, error handling and a bump-allocating device arena.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+#include <stdexcept>
+
+#include "../../include/spdhss.h"
+
+namespace spd {
+
+// ---------------------------------------------------------------- errors --
+struct Error : std::runtime_error {
+  spd_status code;
+  Error(spd_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define SPD_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      throw ::spd::Error(SPD_E_DEVICE, std::string(#call) + ": " +             \
+                                           hipGetErrorString(e_));             \
+  } while (0)
+
+#define SPD_REQUIRE(cond, code, msg)                                           \
+  do {                                                                         \
+    if (!(cond)) throw ::spd::Error((code), (msg));                            \
+  } while (0)
+
+// ------------------------------------------------------------ descriptors --
+// C = beta * C + alpha * sum_t op(A_t) op(B_t); all terms of a problem share
+// (m, n); each term has its own inner size k.  Column-major storage.
+struct GemmProblem {
+  double* C;
+  int m, n, ldc;
+  int term_begin, term_end;
+  double alpha, beta;
+};
+struct GemmTerm {
+  const double* A;
+  const double* B;
+  double scale;  // multiplies this term's product
+  int k, lda, ldb, pad;
+};
+
+// dst (m x n) = beta * dst + sum_t alpha_t * src_t  (+ identity if add_eye)
+struct BlockProblem {
+  double* dst;
+  int m, n, ldd;
+  int term_begin, term_end;
+  int add_eye;
+  double beta;
+};
+struct BlockTerm {
+  const double* src;
+  int lds, trans;
+  double alpha;
+};
+
+// Dense kernel block out(i, j) = K(x_a[ia(i)], x_b[ib(j)]) (+ shift if i == j
+// and diag_shift).  Points are gathered from SoA arrays through index lists
+// (idx == nullptr means the contiguous range starting at off); when proxy is
+// set, the a-side (row) points are generated as Fibonacci shells around the
+// given centre (see proxy_point).
+struct KBlockProblem {
+  double* out;
+  const int* ia;
+  const int* ib;
+  int64_t offa, offb;
+  int na, nb, ld, diag_shift;
+  int proxy;          // a side is a proxy set
+  double cx, cy, cz;  // proxy centre
+  double rin, rout;   // proxy radii
+};
+
+// Cholesky / triangular solves on column-major matrices.
+struct CholProblem {
+  double* A;
+  int n, lda;
+};
+struct TrsmProblem {
+  const double* L;  // triangular factor
+  double* B;        // right-hand sides, overwritten
+  int n, nrhs, ldl, ldb;
+};
+
+// Column-pivoted QR of a column-major m x n matrix.
+struct CpqrProblem {
+  double* A;        // input (destroyed for the global-memory variant)
+  double* Q;        // out: first rank columns of Q (ldq), may be null
+  double* V;        // workspace: Householder vectors (m x maxrank, ld m)
+  double* R;        // out (global variant): R rows in pivot order, rank x n, ld maxrank
+  int* piv;         // out: pivot column indices (maxrank)
+  int* rank;        // out
+  double* diag;     // out: |R_tt|
+  int m, n, lda, ldq;
+  int maxrank;
+  double tol;
+};
+
+// ----------------------------------------------------------- launchers --
+// All launchers enqueue on `s` and copy their descriptor arrays from device
+// memory (`d_*` pointers) that the caller keeps alive until completion.
+void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t,
+                 int nprob, int max_m, int max_n, int transA, int transB);
+void launch_block(hipStream_t s, const BlockProblem* d_p, const BlockTerm* d_t,
+                  int nprob, int max_m, int max_n);
+void launch_kblock(hipStream_t s, const KBlockProblem* d_p, int nprob, int max_m,
+                   int max_n, const double* px, int64_t stride, int kind,
+                   double ell, double shift, int shells, int per_shell);
+void launch_chol(hipStream_t s, const CholProblem* d_p, int nprob, int max_n,
+                 int* d_fail);
+void launch_trsm(hipStream_t s, const TrsmProblem* d_p, int nprob, int max_n,
+                 int max_nrhs, int trans, int upper);
+void launch_cpqr_reg(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_m,
+                     int max_n);
+void launch_cpqr_glob(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_m,
+                      int max_n);
+bool cpqr_reg_fits(int m, int n);
+
+// vector kernels
+void launch_gather_rows(hipStream_t s, const double* src, int64_t lds, double* dst,
+                        int64_t ldd, const int64_t* perm, int64_t n, int ncols);
+void launch_scatter_rows(hipStream_t s, const double* src, int64_t lds, double* dst,
+                         int64_t ldd, const int64_t* perm, int64_t n, int ncols);
+void launch_gaussian_fill(hipStream_t s, double* dst, int64_t n, int ncols,
+                          int64_t ldd, const int64_t* perm, uint64_t seed);
+void launch_soa_points(hipStream_t s, const double* pts_rowmajor,
+                       const int64_t* perm, int64_t n, double* soa);
+// column dot products: out[c] = sum_i x[i,c] * y[i,c] (deterministic, two-stage)
+void launch_coldot(hipStream_t s, const double* x, const double* y, int64_t n,
+                   int ncols, int64_t ld, double* partial, double* out);
+void launch_pcg_update_xr(hipStream_t s, double* x, double* r, const double* p,
+                          const double* q, const double* rz, const double* pq,
+                          const int* active, int64_t n, int ncols, int64_t ld,
+                          double* alpha_out);
+void launch_pcg_update_p(hipStream_t s, double* p, const double* z,
+                         const double* rz_new, double* rz, const int* active,
+                         int64_t n, int ncols, int64_t ld);
+void launch_pcg_active(hipStream_t s, const double* rr, const double* bb,
+                       double rtol, int* active, int ncols, int* any_active);
+void launch_axpby(hipStream_t s, double* y, const double* x, double a, double b,
+                  int64_t n, int ncols, int64_t ld);
+void launch_fill(hipStream_t s, double* p, double v, int64_t count);
+void launch_scatter_interp(hipStream_t s, double* W, int ldw, const double* E,
+                           int lde, const int* perm_full, int cand, int k);
+void launch_gather_skel(hipStream_t s, const int* cand, const int* piv, int k, int* out);
+
+// --------------------------------------------------------------- arena --
+// Device memory handed out by bumping through large hipMalloc'd chunks; all of
+// it is released together when the owning handle is destroyed.
+class Arena {
+ public:
+  ~Arena();
+  void* get(size_t bytes);
+  template <class T>
+  T* get_n(size_t n) { return static_cast<T*>(get(n * sizeof(T))); }
+  void release();
+  size_t bytes_used() const { return used_; }
+
+ private:
+  std::vector<void*> chunks_;
+  char* cur_ = nullptr;
+  size_t left_ = 0;
+  size_t used_ = 0;
+};
+
+// Upload a host vector into arena memory (synchronous w.r.t. the host data).
+template <class T>
+T* upload(Arena& a, hipStream_t s, const std::vector<T>& v) {
+  if (v.empty()) return nullptr;
+  T* d = a.get_n<T>(v.size());
+  SPD_HIP(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  SPD_HIP(hipStreamSynchronize(s));
+  return d;
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace spd

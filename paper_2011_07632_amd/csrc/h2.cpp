@@ -1,0 +1,342 @@
+// H^2 representation of shift*I + K(X, X): construction and product.
+//
+// Section 5.1 (eq. uniformbasis_h2): far blocks A_ij = U_i B_ij U_j^T with
+// nested bases U_i = diag(U_children) R_i (eq. nested); dense near blocks at
+// the leaf level; only Type-3 couplings are stored (Section 5.2.2).
+//
+// Bases come from an interpolative decomposition against proxy points (the
+// paper uses H2Pack's proxy-point method without describing it; this is the
+// library's own construction): for each node, candidates are its points (leaf)
+// or its children's skeletons (nonleaf); G = K(proxies, candidates) with
+// proxies on spheres between the nearest far box and the farthest root-box
+// corner; a column-pivoted QR of G with relative truncation picks the skeleton
+// and W = [I; (R11^{-1} R12)^T] (rows in candidate order) is U_i or R_i.
+#include "model.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace spd {
+
+struct H2Model::MatvecPlan {
+  int ncols = 0;
+  Arena arena;
+  Recorder rec;
+  double* xh = nullptr;
+  double* yh = nullptr;
+  double* xt = nullptr;  // tree-order input
+  double* yt = nullptr;  // tree-order output
+};
+
+H2Model::H2Model() = default;
+H2Model::~H2Model() = default;
+
+void h2_build_impl(H2Model& H, const double* points, int64_t n) {
+  hipStream_t s = H.s;
+  const double t0 = now_seconds();
+  std::vector<double> hp((size_t)3 * n);
+  SPD_HIP(hipMemcpyAsync(hp.data(), points, (size_t)3 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+  SPD_HIP(hipStreamSynchronize(s));
+  for (double x : hp) SPD_REQUIRE(std::isfinite(x), SPD_E_INVALID, "non-finite point coordinate");
+  TreeHost& T = H.T;
+  T.build(hp.data(), n, H.opts.leaf_size, H.opts.eta);
+  const int nn = T.nnodes, L = T.L;
+  H.perm_d = upload(H.arena, s, T.perm);
+  H.pts = H.arena.get_n<double>((size_t)3 * n);
+  launch_soa_points(s, points, H.perm_d, n, H.pts);
+  const double t1 = now_seconds();
+
+  H.k.assign(nn, 0);
+  H.cand.assign(nn, 0);
+  H.cand_d.assign(nn, nullptr);
+  H.cand_h.assign(nn, {});
+  H.skel_h.assign(nn, {});
+  H.W.assign(nn, nullptr);
+  {
+    std::vector<int> pos(n);
+    std::iota(pos.begin(), pos.end(), 0);
+    int* leafpos = upload(H.arena, s, pos);
+    for (int v = T.first_at(1); v < T.first_at(1) + T.count_at(1); ++v) {
+      H.cand[v] = (int)T.size(v);
+      H.cand_d[v] = leafpos + T.start[v];
+      H.cand_h[v].resize(T.size(v));
+      std::iota(H.cand_h[v].begin(), H.cand_h[v].end(), (int)T.start[v]);
+    }
+  }
+  const int P = H.opts.proxy_shells * H.opts.proxy_per_shell;
+  Stage& st = H.stage;
+  for (int lev = 1; lev < L; ++lev) {
+    struct Job { int v; double rin, rout; };
+    std::vector<Job> jobs;
+    for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
+      double rin, rout;
+      if (H.cand[v] > 0 && T.proxy_radii(v, rin, rout)) jobs.push_back({v, rin, rout});
+    }
+    size_t i = 0;
+    while (i < jobs.size()) {
+      size_t j = i, bytes = 0;
+      while (j < jobs.size()) {
+        const size_t b = (size_t)P * H.cand[jobs[j].v] * 8 * 2;
+        if (j > i && bytes + b > (size_t(1) << 30)) break;
+        bytes += b;
+        ++j;
+      }
+      const int nj = (int)(j - i);
+      Arena tmp;
+      std::vector<KBlockProblem> kb(nj);
+      std::vector<CpqrProblem> cq(nj);
+      std::vector<double*> Rp(nj);
+      std::vector<int*> pivp(nj);
+      int* d_rank = tmp.get_n<int>(nj);
+      int maxc = 0;
+      for (int q = 0; q < nj; ++q) {
+        const Job& jb = jobs[i + q];
+        const int v = jb.v, c = H.cand[v], mr = std::min(P, c);
+        maxc = std::max(maxc, c);
+        double* G = tmp.get_n<double>((size_t)P * c);
+        Rp[q] = tmp.get_n<double>((size_t)mr * c);
+        pivp[q] = tmp.get_n<int>(c);
+        KBlockProblem& kp = kb[q];
+        kp = KBlockProblem{};
+        kp.out = G;
+        kp.ia = nullptr;
+        kp.ib = T.is_leaf(v) ? nullptr : H.cand_d[v];
+        kp.offa = 0;
+        kp.offb = T.is_leaf(v) ? T.start[v] : 0;
+        kp.na = P;
+        kp.nb = c;
+        kp.ld = P;
+        kp.proxy = 1;
+        kp.cx = T.center[3 * v];
+        kp.cy = T.center[3 * v + 1];
+        kp.cz = T.center[3 * v + 2];
+        kp.rin = jb.rin;
+        kp.rout = jb.rout;
+        CpqrProblem& cp = cq[q];
+        cp = CpqrProblem{};
+        cp.A = G;
+        cp.R = Rp[q];
+        cp.piv = pivp[q];
+        cp.rank = d_rank + q;
+        cp.m = P;
+        cp.n = c;
+        cp.lda = P;
+        cp.maxrank = mr;
+        cp.tol = H.opts.tol;
+      }
+      auto* dkb = (const KBlockProblem*)st.push(s, kb.data(), kb.size() * sizeof(KBlockProblem));
+      launch_kblock(s, dkb, nj, P, maxc, H.pts, n, H.kern.kind, H.kern.ell, H.kern.shift,
+                    H.opts.proxy_shells, H.opts.proxy_per_shell);
+      auto* dcq = (const CpqrProblem*)st.push(s, cq.data(), cq.size() * sizeof(CpqrProblem));
+      launch_cpqr_glob(s, dcq, nj, P, maxc);
+      std::vector<int> ranks(nj);
+      SPD_HIP(hipMemcpyAsync(ranks.data(), d_rank, nj * sizeof(int), hipMemcpyDeviceToHost, s));
+      SPD_HIP(hipStreamSynchronize(s));
+      st.reset();
+      TrsmBatch tb;
+      for (int q = 0; q < nj; ++q) {
+        const int v = jobs[i + q].v, c = H.cand[v], mr = std::min(P, c), k = ranks[q];
+        if (k > 0 && c > k) tb.add(Rp[q], mr, Rp[q] + (size_t)k * mr, mr, k, c - k);
+      }
+      tb.run(s, st, 1, 1);
+      std::vector<std::vector<int>> pivh(nj);
+      for (int q = 0; q < nj; ++q) {
+        const int v = jobs[i + q].v, c = H.cand[v], mr = std::min(P, c), k = ranks[q];
+        H.k[v] = k;
+        if (k > 0) {
+          H.W[v] = H.arena.get_n<double>((size_t)c * k);
+          launch_scatter_interp(s, H.W[v], c, Rp[q] + (size_t)k * mr, mr, pivp[q], c, k);
+        }
+        pivh[q].resize(k);
+        if (k > 0)
+          SPD_HIP(hipMemcpyAsync(pivh[q].data(), pivp[q], k * sizeof(int), hipMemcpyDeviceToHost, s));
+      }
+      SPD_HIP(hipStreamSynchronize(s));
+      st.reset();
+      for (int q = 0; q < nj; ++q) {
+        const int v = jobs[i + q].v;
+        std::vector<int> sk(pivh[q].size());
+        for (size_t t = 0; t < sk.size(); ++t) sk[t] = H.cand_h[v][pivh[q][t]];
+        H.skel_h[v] = std::move(sk);
+      }
+      i = j;
+    }
+    // nodes without a far field keep no skeleton
+    for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v)
+      if (H.k[v] == 0) H.skel_h[v].clear();
+    // parents' candidates: children's skeletons in child order
+    for (int p = T.first_at(lev + 1); p < T.first_at(lev + 1) + T.count_at(lev + 1); ++p) {
+      const int c1 = 2 * p + 1, c2 = 2 * p + 2;
+      std::vector<int> cc(H.skel_h[c1]);
+      cc.insert(cc.end(), H.skel_h[c2].begin(), H.skel_h[c2].end());
+      H.cand[p] = (int)cc.size();
+      H.cand_d[p] = cc.empty() ? H.arena.get_n<int>(1) : upload(H.arena, s, cc);
+      H.cand_h[p] = std::move(cc);
+    }
+  }
+  const double t2 = now_seconds();
+
+  // coupling blocks B_ij = K(skel_i, skel_j) and dense near blocks
+  H.Bh.assign(T.coup_idx.size(), nullptr);
+  H.nearA.assign(T.near_idx.size(), nullptr);
+  {
+    std::vector<KBlockProblem> kb;
+    int mm = 0, mn = 0;
+    for (int v = 1; v < nn; ++v)
+      for (int64_t e = T.coup_ptr[v]; e < T.coup_ptr[v + 1]; ++e) {
+        const int j = T.coup_idx[e];
+        if (H.k[v] == 0 || H.k[j] == 0) continue;
+        H.Bh[e] = H.arena.get_n<double>((size_t)H.k[v] * H.k[j]);
+        KBlockProblem kp{};
+        kp.out = H.Bh[e];
+        kp.ia = H.skel_d(v);
+        kp.ib = H.skel_d(j);
+        kp.na = H.k[v];
+        kp.nb = H.k[j];
+        kp.ld = H.k[v];
+        kb.push_back(kp);
+        mm = std::max(mm, kp.na);
+        mn = std::max(mn, kp.nb);
+      }
+    for (int v = T.first_at(1); v < T.first_at(1) + T.count_at(1); ++v)
+      for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) {
+        const int j = T.near_idx[e];
+        const int ni = (int)T.size(v), nj = (int)T.size(j);
+        H.nearA[e] = H.arena.get_n<double>((size_t)std::max(ni * nj, 1));
+        KBlockProblem kp{};
+        kp.out = H.nearA[e];
+        kp.offa = T.start[v];
+        kp.offb = T.start[j];
+        kp.na = ni;
+        kp.nb = nj;
+        kp.ld = std::max(ni, 1);
+        kp.diag_shift = (v == j);
+        kb.push_back(kp);
+        mm = std::max(mm, ni);
+        mn = std::max(mn, nj);
+      }
+    // launch in bounded chunks of descriptors
+    const size_t chunk = 1 << 16;
+    for (size_t a = 0; a < kb.size(); a += chunk) {
+      const size_t b = std::min(kb.size(), a + chunk);
+      auto* d = (const KBlockProblem*)st.push(s, kb.data() + a, (b - a) * sizeof(KBlockProblem));
+      launch_kblock(s, d, (int)(b - a), mm, mn, H.pts, n, H.kern.kind, H.kern.ell, H.kern.shift,
+                    H.opts.proxy_shells, H.opts.proxy_per_shell);
+    }
+    SPD_HIP(hipStreamSynchronize(s));
+    st.reset();
+  }
+  H.par_off.assign(nn, 0);
+  H.stack_rows = 0;
+  for (int p = 0; p < nn; ++p)
+    if (!T.is_leaf(p)) {
+      H.par_off[p] = H.stack_rows;
+      H.stack_rows += H.cand[p];
+    }
+  const double t3 = now_seconds();
+  H.times[0] = t1 - t0;
+  H.times[1] = t2 - t1;
+  H.times[2] = t3 - t2;
+  H.times[3] = t3 - t0;
+}
+
+// ------------------------------------------------------------- product --
+static void build_plan(H2Model& H, int m) {
+  auto pl = std::make_unique<H2Model::MatvecPlan>();
+  pl->ncols = m;
+  const TreeHost& T = H.T;
+  const int L = T.L;
+  const int64_t N = T.N;
+  hipStream_t s = H.s;
+  Arena& a = pl->arena;
+  pl->xt = a.get_n<double>((size_t)N * m);
+  pl->yt = a.get_n<double>((size_t)N * m);
+  pl->xh = a.get_n<double>((size_t)std::max<int64_t>(H.stack_rows, 1) * m);
+  pl->yh = a.get_n<double>((size_t)std::max<int64_t>(H.stack_rows, 1) * m);
+  Recorder& rec = pl->rec;
+  const int lf = T.first_at(1), lc = T.count_at(1);
+  if (L > 1) {
+    // upward: x-hat_v = W_v^T x_v (leaf) or W_v^T [x-hat_c1; x-hat_c2]
+    for (int lev = 1; lev < L; ++lev) {
+      GemmBatch g(1, 0);
+      for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
+        if (H.k[v] == 0) continue;
+        g.add(H.hat(pl->xh, v, m), H.k[v], m, H.hat_ld(v));
+        if (lev == 1)
+          g.term(H.W[v], H.cand[v], pl->xt + T.start[v], (int)N, H.cand[v]);
+        else
+          g.term(H.W[v], H.cand[v], pl->xh + H.par_off[v] * m, H.cand[v], H.cand[v]);
+      }
+      rec.gemm(a, s, g);
+    }
+    // coupling: y-hat_v = sum_j B_vj x-hat_j
+    {
+      GemmBatch g(0, 0);
+      for (int v = 1; v < T.nnodes; ++v) {
+        if (H.k[v] == 0) continue;
+        g.add(H.hat(pl->yh, v, m), H.k[v], m, H.hat_ld(v));
+        for (int64_t e = T.coup_ptr[v]; e < T.coup_ptr[v + 1]; ++e) {
+          const int j = T.coup_idx[e];
+          if (H.k[j] == 0) continue;
+          g.term(H.Bh[e], H.k[v], H.hat(pl->xh, j, m), H.hat_ld(j), H.k[j]);
+        }
+      }
+      rec.gemm(a, s, g);
+    }
+    // downward: [y-hat_c1; y-hat_c2] += W_v y-hat_v
+    for (int lev = L - 1; lev >= 2; --lev) {
+      GemmBatch g(0, 0);
+      for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
+        if (H.k[v] == 0 || H.cand[v] == 0) continue;
+        g.add(pl->yh + H.par_off[v] * m, H.cand[v], m, H.cand[v], 1.0);
+        g.term(H.W[v], H.cand[v], H.hat(pl->yh, v, m), H.hat_ld(v), H.k[v]);
+      }
+      rec.gemm(a, s, g);
+    }
+  }
+  // leaves: y_v = W_v y-hat_v + sum_{j near v} A_vj x_j
+  {
+    GemmBatch g(0, 0);
+    for (int v = lf; v < lf + lc; ++v) {
+      g.add(pl->yt + T.start[v], (int)T.size(v), m, (int)N);
+      if (L > 1 && H.k[v] > 0) g.term(H.W[v], H.cand[v], H.hat(pl->yh, v, m), H.hat_ld(v), H.k[v]);
+      for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) {
+        const int j = T.near_idx[e];
+        g.term(H.nearA[e], (int)T.size(v), pl->xt + T.start[j], (int)N, (int)T.size(j));
+      }
+    }
+    rec.gemm(a, s, g);
+  }
+  SPD_HIP(hipStreamSynchronize(s));
+  H.plan = std::move(pl);
+}
+
+void h2_matvec_tree(H2Model& H, const double* x, double* y, int m) {
+  if (!H.plan || H.plan->ncols != m) {
+    H.plan.reset();
+    build_plan(H, m);
+  }
+  const int64_t N = H.T.N;
+  auto& pl = *H.plan;
+  if (x != pl.xt)
+    SPD_HIP(hipMemcpyAsync(pl.xt, x, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, H.s));
+  pl.rec.replay(H.s);
+  if (y != pl.yt)
+    SPD_HIP(hipMemcpyAsync(y, pl.yt, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, H.s));
+}
+
+double* h2_plan_x(H2Model& H, int m) {
+  if (!H.plan || H.plan->ncols != m) {
+    H.plan.reset();
+    build_plan(H, m);
+  }
+  return H.plan->xt;
+}
+double* h2_plan_y(H2Model& H, int m) {
+  h2_plan_x(H, m);
+  return H.plan->yt;
+}
+void h2_plan_run(H2Model& H) { H.plan->rec.replay(H.s); }
+
+}  // namespace spd

@@ -1,0 +1,1048 @@
+// Device kernels of the spdhss library (gfx950, FP64).
+//
+// Every kernel takes an array of per-problem descriptors so that one launch
+// covers all nodes (or node pairs) of a tree level: the level-parallel axis of
+// the construction (all blocks of one level can be scaled and compressed
+// independently, Section 1).
+#include "common.h"
+
+#include <cmath>
+
+namespace spd {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ reductions --
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off, 64);
+  }
+}
+
+// argmax with ties to the lowest index; every lane gets the result
+__device__ __forceinline__ void wave_argmax(double& v, int& idx) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    double ov = __shfl_xor(v, off, 64);
+    int oi = __shfl_xor(idx, off, 64);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+}
+
+// ------------------------------------------------------------------- GEMM --
+// Grouped GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64).  One workgroup computes a
+// BM x BN tile of one problem, summing over all of the problem's terms in
+// order (deterministic).  Four waves tile the block as (BM/WM) x (BN/WN).
+// Operand layout of the 16x16x4 f64 MFMA: lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; result element v of lane l is D[l/16 + 4*v][l%16].
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm(const GemmProblem* __restrict__ probs,
+                                              const GemmTerm* __restrict__ terms,
+                                              int tiles_max, int transA, int transB) {
+  constexpr int BK = 16;
+  constexpr int NWM = BM / WM;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  static_assert((BM / WM) * (BN / WN) == 4, "four waves");
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+  const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
+  const GemmProblem P = probs[p];
+  const int tm = (P.m + BM - 1) / BM, tn = (P.n + BN - 1) / BN;
+  if (tile >= tm * tn) return;
+  const int i0 = (tile % tm) * BM, j0 = (tile / tm) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % NWM, wn = wave / NWM;
+  d4 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+  for (int t = P.term_begin; t < P.term_end; ++t) {
+    const GemmTerm T = terms[t];
+    for (int k0 = 0; k0 < T.k; k0 += BK) {
+#pragma unroll
+      for (int e = tid; e < BM * BK; e += 256) {
+        int i, kk;
+        if (!transA) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
+        const int gi = i0 + i, gk = k0 + kk;
+        double v = 0.0;
+        if (gi < P.m && gk < T.k)
+          v = T.scale * (transA ? T.A[gk + (int64_t)gi * T.lda] : T.A[gi + (int64_t)gk * T.lda]);
+        As[kk][i] = v;
+      }
+#pragma unroll
+      for (int e = tid; e < BK * BN; e += 256) {
+        int j, kk;
+        if (!transB) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
+        const int gj = j0 + j, gk = k0 + kk;
+        double v = 0.0;
+        if (gj < P.n && gk < T.k)
+          v = transB ? T.B[gj + (int64_t)gk * T.ldb] : T.B[gk + (int64_t)gj * T.ldb];
+        Bs[kk][j] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 4) {
+        double af[FM], bf[FN];
+#pragma unroll
+        for (int a = 0; a < FM; ++a) af[a] = As[ks + (lane >> 4)][wm * WM + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < FN; ++b) bf[b] = Bs[ks + (lane >> 4)][wn * WN + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wm * WM + a * 16 + (lane >> 4) + 4 * v;
+        const int j = j0 + wn * WN + b * 16 + (lane & 15);
+        if (i < P.m && j < P.n) {
+          double* c = P.C + i + (int64_t)j * P.ldc;
+          double val = P.alpha * acc[a][b][v];
+          if (P.beta != 0.0) val += P.beta * (*c);
+          *c = val;
+        }
+      }
+}
+
+void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
+                 int max_m, int max_n, int transA, int transB) {
+  if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
+  if (max_n <= 16) {
+    const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 16);
+    hipLaunchKernelGGL((k_gemm<64, 16, 16, 16>), dim3((unsigned)nprob * tiles), dim3(256), 0, s,
+                       d_p, d_t, tiles, transA, transB);
+  } else if (max_n <= 32) {
+    const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 32);
+    hipLaunchKernelGGL((k_gemm<64, 32, 32, 16>), dim3((unsigned)nprob * tiles), dim3(256), 0, s,
+                       d_p, d_t, tiles, transA, transB);
+  } else {
+    const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 64);
+    hipLaunchKernelGGL((k_gemm<64, 64, 32, 32>), dim3((unsigned)nprob * tiles), dim3(256), 0, s,
+                       d_p, d_t, tiles, transA, transB);
+  }
+  SPD_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------- block updates --
+__global__ __launch_bounds__(256) void k_block(const BlockProblem* __restrict__ probs,
+                                               const BlockTerm* __restrict__ terms,
+                                               int tiles_max) {
+  const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
+  const BlockProblem P = probs[p];
+  const int tm = (P.m + 63) / 64, tn = (P.n + 63) / 64;
+  if (tile >= tm * tn) return;
+  const int i0 = (tile % tm) * 64, j0 = (tile / tm) * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int i = i0 + (e & 63), j = j0 + (e >> 6);
+    if (i >= P.m || j >= P.n) continue;
+    double* d = P.dst + i + (int64_t)j * P.ldd;
+    double v = (P.beta != 0.0) ? P.beta * (*d) : 0.0;
+    for (int t = P.term_begin; t < P.term_end; ++t) {
+      const BlockTerm T = terms[t];
+      v += T.alpha * (T.trans ? T.src[j + (int64_t)i * T.lds] : T.src[i + (int64_t)j * T.lds]);
+    }
+    if (P.add_eye && i == j) v += 1.0;
+    *d = v;
+  }
+}
+
+void launch_block(hipStream_t s, const BlockProblem* d_p, const BlockTerm* d_t, int nprob,
+                  int max_m, int max_n) {
+  if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
+  const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 64);
+  hipLaunchKernelGGL(k_block, dim3((unsigned)nprob * tiles), dim3(256), 0, s, d_p, d_t, tiles);
+  SPD_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------- kernel entries --
+__device__ __forceinline__ double kfun(int kind, double ell, double r2) {
+  if (kind == SPD_K_GAUSSIAN) return exp(-r2 / (ell * ell));
+  if (kind == SPD_K_MATERN32) {
+    const double t = 1.7320508075688772 * sqrt(r2) / ell;
+    return (1.0 + t) * exp(-t);
+  }
+  if (kind == SPD_K_EXPONENTIAL) return exp(-sqrt(r2) / ell);
+  return 1.0 / sqrt(r2 + ell * ell);
+}
+
+// Proxy point t of a node: sphere q = t / per_shell at radius
+// rin (rout/rin)^(q/(shells-1)), Fibonacci lattice point u = t % per_shell.
+__device__ __forceinline__ void proxy_point(const KBlockProblem& P, int t, int shells,
+                                            int per_shell, double& x, double& y, double& z) {
+  const int q = t / per_shell, u = t % per_shell;
+  const double zz = 1.0 - (2.0 * u + 1.0) / per_shell;
+  const double rho = sqrt(fmax(0.0, 1.0 - zz * zz));
+  const double phi = u * (3.141592653589793 * (3.0 - 2.23606797749979));
+  const double rad =
+      shells == 1 ? P.rin : P.rin * pow(P.rout / P.rin, (double)q / (double)(shells - 1));
+  x = P.cx + rad * (rho * cos(phi));
+  y = P.cy + rad * (rho * sin(phi));
+  z = P.cz + rad * zz;
+}
+
+__global__ __launch_bounds__(256) void k_kblock(const KBlockProblem* __restrict__ probs,
+                                                int tiles_max, const double* __restrict__ px,
+                                                int64_t stride, int kind, double ell,
+                                                double shift, int shells, int per_shell) {
+  __shared__ double ax[64], ay[64], az[64], bx[64], by[64], bz[64];
+  const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
+  const KBlockProblem P = probs[p];
+  const int tm = (P.na + 63) / 64, tn = (P.nb + 63) / 64;
+  if (tile >= tm * tn) return;
+  const int i0 = (tile % tm) * 64, j0 = (tile / tm) * 64;
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    const int i = i0 + tid;
+    if (i < P.na) {
+      double x, y, z;
+      if (P.proxy) {
+        proxy_point(P, i, shells, per_shell, x, y, z);
+      } else {
+        const int64_t g = P.ia ? (int64_t)P.ia[i] : P.offa + i;
+        x = px[g];
+        y = px[g + stride];
+        z = px[g + 2 * stride];
+      }
+      ax[tid] = x;
+      ay[tid] = y;
+      az[tid] = z;
+    }
+  } else if (tid < 128) {
+    const int j = j0 + tid - 64;
+    if (j < P.nb) {
+      const int64_t g = P.ib ? (int64_t)P.ib[j] : P.offb + j;
+      bx[tid - 64] = px[g];
+      by[tid - 64] = px[g + stride];
+      bz[tid - 64] = px[g + 2 * stride];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int il = e & 63, jl = e >> 6;
+    const int i = i0 + il, j = j0 + jl;
+    if (i >= P.na || j >= P.nb) continue;
+    const double dx = ax[il] - bx[jl], dy = ay[il] - by[jl], dz = az[il] - bz[jl];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    double v = kfun(kind, ell, r2);
+    if (P.diag_shift && i == j) v += shift;
+    P.out[i + (int64_t)j * P.ld] = v;
+  }
+}
+
+void launch_kblock(hipStream_t s, const KBlockProblem* d_p, int nprob, int max_m, int max_n,
+                   const double* px, int64_t stride, int kind, double ell, double shift,
+                   int shells, int per_shell) {
+  if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
+  const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 64);
+  hipLaunchKernelGGL(k_kblock, dim3((unsigned)nprob * tiles), dim3(256), 0, s, d_p, tiles, px,
+                     stride, kind, ell, shift, shells, per_shell);
+  SPD_HIP(hipGetLastError());
+}
+
+// --------------------------------------------------------------- Cholesky --
+// In-place lower Cholesky, one workgroup per matrix, left-looking by panels of
+// 32 columns.  The strictly upper triangle is set to zero on exit.
+__global__ __launch_bounds__(256) void k_chol(const CholProblem* __restrict__ probs, int* fail) {
+  __shared__ double W[32][33];
+  __shared__ double D[32][33];
+  __shared__ int bad;
+  const CholProblem P = probs[blockIdx.x];
+  const int n = P.n, lda = P.lda, tid = threadIdx.x;
+  double* A = P.A;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j0 = 0; j0 < n; j0 += 32) {
+    const int jb = min(32, n - j0);
+    const int nrows = n - j0;
+    // panel update A[j0:n, j0:j0+jb] -= A[j0:n, 0:j0] A[j0:j0+jb, 0:j0]^T
+    for (int rbase = 0; rbase < nrows; rbase += 256) {
+      const int r = rbase + tid;
+      const bool act = r < nrows;
+      double acc[32];
+#pragma unroll
+      for (int c = 0; c < 32; ++c)
+        acc[c] = (act && c < jb) ? A[(j0 + r) + (int64_t)(j0 + c) * lda] : 0.0;
+      for (int k0 = 0; k0 < j0; k0 += 32) {
+        __syncthreads();
+        for (int e = tid; e < 32 * 32; e += 256) {
+          const int c = e & 31, kk = e >> 5;
+          W[c][kk] = (c < jb) ? A[(j0 + c) + (int64_t)(k0 + kk) * lda] : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < 32; ++kk) {
+          const double a = act ? A[(j0 + r) + (int64_t)(k0 + kk) * lda] : 0.0;
+#pragma unroll
+          for (int c = 0; c < 32; ++c) acc[c] -= a * W[c][kk];
+        }
+      }
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+          if (c < jb) A[(j0 + r) + (int64_t)(j0 + c) * lda] = acc[c];
+      }
+    }
+    __syncthreads();
+    // factor the diagonal block in LDS
+    for (int e = tid; e < 32 * 32; e += 256) {
+      const int r = e & 31, c = e >> 5;
+      D[r][c] = (r < jb && c < jb && c <= r) ? A[(j0 + r) + (int64_t)(j0 + c) * lda] : 0.0;
+    }
+    __syncthreads();
+    for (int c = 0; c < jb; ++c) {
+      if (tid == 0) {
+        const double d = D[c][c];
+        if (!(d > 0.0)) bad = 1;
+        D[c][c] = sqrt(fmax(d, 0.0));
+      }
+      __syncthreads();
+      const double dc = D[c][c];
+      if (tid > c && tid < jb) D[tid][c] = (dc > 0.0) ? D[tid][c] / dc : 0.0;
+      __syncthreads();
+      for (int e = tid; e < 32 * 32; e += 256) {
+        const int r = e & 31, q = e >> 5;
+        if (q > c && r >= q && r < jb) D[r][q] -= D[r][c] * D[q][c];
+      }
+      __syncthreads();
+    }
+    if (bad) break;
+    for (int e = tid; e < 32 * 32; e += 256) {
+      const int r = e & 31, c = e >> 5;
+      if (r < jb && c < jb && c <= r) A[(j0 + r) + (int64_t)(j0 + c) * lda] = D[r][c];
+    }
+    // rows below the diagonal block: X D^T = P
+    for (int rbase = jb; rbase < nrows; rbase += 256) {
+      const int r = rbase + tid;
+      if (r < nrows) {
+        double x[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) x[c] = (c < jb) ? A[(j0 + r) + (int64_t)(j0 + c) * lda] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) {
+          if (c < jb) {
+            double sacc = x[c];
+#pragma unroll
+            for (int q = 0; q < c; ++q) sacc -= x[q] * D[c][q];
+            x[c] = sacc / D[c][c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+          if (c < jb) A[(j0 + r) + (int64_t)(j0 + c) * lda] = x[c];
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) fail[blockIdx.x] = 1;
+    return;
+  }
+  for (int64_t e = tid; e < (int64_t)n * n; e += 256) {
+    const int r = (int)(e % n), c = (int)(e / n);
+    if (r < c) A[r + (int64_t)c * lda] = 0.0;
+  }
+}
+
+void launch_chol(hipStream_t s, const CholProblem* d_p, int nprob, int max_n, int* d_fail) {
+  if (nprob <= 0 || max_n <= 0) return;
+  hipLaunchKernelGGL(k_chol, dim3(nprob), dim3(256), 0, s, d_p, d_fail);
+  SPD_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- TRSM --
+// B <- op(L)^{-1} B for lower-triangular L (trans: L^T).  With upper = 1 the
+// factor is read as L(i, j) = M[j + i*ld], i.e. the transpose of an upper
+// triangular M, so (trans=1, upper=1) computes M^{-1} B.  One workgroup per
+// (problem, block of CB right-hand sides); the block stays in LDS.
+template <int CB>
+__global__ __launch_bounds__(256) void k_trsm(const TrsmProblem* __restrict__ probs, int nprob,
+                                              int ncb, int trans, int upper) {
+  extern __shared__ double X[];  // n x CB, row-major
+  __shared__ double Dg[32][33];
+  // XCD-aware decode: all column blocks of one problem share blockIdx % 8.
+  const int b = blockIdx.x;
+  const int x8 = b & 7, rest = b >> 3;
+  const int cb = rest % ncb, p = (rest / ncb) * 8 + x8;
+  if (p >= nprob) return;
+  const TrsmProblem P = probs[p];
+  const int n = P.n, ldl = P.ldl, tid = threadIdx.x;
+  const int c0 = cb * CB;
+  const int ncol = min(CB, P.nrhs - c0);
+  if (ncol <= 0 || n <= 0) return;
+  auto Lg = [&](int i, int j) -> double {
+    return upper ? P.L[j + (int64_t)i * ldl] : P.L[i + (int64_t)j * ldl];
+  };
+  for (int e = tid; e < n * CB; e += 256) {
+    const int r = e % n, c = e / n;
+    X[r * CB + c] = (c < ncol) ? P.B[r + (int64_t)(c0 + c) * P.ldb] : 0.0;
+  }
+  __syncthreads();
+  constexpr int CPT = CB / 8;  // columns per thread in the update
+  const int nblk = (n + 31) / 32;
+  for (int bi = 0; bi < nblk; ++bi) {
+    const int blk = trans ? (nblk - 1 - bi) : bi;
+    const int r0 = blk * 32, rb = min(32, n - r0);
+    const int r = tid & 31, cg = tid >> 5;
+    double acc[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) acc[q] = 0.0;
+    if (r < rb) {
+      if (!trans) {
+        for (int k = 0; k < r0; ++k) {
+          const double l = Lg(r0 + r, k);
+#pragma unroll
+          for (int q = 0; q < CPT; ++q) acc[q] += l * X[k * CB + cg * CPT + q];
+        }
+      } else {
+        for (int k = r0 + rb; k < n; ++k) {
+          const double l = Lg(k, r0 + r);
+#pragma unroll
+          for (int q = 0; q < CPT; ++q) acc[q] += l * X[k * CB + cg * CPT + q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) X[(r0 + r) * CB + cg * CPT + q] -= acc[q];
+    }
+    for (int e = tid; e < 32 * 32; e += 256) {
+      const int rr = e & 31, qq = e >> 5;
+      Dg[rr][qq] = (rr < rb && qq < rb && qq <= rr) ? Lg(r0 + rr, r0 + qq) : 0.0;
+    }
+    __syncthreads();
+    if (tid < CB) {
+      double x[32];
+#pragma unroll
+      for (int rr = 0; rr < 32; ++rr) x[rr] = (rr < rb) ? X[(r0 + rr) * CB + tid] : 0.0;
+      if (!trans) {
+#pragma unroll
+        for (int rr = 0; rr < 32; ++rr) {
+          if (rr < rb) {
+            double sacc = x[rr];
+#pragma unroll
+            for (int qq = 0; qq < rr; ++qq) sacc -= Dg[rr][qq] * x[qq];
+            x[rr] = sacc / Dg[rr][rr];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int rr = 31; rr >= 0; --rr) {
+          if (rr < rb) {
+            double sacc = x[rr];
+#pragma unroll
+            for (int qq = rr + 1; qq < 32; ++qq)
+              if (qq < rb) sacc -= Dg[qq][rr] * x[qq];
+            x[rr] = sacc / Dg[rr][rr];
+          }
+        }
+      }
+#pragma unroll
+      for (int rr = 0; rr < 32; ++rr)
+        if (rr < rb) X[(r0 + rr) * CB + tid] = x[rr];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * ncol; e += 256) {
+    const int r = e % n, c = e / n;
+    P.B[r + (int64_t)(c0 + c) * P.ldb] = X[r * CB + c];
+  }
+}
+
+void launch_trsm(hipStream_t s, const TrsmProblem* d_p, int nprob, int max_n, int max_nrhs,
+                 int trans, int upper) {
+  if (nprob <= 0 || max_n <= 0 || max_nrhs <= 0) return;
+  const int np8 = (nprob + 7) / 8 * 8;
+  if (max_n <= 256) {
+    constexpr int CB = 32;
+    const int ncb = ceil_div(max_nrhs, CB);
+    hipLaunchKernelGGL((k_trsm<CB>), dim3((unsigned)np8 * ncb), dim3(256),
+                       (size_t)max_n * CB * sizeof(double), s, d_p, nprob, ncb, trans, upper);
+  } else {
+    SPD_REQUIRE(max_n <= 1024, SPD_E_INVALID, "triangular solve: order above 1024");
+    constexpr int CB = 8;
+    const int ncb = ceil_div(max_nrhs, CB);
+    hipLaunchKernelGGL((k_trsm<CB>), dim3((unsigned)np8 * ncb), dim3(256),
+                       (size_t)max_n * CB * sizeof(double), s, d_p, nprob, ncb, trans, upper);
+  }
+  SPD_HIP(hipGetLastError());
+}
+
+// --------------------------------------------------------------- CPQR --
+// Register-resident Householder QR with column pivoting (Algorithm 5.1,
+// step 3).  Wave w owns columns w + NW*c, lane l owns rows l + 64*q.  At step t
+// the pivot is the unused column with the largest exactly recomputed trailing
+// norm (rows >= t), ties to the lowest column index; the factorization stops
+// when t reaches maxrank or min(m, n), or when that norm is not larger than
+// tol times the first pivot norm.  Q's first rank columns are then formed by
+// applying the reflectors to the identity, with signs making R_tt >= 0.
+template <int NW, int RPL, int CPW>
+__global__ __launch_bounds__(NW * 64) void k_cpqr_reg(const CpqrProblem* __restrict__ probs) {
+  constexpr int NC = NW * CPW;
+  __shared__ double nrm2[NC];
+  __shared__ double vbuf[64 * RPL];
+  __shared__ double betas[NC];
+  __shared__ double alphas[NC];
+  __shared__ double sh_beta;
+  const CpqrProblem P = probs[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = P.m, n = P.n;
+  double a[CPW][RPL];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int col = w + NW * c;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int row = lane + 64 * q;
+      a[c][q] = (col < n && row < m) ? P.A[row + (int64_t)col * P.lda] : 0.0;
+    }
+  }
+  {
+    double s2[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      s2[c] = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) s2[c] += a[c][q] * a[c][q];
+    }
+    wave_sum_n<CPW>(s2);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int col = w + NW * c;
+        nrm2[col] = (col < n) ? s2[c] : -1.0;
+      }
+    }
+  }
+  __syncthreads();
+  const int kmax = min(min(m, n), P.maxrank);
+  uint32_t used = 0;
+  double ref = 0.0;
+  int rank = 0;
+  for (int t = 0; t < kmax; ++t) {
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    for (int j = lane; j < NC; j += 64) {
+      const double v = nrm2[j];
+      if (v > best) { best = v; bi = j; }
+    }
+    wave_argmax(best, bi);
+    const double nrm = sqrt(fmax(best, 0.0));
+    if (t == 0) ref = nrm;
+    if (!(nrm > P.tol * ref) || nrm == 0.0) break;
+    __syncthreads();  // everyone has read nrm2 of this step
+    const int owner = bi % NW, slot = bi / NW;
+    if (w == owner) {
+      double col[RPL];
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) col[q] = 0.0;
+#pragma unroll
+      for (int c = 0; c < CPW; ++c)
+        if (c == slot)
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) col[q] = a[c][q];
+      double xt = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q)
+        if (q == t / 64) xt = col[q];
+      xt = __shfl(xt, t % 64, 64);
+      const double alpha = (xt >= 0.0) ? -nrm : nrm;
+      const double beta = 1.0 / (nrm * (nrm + fabs(xt)));
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int row = lane + 64 * q;
+        double v = (row >= t) ? col[q] : 0.0;
+        if (row == t) v = xt - alpha;
+        vbuf[row] = v;
+        if (row < m && P.V) P.V[row + (int64_t)t * m] = v;
+      }
+#pragma unroll
+      for (int c = 0; c < CPW; ++c)
+        if (c == slot)
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) {
+            const int row = lane + 64 * q;
+            if (row == t) a[c][q] = alpha;
+            else if (row > t) a[c][q] = 0.0;
+          }
+      if (lane == 0) {
+        sh_beta = beta;
+        betas[t] = beta;
+        alphas[t] = alpha;
+        P.piv[t] = bi;
+        if (P.diag) P.diag[t] = nrm;
+      }
+      used |= (1u << slot);
+    }
+    __syncthreads();
+    const double beta = sh_beta;
+    double v[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) v[q] = vbuf[lane + 64 * q];
+    double d[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      d[c] = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) d[c] += v[q] * a[c][q];
+    }
+    wave_sum_n<CPW>(d);
+    double s2[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const bool live = !((used >> c) & 1u);
+      s2[c] = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        if (live) a[c][q] -= beta * d[c] * v[q];
+        const int row = lane + 64 * q;
+        if (row > t) s2[c] += a[c][q] * a[c][q];
+      }
+    }
+    wave_sum_n<CPW>(s2);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int col = w + NW * c;
+        if (col < NC) nrm2[col] = (col < n && !((used >> c) & 1u)) ? s2[c] : -1.0;
+      }
+    }
+    rank = t + 1;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *P.rank = rank;
+  if (!P.Q) return;
+  // form Q = H_0 ... H_{rank-1} [I; 0]
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int col = w + NW * c;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) a[c][q] = (col < rank && lane + 64 * q == col) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int t = rank - 1; t >= 0; --t) {
+    double v[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int row = lane + 64 * q;
+      v[q] = (row < m && row >= t) ? P.V[row + (int64_t)t * m] : 0.0;
+    }
+    const double beta = betas[t];
+    double d[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      d[c] = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) d[c] += v[q] * a[c][q];
+    }
+    wave_sum_n<CPW>(d);
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int col = w + NW * c;
+      if (col >= t && col < rank)
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) a[c][q] -= beta * d[c] * v[q];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int col = w + NW * c;
+    if (col < rank) {
+      const double sg = (alphas[col] < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int row = lane + 64 * q;
+        if (row < m) P.Q[row + (int64_t)col * P.ldq] = sg * a[c][q];
+      }
+    }
+  }
+}
+
+bool cpqr_reg_fits(int m, int n) { return m <= 512 && n <= 128; }
+
+void launch_cpqr_reg(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_m, int max_n) {
+  if (nprob <= 0) return;
+  SPD_REQUIRE(cpqr_reg_fits(max_m, max_n), SPD_E_INVALID, "cpqr: shape exceeds register kernel");
+  if (max_m <= 256)
+    hipLaunchKernelGGL((k_cpqr_reg<8, 4, 16>), dim3(nprob), dim3(512), 0, s, d_p);
+  else
+    hipLaunchKernelGGL((k_cpqr_reg<16, 8, 8>), dim3(nprob), dim3(1024), 0, s, d_p);
+  SPD_HIP(hipGetLastError());
+}
+
+// Global-memory variant for tall or wide matrices (the proxy interpolative
+// decomposition).  The matrix is updated in place; each column is streamed
+// through registers once per step (RCH chunks of 64 rows per lane).  On exit
+// P.piv holds the full column order (pivots first, then the unused columns in
+// ascending order) and P.R the first rank rows of R in that order.
+template <int RCH>
+__global__ __launch_bounds__(1024) void k_cpqr_glob(const CpqrProblem* __restrict__ probs,
+                                                    double* nrm_ws) {
+  constexpr int NW = 16;
+  extern __shared__ double sm[];  // vbuf[64*RCH] | nrm2[n]
+  __shared__ double sh_beta;
+  __shared__ int sh_rank;
+  const CpqrProblem P = probs[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = P.m, n = P.n;
+  double* vbuf = sm;
+  double* nrm2 = sm + 64 * RCH;
+  double* A = P.A;
+  const int64_t lda = P.lda;
+  for (int col = w; col < n; col += NW) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < RCH; ++q) {
+      const int row = lane + 64 * q;
+      if (row < m) { const double x = A[row + col * lda]; s2 += x * x; }
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) nrm2[col] = s2;
+  }
+  __syncthreads();
+  const int kmax = min(min(m, n), P.maxrank);
+  double ref = 0.0;
+  int rank = 0;
+  for (int t = 0; t < kmax; ++t) {
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    for (int j = lane; j < n; j += 64) {
+      const double v = nrm2[j];
+      if (v > best) { best = v; bi = j; }
+    }
+    wave_argmax(best, bi);
+    const double nrm = sqrt(fmax(best, 0.0));
+    if (t == 0) ref = nrm;
+    if (!(nrm > P.tol * ref) || nrm == 0.0) break;
+    __syncthreads();
+    if (w == bi % NW) {
+      const double xt = A[t + bi * lda];
+      const double alpha = (xt >= 0.0) ? -nrm : nrm;
+      const double beta = 1.0 / (nrm * (nrm + fabs(xt)));
+#pragma unroll
+      for (int q = 0; q < RCH; ++q) {
+        const int row = lane + 64 * q;
+        double v = 0.0;
+        if (row < m && row >= t) v = (row == t) ? xt - alpha : A[row + bi * lda];
+        vbuf[row] = v;
+        if (row < m && row >= t) A[row + bi * lda] = (row == t) ? alpha : 0.0;
+      }
+      if (lane == 0) {
+        sh_beta = beta;
+        P.piv[t] = bi;
+        if (P.diag) P.diag[t] = nrm;
+        nrm2[bi] = -1.0;
+      }
+    }
+    __syncthreads();
+    const double beta = sh_beta;
+    for (int col = w; col < n; col += NW) {
+      if (nrm2[col] < 0.0) continue;  // used (the pivot's owner wrote -1 before the barrier)
+      double x[RCH];
+      double d = 0.0;
+#pragma unroll
+      for (int q = 0; q < RCH; ++q) {
+        const int row = lane + 64 * q;
+        x[q] = (row < m && row >= t) ? A[row + col * lda] : 0.0;
+        d += vbuf[row] * x[q];
+      }
+      d = wave_sum(d);
+      double s2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < RCH; ++q) {
+        const int row = lane + 64 * q;
+        if (row < m && row >= t) {
+          x[q] -= beta * d * vbuf[row];
+          A[row + col * lda] = x[q];
+          if (row > t) s2 += x[q] * x[q];
+        }
+      }
+      s2 = wave_sum(s2);
+      if (lane == 0) nrm2[col] = s2;
+    }
+    rank = t + 1;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { *P.rank = rank; sh_rank = rank; }
+  __syncthreads();
+  // complete the permutation with the unused columns in ascending order
+  if (threadIdx.x == 0) {
+    int pos = rank;
+    for (int j = 0; j < n; ++j)
+      if (nrm2[j] >= 0.0) P.piv[pos++] = j;
+  }
+  __syncthreads();
+  if (P.R) {
+    const int64_t ldr = P.maxrank;
+    for (int64_t e = threadIdx.x; e < (int64_t)rank * n; e += blockDim.x) {
+      const int i = (int)(e % rank), j = (int)(e / rank);
+      P.R[i + j * ldr] = A[i + (int64_t)P.piv[j] * lda];
+    }
+  }
+  (void)nrm_ws;
+}
+
+void launch_cpqr_glob(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_m, int max_n) {
+  if (nprob <= 0) return;
+  const size_t sh = 0;
+  (void)sh;
+  if (max_m <= 1024) {
+    const size_t bytes = (64 * 16 + (size_t)max_n) * sizeof(double);
+    hipLaunchKernelGGL((k_cpqr_glob<16>), dim3(nprob), dim3(1024), bytes, s, d_p, nullptr);
+  } else {
+    SPD_REQUIRE(max_m <= 2048, SPD_E_INVALID, "cpqr: more than 2048 rows");
+    const size_t bytes = (64 * 32 + (size_t)max_n) * sizeof(double);
+    hipLaunchKernelGGL((k_cpqr_glob<32>), dim3(nprob), dim3(1024), bytes, s, d_p, nullptr);
+  }
+  SPD_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------- vectors --
+__global__ void k_gather_rows(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                              int64_t ldd, const int64_t* __restrict__ perm, int64_t n, int ncols) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < n && c < ncols) dst[i + c * ldd] = src[perm[i] + c * lds];
+}
+void launch_gather_rows(hipStream_t s, const double* src, int64_t lds, double* dst, int64_t ldd,
+                        const int64_t* perm, int64_t n, int ncols) {
+  if (n <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3(ceil_div(n, 256), ncols), dim3(256), 0, s, src, lds, dst,
+                     ldd, perm, n, ncols);
+  SPD_HIP(hipGetLastError());
+}
+
+__global__ void k_scatter_rows(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                               int64_t ldd, const int64_t* __restrict__ perm, int64_t n, int ncols) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < n && c < ncols) dst[perm[i] + c * ldd] = src[i + c * lds];
+}
+void launch_scatter_rows(hipStream_t s, const double* src, int64_t lds, double* dst, int64_t ldd,
+                         const int64_t* perm, int64_t n, int ncols) {
+  if (n <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(k_scatter_rows, dim3(ceil_div(n, 256), ncols), dim3(256), 0, s, src, lds, dst,
+                     ldd, perm, n, ncols);
+  SPD_HIP(hipGetLastError());
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014) on the counter (seed, original row,
+// column), two draws turned into a standard normal by the Box-Muller formula.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+__global__ void k_gaussian_fill(double* __restrict__ dst, int64_t n, int ncols, int64_t ldd,
+                                const int64_t* __restrict__ perm, uint64_t seed) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  const uint64_t ctr = (uint64_t)perm[i] * (uint64_t)ncols + (uint64_t)c;
+  const uint64_t h1 = splitmix64(seed ^ splitmix64(2 * ctr));
+  const uint64_t h2 = splitmix64(seed ^ splitmix64(2 * ctr + 1));
+  const double u1 = ((h1 >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
+  const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
+  dst[i + c * ldd] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+void launch_gaussian_fill(hipStream_t s, double* dst, int64_t n, int ncols, int64_t ldd,
+                          const int64_t* perm, uint64_t seed) {
+  if (n <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(k_gaussian_fill, dim3(ceil_div(n, 256), ncols), dim3(256), 0, s, dst, n, ncols,
+                     ldd, perm, seed);
+  SPD_HIP(hipGetLastError());
+}
+
+__global__ void k_soa_points(const double* __restrict__ pts, const int64_t* __restrict__ perm,
+                             int64_t n, double* __restrict__ soa) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = perm[i];
+  soa[i] = pts[3 * o];
+  soa[n + i] = pts[3 * o + 1];
+  soa[2 * n + i] = pts[3 * o + 2];
+}
+void launch_soa_points(hipStream_t s, const double* pts, const int64_t* perm, int64_t n,
+                       double* soa) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_soa_points, dim3(ceil_div(n, 256)), dim3(256), 0, s, pts, perm, n, soa);
+  SPD_HIP(hipGetLastError());
+}
+
+// Deterministic column dot products: fixed-size chunks reduced per block, the
+// partials then summed in order by one block per column.
+constexpr int DOT_CHUNK = 8192;
+__global__ __launch_bounds__(256) void k_coldot_partial(const double* __restrict__ x,
+                                                        const double* __restrict__ y, int64_t n,
+                                                        int64_t ld, double* __restrict__ partial,
+                                                        int nblk) {
+  __shared__ double red[4];
+  const int b = blockIdx.x, c = blockIdx.y;
+  const int64_t lo = (int64_t)b * DOT_CHUNK, hi = min(n, lo + DOT_CHUNK);
+  double sacc = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) sacc += x[i + c * ld] * y[i + c * ld];
+  sacc = wave_sum(sacc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sacc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[b + (int64_t)c * nblk] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+__global__ __launch_bounds__(64) void k_coldot_final(const double* __restrict__ partial, int nblk,
+                                                     double* __restrict__ out) {
+  const int c = blockIdx.x;
+  double sacc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) sacc += partial[b + (int64_t)c * nblk];
+  sacc = wave_sum(sacc);
+  if (threadIdx.x == 0) out[c] = sacc;
+}
+void launch_coldot(hipStream_t s, const double* x, const double* y, int64_t n, int ncols, int64_t ld,
+                   double* partial, double* out) {
+  if (ncols <= 0) return;
+  const int nblk = ceil_div(n, DOT_CHUNK);
+  hipLaunchKernelGGL(k_coldot_partial, dim3(nblk, ncols), dim3(256), 0, s, x, y, n, ld, partial, nblk);
+  hipLaunchKernelGGL(k_coldot_final, dim3(ncols), dim3(64), 0, s, partial, nblk, out);
+  SPD_HIP(hipGetLastError());
+}
+
+__global__ void k_pcg_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                const double* __restrict__ p, const double* __restrict__ q,
+                                const double* __restrict__ rz, const double* __restrict__ pq,
+                                const int* __restrict__ active, int64_t n, int64_t ld,
+                                double* alpha_out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (!active[c]) return;
+  const double alpha = rz[c] / pq[c];
+  if (i == 0 && alpha_out) alpha_out[c] = alpha;
+  if (i < n) {
+    x[i + c * ld] += alpha * p[i + c * ld];
+    r[i + c * ld] -= alpha * q[i + c * ld];
+  }
+}
+void launch_pcg_update_xr(hipStream_t s, double* x, double* r, const double* p, const double* q,
+                          const double* rz, const double* pq, const int* active, int64_t n,
+                          int ncols, int64_t ld, double* alpha_out) {
+  hipLaunchKernelGGL(k_pcg_update_xr, dim3(ceil_div(n, 256), ncols), dim3(256), 0, s, x, r, p, q,
+                     rz, pq, active, n, ld, alpha_out);
+  SPD_HIP(hipGetLastError());
+}
+
+__global__ void k_pcg_update_p(double* __restrict__ p, const double* __restrict__ z,
+                               const double* __restrict__ rz_new, const double* __restrict__ rz,
+                               const int* __restrict__ active, int64_t n, int64_t ld) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (!active[c] || i >= n) return;
+  const double beta = rz_new[c] / rz[c];
+  p[i + c * ld] = z[i + c * ld] + beta * p[i + c * ld];
+}
+__global__ void k_copy_active(double* __restrict__ dst, const double* __restrict__ src,
+                              const int* __restrict__ active, int ncols) {
+  const int c = threadIdx.x;
+  if (c < ncols && active[c]) dst[c] = src[c];
+}
+void launch_pcg_update_p(hipStream_t s, double* p, const double* z, const double* rz_new, double* rz,
+                         const int* active, int64_t n, int ncols, int64_t ld) {
+  hipLaunchKernelGGL(k_pcg_update_p, dim3(ceil_div(n, 256), ncols), dim3(256), 0, s, p, z, rz_new,
+                     rz, active, n, ld);
+  hipLaunchKernelGGL(k_copy_active, dim3(1), dim3(64 * ceil_div(ncols, 64)), 0, s, rz, rz_new,
+                     active, ncols);
+  SPD_HIP(hipGetLastError());
+}
+
+__global__ void k_pcg_active(const double* __restrict__ rr, const double* __restrict__ bb,
+                             double rtol, int* __restrict__ active, int ncols, int* any_active) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+    if (active[c]) {
+      const bool a = sqrt(rr[c]) > rtol * sqrt(bb[c]);
+      active[c] = a ? 1 : 0;
+      if (a) atomicOr(&any, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *any_active = any;
+}
+void launch_pcg_active(hipStream_t s, const double* rr, const double* bb, double rtol, int* active,
+                       int ncols, int* any_active) {
+  hipLaunchKernelGGL(k_pcg_active, dim3(1), dim3(64), 0, s, rr, bb, rtol, active, ncols, any_active);
+  SPD_HIP(hipGetLastError());
+}
+
+__global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a, double b,
+                        int64_t n, int64_t ld) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < n) y[i + c * ld] = a * x[i + c * ld] + (b != 0.0 ? b * y[i + c * ld] : 0.0);
+}
+void launch_axpby(hipStream_t s, double* y, const double* x, double a, double b, int64_t n,
+                  int ncols, int64_t ld) {
+  if (n <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(k_axpby, dim3(ceil_div(n, 256), ncols), dim3(256), 0, s, y, x, a, b, n, ld);
+  SPD_HIP(hipGetLastError());
+}
+
+__global__ void k_fill(double* __restrict__ p, double v, int64_t count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+void launch_fill(hipStream_t s, double* p, double v, int64_t count) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(ceil_div(count, 256)), dim3(256), 0, s, p, v, count);
+  SPD_HIP(hipGetLastError());
+}
+
+// W (cand x k) of an interpolative decomposition from E = R11^{-1} R12 and
+// the full column order: identity rows at the skeleton, E^T rows elsewhere.
+__global__ void k_scatter_interp(double* __restrict__ W, int ldw, const double* __restrict__ E,
+                                 int lde, const int* __restrict__ perm, int cand, int k) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)cand * k) return;
+  const int j = (int)(e / k), i = (int)(e % k);  // row position j in pivot order, column i
+  const int row = perm[j];
+  double v;
+  if (j < k) v = (i == j) ? 1.0 : 0.0;
+  else v = E[i + (int64_t)(j - k) * lde];
+  W[row + (int64_t)i * ldw] = v;
+}
+void launch_scatter_interp(hipStream_t s, double* W, int ldw, const double* E, int lde,
+                           const int* perm, int cand, int k) {
+  if ((int64_t)cand * k <= 0) return;
+  hipLaunchKernelGGL(k_scatter_interp, dim3(ceil_div((int64_t)cand * k, 256)), dim3(256), 0, s, W, ldw,
+                     E, lde, perm, cand, k);
+  SPD_HIP(hipGetLastError());
+}
+
+__global__ void k_gather_skel(const int* __restrict__ cand, const int* __restrict__ piv, int k,
+                              int* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < k) out[j] = cand[piv[j]];
+}
+void launch_gather_skel(hipStream_t s, const int* cand, const int* piv, int k, int* out) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_gather_skel, dim3(ceil_div(k, 256)), dim3(256), 0, s, cand, piv, k, out);
+  SPD_HIP(hipGetLastError());
+}
+
+}  // namespace spd

@@ -1,0 +1,212 @@
+// Host-side model of the library's handles: the tree, the H^2 matrix, the SPD
+// HSS matrix and its nested factors, plus the descriptor staging used to
+// launch the batched kernels.
+#pragma once
+#include "common.h"
+
+#include <memory>
+
+namespace spd {
+
+// ------------------------------------------------------------------ tree --
+struct TreeHost {
+  int64_t N = 0;
+  int leaf = 0, D = 0, L = 0, nnodes = 0;
+  double eta = 1.0;
+  std::vector<int64_t> perm, start, end;
+  std::vector<double> lo, hi, center, radius;
+  std::vector<int64_t> near_ptr, coup_ptr;
+  std::vector<int> near_idx, coup_idx;
+
+  void build(const double* pts_rowmajor, int64_t n, int leaf_size, double eta);
+  bool admissible(int i, int j) const;
+  void build_lists();
+  int depth(int v) const { int d = 0; while ((1 << (d + 1)) - 1 <= v) ++d; return d; }
+  int level(int v) const { return L - depth(v); }
+  bool is_leaf(int v) const { return depth(v) == D; }
+  int first_at(int k) const { return (1 << (L - k)) - 1; }
+  int count_at(int k) const { return 1 << (L - k); }
+  int64_t size(int v) const { return end[v] - start[v]; }
+  int lca_level(int i, int j) const;
+  int64_t near_pos(int i, int j) const;
+  int64_t coup_pos(int i, int j) const;
+  bool proxy_radii(int v, double& rin, double& rout) const;
+};
+
+// --------------------------------------------------- descriptor staging --
+// Collects descriptor arrays on the host and copies them to device memory.
+// Device copies stay valid until reset(), which the owner calls only after
+// synchronizing the stream.
+class Stage {
+ public:
+  ~Stage();
+  void* push(hipStream_t s, const void* data, size_t bytes);
+  void reset() { off_ = 0; }
+
+ private:
+  void grow(hipStream_t s, size_t need);
+  char* dev_ = nullptr;
+  char* host_ = nullptr;
+  size_t cap_ = 0, off_ = 0;
+};
+
+struct GemmBatch {
+  std::vector<GemmProblem> probs;
+  std::vector<GemmTerm> terms;
+  int max_m = 0, max_n = 0, transA = 0, transB = 0;
+  explicit GemmBatch(int ta = 0, int tb = 0) : transA(ta), transB(tb) {}
+  void add(double* C, int m, int n, int ldc, double beta = 0.0, double alpha = 1.0);
+  void term(const double* A, int lda, const double* B, int ldb, int k, double scale = 1.0);
+  void run(hipStream_t s, Stage& st);
+  bool empty() const { return probs.empty(); }
+};
+
+struct BlockBatch {
+  std::vector<BlockProblem> probs;
+  std::vector<BlockTerm> terms;
+  int max_m = 0, max_n = 0;
+  void add(double* dst, int m, int n, int ldd, double beta = 0.0, int add_eye = 0);
+  void term(const double* src, int lds, double alpha = 1.0, int trans = 0);
+  void run(hipStream_t s, Stage& st);
+};
+
+struct TrsmBatch {
+  std::vector<TrsmProblem> probs;
+  int max_n = 0, max_nrhs = 0;
+  void add(const double* L, int ldl, double* B, int ldb, int n, int nrhs);
+  void run(hipStream_t s, Stage& st, int trans, int upper = 0);
+};
+
+// A recorded launch with descriptors resident in device memory, replayed by
+// the solve loops (matvec and preconditioner apply) without host work.
+struct LaunchRec {
+  int type;  // 0 gemm, 1 block, 2 trsm
+  const void* probs;
+  const void* terms;
+  int nprob, max_m, max_n, transA, transB;
+};
+struct Recorder {
+  std::vector<LaunchRec> recs;
+  void gemm(Arena& a, hipStream_t s, const GemmBatch& b);
+  void block(Arena& a, hipStream_t s, const BlockBatch& b);
+  void trsm(Arena& a, hipStream_t s, const TrsmBatch& b, int trans);
+  void replay(hipStream_t s) const;
+};
+
+// ---------------------------------------------------------------- H^2 --
+struct H2Model {
+  spd_kernel kern{};
+  spd_h2_opts opts{};
+  TreeHost T;
+  Arena arena;
+  Stage stage;
+  hipStream_t s = nullptr;
+  double* pts = nullptr;        // SoA, tree order: x[N] y[N] z[N]
+  int64_t* perm_d = nullptr;    // tree position -> original index
+  // per node (heap order)
+  std::vector<int> k;             // skeleton size k_v
+  std::vector<int> cand;          // candidates: n_v (leaf) or k_c1 + k_c2
+  std::vector<int*> cand_d;       // device candidate tree positions (nonleaf: [skel_c1; skel_c2])
+  std::vector<std::vector<int>> cand_h;  // host copy (tree positions)
+  std::vector<std::vector<int>> skel_h;  // skeleton of every node (tree positions)
+  std::vector<double*> W;         // U_v (leaf) or R_v (nonleaf): cand_v x k_v, ld cand_v
+  std::vector<double*> Bh;        // per coupling entry: K(skel_i, skel_j), k_i x k_j
+  std::vector<double*> nearA;     // per leaf near entry: n_i x n_j, ld n_i
+  double times[4] = {0, 0, 0, 0};
+  // stacked layout of skeleton-space blocks: the two children of a node share
+  // one (cand_p x ncols, ld cand_p) buffer; par_off[p] is its row offset.
+  std::vector<int64_t> par_off;
+  int64_t stack_rows = 0;
+  struct MatvecPlan;
+  std::unique_ptr<MatvecPlan> plan;
+
+  H2Model();
+  ~H2Model();
+  const int* skel_d(int v) const {
+    const int p = (v - 1) / 2;
+    return cand_d[p] + ((v % 2 == 0) ? k[v - 1] : 0);
+  }
+  // block of node v (k_v x ncols, ld cand_parent) inside a stacked buffer
+  double* hat(double* base, int v, int ncols) const {
+    const int p = (v - 1) / 2;
+    return base + par_off[p] * ncols + ((v % 2 == 0) ? k[v - 1] : 0);
+  }
+  int hat_ld(int v) const { return cand[(v - 1) / 2]; }
+  int64_t n(int v) const { return T.size(v); }
+};
+
+void h2_build_impl(H2Model& H, const double* points, int64_t n);
+void h2_matvec_tree(H2Model& H, const double* x, double* y, int ncols);
+
+// --------------------------------------------------- SPD HSS + factors --
+// Nested factors shared by an HSS handle and the ULV handle made from it.
+struct Factors {
+  Arena arena;
+  TreeHost T;             // tree shape and ranges
+  int64_t* perm_d = nullptr;
+  std::vector<int> r;     // HSS rank per node
+  std::vector<int> rho;   // rows of the node's basis: n_v at leaves, r_c1 + r_c2 above
+  std::vector<double*> S; // leaf Cholesky factors S_v (n_v x n_v)
+  std::vector<double*> V; // V_v (leaf, n_v x r_v) or V-bar_v (rho_v x r_v)
+  std::vector<double*> F; // factor of I + bold B_v (rho_v x rho_v), nonleaf incl. root
+  bool root_factored = false;
+  // stacked rank-space layout: the children of p share a rho_p-row buffer
+  std::vector<int64_t> par_off;
+  int64_t stack_rows = 0;
+  double* blk(double* base, int v, int ncols) const {
+    const int p = (v - 1) / 2;
+    return base + par_off[p] * ncols + ((v % 2 == 0) ? r[v - 1] : 0);
+  }
+  int blk_ld(int v) const { return rho[(v - 1) / 2]; }
+};
+
+struct HSSModel {
+  std::shared_ptr<Factors> f;
+  spd_hss_opts opts{};
+  int s = 0;
+  Arena arena;
+  std::vector<double*> Z;     // S^{-T} V (leaf) or F^{-T} V-bar (nonleaf)
+  std::vector<double*> R;     // transfer matrices F V-bar (nonleaf)
+  std::vector<double*> PhiU;  // Phi_v U_v^H2: r_v x k_v
+  std::vector<int*> piv;      // pivots of the node's CPQR
+  std::vector<double*> Bn;    // HSS couplings per near entry (self entries null)
+  std::vector<double*> Bc;    // per coupling entry
+  std::vector<int> hk;        // H^2 ranks (copy)
+  TreeHost lists;             // tree with lists (for coupling queries)
+  double times[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double flops[4] = {0, 0, 0, 0};
+};
+
+void spdhss_build_impl(H2Model& H, const spd_hss_opts& o, HSSModel& M, hipStream_t s);
+
+struct ULVModel {
+  std::shared_ptr<Factors> f;
+  Stage stage;
+  hipStream_t s = nullptr;
+  struct ApplyPlan;
+  std::unique_ptr<ApplyPlan> plan;
+  ULVModel();
+  ~ULVModel();
+};
+
+void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s);
+void ulv_apply_tree(ULVModel& U, const double* b, double* x, int ncols);
+double* ulv_plan_z(ULVModel& U, int m);
+
+// product plan buffers: h2_plan_x is read and h2_plan_y written in place
+double* h2_plan_x(H2Model& H, int m);
+double* h2_plan_y(H2Model& H, int m);
+void h2_plan_run(H2Model& H);
+
+struct PcgResult {
+  std::vector<int> iters;
+  std::vector<double> relres;
+  bool converged = true;
+};
+PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m, double rtol,
+                   int maxit);
+
+double now_seconds();
+const char* last_error_cstr();
+
+}  // namespace spd

@@ -1,0 +1,221 @@
+// Runtime pieces of the library: device arena, descriptor staging, batch
+// builders and error bookkeeping.
+#include "model.h"
+
+#include <chrono>
+#include <cstring>
+
+namespace spd {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+double now_seconds() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------- arena --
+static constexpr size_t kChunk = size_t(256) << 20;
+
+Arena::~Arena() { release(); }
+
+void Arena::release() {
+  for (void* p : chunks_) (void)hipFree(p);
+  chunks_.clear();
+  cur_ = nullptr;
+  left_ = 0;
+  used_ = 0;
+}
+
+void* Arena::get(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  if (bytes > left_) {
+    const size_t sz = bytes > kChunk / 4 ? bytes : kChunk;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(SPD_E_NOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
+    }
+    chunks_.push_back(p);
+    used_ += sz;
+    if (sz != kChunk) return p;  // dedicated allocation; keep the current chunk
+    cur_ = static_cast<char*>(p);
+    left_ = sz;
+  }
+  void* r = cur_;
+  cur_ += bytes;
+  left_ -= bytes;
+  return r;
+}
+
+// ---------------------------------------------------------------- stage --
+Stage::~Stage() {
+  if (dev_) (void)hipFree(dev_);
+  if (host_) (void)hipHostFree(host_);
+}
+
+void Stage::grow(hipStream_t s, size_t need) {
+  size_t cap = cap_ ? cap_ : (size_t(4) << 20);
+  while (cap < need) cap *= 2;
+  SPD_HIP(hipStreamSynchronize(s));
+  if (dev_) SPD_HIP(hipFree(dev_));
+  if (host_) SPD_HIP(hipHostFree(host_));
+  dev_ = nullptr;
+  host_ = nullptr;
+  SPD_HIP(hipMalloc(&dev_, cap));
+  SPD_HIP(hipHostMalloc((void**)&host_, cap, hipHostMallocDefault));
+  cap_ = cap;
+  off_ = 0;
+}
+
+void* Stage::push(hipStream_t s, const void* data, size_t bytes) {
+  const size_t aligned = (bytes + 255) & ~size_t(255);
+  if (off_ + aligned > cap_) {
+    // everything already pushed must have been consumed before the buffer is
+    // replaced; grow() synchronizes the stream first
+    grow(s, std::max(aligned, cap_ * 2));
+  }
+  std::memcpy(host_ + off_, data, bytes);
+  void* d = dev_ + off_;
+  SPD_HIP(hipMemcpyAsync(d, host_ + off_, bytes, hipMemcpyHostToDevice, s));
+  off_ += aligned;
+  return d;
+}
+
+// -------------------------------------------------------------- batches --
+void GemmBatch::add(double* C, int m, int n, int ldc, double beta, double alpha) {
+  GemmProblem p{};
+  p.C = C;
+  p.m = m;
+  p.n = n;
+  p.ldc = ldc;
+  p.term_begin = p.term_end = (int)terms.size();
+  p.alpha = alpha;
+  p.beta = beta;
+  probs.push_back(p);
+  max_m = std::max(max_m, m);
+  max_n = std::max(max_n, n);
+}
+
+void GemmBatch::term(const double* A, int lda, const double* B, int ldb, int k, double scale) {
+  if (k <= 0) return;
+  GemmTerm t{};
+  t.A = A;
+  t.B = B;
+  t.scale = scale;
+  t.k = k;
+  t.lda = lda;
+  t.ldb = ldb;
+  terms.push_back(t);
+  probs.back().term_end = (int)terms.size();
+}
+
+void GemmBatch::run(hipStream_t s, Stage& st) {
+  if (probs.empty() || max_m == 0 || max_n == 0) return;
+  const GemmTerm dummy{};
+  auto* dp = (const GemmProblem*)st.push(s, probs.data(), probs.size() * sizeof(GemmProblem));
+  auto* dt = (const GemmTerm*)st.push(s, terms.empty() ? &dummy : terms.data(),
+                                      std::max<size_t>(1, terms.size()) * sizeof(GemmTerm));
+  launch_gemm(s, dp, dt, (int)probs.size(), max_m, max_n, transA, transB);
+}
+
+void BlockBatch::add(double* dst, int m, int n, int ldd, double beta, int add_eye) {
+  BlockProblem p{};
+  p.dst = dst;
+  p.m = m;
+  p.n = n;
+  p.ldd = ldd;
+  p.term_begin = p.term_end = (int)terms.size();
+  p.add_eye = add_eye;
+  p.beta = beta;
+  probs.push_back(p);
+  max_m = std::max(max_m, m);
+  max_n = std::max(max_n, n);
+}
+
+void BlockBatch::term(const double* src, int lds, double alpha, int trans) {
+  BlockTerm t{};
+  t.src = src;
+  t.lds = lds;
+  t.trans = trans;
+  t.alpha = alpha;
+  terms.push_back(t);
+  probs.back().term_end = (int)terms.size();
+}
+
+void BlockBatch::run(hipStream_t s, Stage& st) {
+  if (probs.empty() || max_m == 0 || max_n == 0) return;
+  const BlockTerm dummy{};
+  auto* dp = (const BlockProblem*)st.push(s, probs.data(), probs.size() * sizeof(BlockProblem));
+  auto* dt = (const BlockTerm*)st.push(s, terms.empty() ? &dummy : terms.data(),
+                                       std::max<size_t>(1, terms.size()) * sizeof(BlockTerm));
+  launch_block(s, dp, dt, (int)probs.size(), max_m, max_n);
+}
+
+void TrsmBatch::add(const double* L, int ldl, double* B, int ldb, int n, int nrhs) {
+  if (n <= 0 || nrhs <= 0) return;
+  TrsmProblem p{};
+  p.L = L;
+  p.B = B;
+  p.n = n;
+  p.nrhs = nrhs;
+  p.ldl = ldl;
+  p.ldb = ldb;
+  probs.push_back(p);
+  max_n = std::max(max_n, n);
+  max_nrhs = std::max(max_nrhs, nrhs);
+}
+
+void TrsmBatch::run(hipStream_t s, Stage& st, int trans, int upper) {
+  if (probs.empty()) return;
+  auto* dp = (const TrsmProblem*)st.push(s, probs.data(), probs.size() * sizeof(TrsmProblem));
+  launch_trsm(s, dp, (int)probs.size(), max_n, max_nrhs, trans, upper);
+}
+
+// ------------------------------------------------------------- recorder --
+template <class T>
+static const void* keep(Arena& a, hipStream_t s, const std::vector<T>& v) {
+  if (v.empty()) return nullptr;
+  return upload(a, s, v);
+}
+
+void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
+  if (b.probs.empty() || b.max_m == 0 || b.max_n == 0) return;
+  std::vector<GemmTerm> t = b.terms;
+  if (t.empty()) t.push_back(GemmTerm{});
+  recs.push_back({0, keep(a, s, b.probs), keep(a, s, t), (int)b.probs.size(), b.max_m, b.max_n,
+                  b.transA, b.transB});
+}
+
+void Recorder::block(Arena& a, hipStream_t s, const BlockBatch& b) {
+  if (b.probs.empty() || b.max_m == 0 || b.max_n == 0) return;
+  std::vector<BlockTerm> t = b.terms;
+  if (t.empty()) t.push_back(BlockTerm{});
+  recs.push_back({1, keep(a, s, b.probs), keep(a, s, t), (int)b.probs.size(), b.max_m, b.max_n, 0,
+                  0});
+}
+
+void Recorder::trsm(Arena& a, hipStream_t s, const TrsmBatch& b, int trans) {
+  if (b.probs.empty()) return;
+  recs.push_back({2, keep(a, s, b.probs), nullptr, (int)b.probs.size(), b.max_n, b.max_nrhs, trans,
+                  0});
+}
+
+void Recorder::replay(hipStream_t s) const {
+  for (const LaunchRec& r : recs) {
+    if (r.type == 0)
+      launch_gemm(s, (const GemmProblem*)r.probs, (const GemmTerm*)r.terms, r.nprob, r.max_m,
+                  r.max_n, r.transA, r.transB);
+    else if (r.type == 1)
+      launch_block(s, (const BlockProblem*)r.probs, (const BlockTerm*)r.terms, r.nprob, r.max_m,
+                   r.max_n);
+    else
+      launch_trsm(s, (const TrsmProblem*)r.probs, r.nprob, r.max_m, r.max_n, r.transA, 0);
+  }
+}
+
+}  // namespace spd

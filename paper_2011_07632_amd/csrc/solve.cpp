@@ -1,0 +1,283 @@
+// Solves with the SPD HSS matrix and PCG.
+//
+// Nested-factor solve.  At the leaf level the HSS matrix is
+// A = S (I + V M V^T) S^T with S = diag(S_i) and orthonormal V = diag(V_i)
+// (eq. Aii0 applied to the whole matrix), so
+// A^{-1} = S^{-T} (I + V((I + M)^{-1} - I) V^T) S^{-1}, and I + M has the same
+// form one level up with the factors F_i of I + bold B_ii (eqs. Si0/Si) down
+// to I + bold B_root at the root.  Unfolded this gives an upward sweep
+// (z = S^{-1} b, t = V^T z, u = F^{-1}[t_c], t = V-bar^T u), a root solve and a
+// downward sweep (u += V-bar (w - t), w_c = F^{-T} u; at the leaves
+// z += V (w - t), x = S^{-T} z).  The paper calls this step a ULV solve and
+// times it with the construction; the method is not spelled out there.
+//
+// PCG (Section 6): x0 = 0, one recurrence per right-hand side, a column stops
+// once its recursively updated residual satisfies ||r|| <= rtol ||b||.
+#include "model.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace spd {
+
+struct ULVModel::ApplyPlan {
+  int ncols = 0;
+  Arena arena;
+  Recorder rec;
+  double* z = nullptr;   // tree-order work vector (input and output)
+  double* ts = nullptr;  // stacked t blocks
+  double* ws = nullptr;  // stacked w blocks
+  std::vector<double*> u;
+};
+
+ULVModel::ULVModel() = default;
+ULVModel::~ULVModel() = default;
+
+void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
+  U.f = M.f;
+  U.s = s;
+  Factors& F = *U.f;
+  const TreeHost& T = F.T;
+  if (T.L == 1 || F.root_factored) {
+    F.root_factored = true;
+    return;
+  }
+  const int c1 = 1, c2 = 2, r1 = F.r[c1], r2 = F.r[c2], rv = r1 + r2;
+  F.rho[0] = rv;
+  F.F[0] = F.arena.get_n<double>((size_t)std::max(rv * rv, 1));
+  if (rv > 0) {
+    BlockBatch as;
+    if (r1 > 0) as.add(F.F[0], r1, r1, rv, 0.0, 1);
+    if (r2 > 0) as.add(F.F[0] + r1 + (size_t)r1 * rv, r2, r2, rv, 0.0, 1);
+    if (r1 > 0 && r2 > 0) {
+      const int64_t e12 = M.lists.near_pos(c1, c2), e21 = M.lists.near_pos(c2, c1);
+      const double* B12 = e12 >= 0 ? M.Bn[e12] : M.Bc[M.lists.coup_pos(c1, c2)];
+      const double* B21 = e21 >= 0 ? M.Bn[e21] : M.Bc[M.lists.coup_pos(c2, c1)];
+      as.add(F.F[0] + (size_t)r1 * rv, r1, r2, rv);
+      as.term(B12, r1);
+      as.add(F.F[0] + r1, r2, r1, rv);
+      as.term(B21, r2);
+    }
+    as.run(s, U.stage);
+    int* fail = F.arena.get_n<int>(2);
+    launch_fill(s, (double*)fail, 0.0, 1);
+    std::vector<CholProblem> ch{{F.F[0], rv, rv}};
+    auto* d = (const CholProblem*)U.stage.push(s, ch.data(), sizeof(CholProblem));
+    launch_chol(s, d, 1, rv, fail);
+    int hf = 0;
+    SPD_HIP(hipMemcpyAsync(&hf, fail, sizeof(int), hipMemcpyDeviceToHost, s));
+    SPD_HIP(hipStreamSynchronize(s));
+    U.stage.reset();
+    if (hf) throw Error(SPD_E_NOT_SPD, "I + B_root not positive definite (root, level " +
+                                           std::to_string(T.L) + ")");
+  }
+  SPD_HIP(hipStreamSynchronize(s));
+  F.root_factored = true;
+}
+
+static void build_apply_plan(ULVModel& U, int m) {
+  auto pl = std::make_unique<ULVModel::ApplyPlan>();
+  pl->ncols = m;
+  Factors& F = *U.f;
+  const TreeHost& T = F.T;
+  const int L = T.L, nn = T.nnodes;
+  const int64_t N = T.N;
+  hipStream_t s = U.s;
+  Arena& a = pl->arena;
+  Recorder& rec = pl->rec;
+  pl->z = a.get_n<double>((size_t)N * m);
+  const int lf = T.first_at(1), lc = T.count_at(1);
+  if (L == 1) {
+    TrsmBatch tb;
+    tb.add(F.S[0], (int)N, pl->z, (int)N, (int)N, m);
+    rec.trsm(a, s, tb, 0);
+    rec.trsm(a, s, tb, 1);
+    SPD_HIP(hipStreamSynchronize(s));
+    U.plan = std::move(pl);
+    return;
+  }
+  const int64_t rows = std::max<int64_t>(F.stack_rows, 1);
+  pl->ts = a.get_n<double>((size_t)rows * m);
+  pl->ws = a.get_n<double>((size_t)rows * m);
+  pl->u.assign(nn, nullptr);
+  // leaves: z = S^{-1} b ; t = V^T z
+  {
+    TrsmBatch tb;
+    GemmBatch g(1, 0);
+    for (int v = lf; v < lf + lc; ++v) {
+      const int nv = F.rho[v];
+      tb.add(F.S[v], nv, pl->z + T.start[v], (int)N, nv, m);
+      if (F.r[v] == 0) continue;
+      g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
+      g.term(F.V[v], nv, pl->z + T.start[v], (int)N, nv);
+    }
+    rec.trsm(a, s, tb, 0);
+    rec.gemm(a, s, g);
+  }
+  // upward: u = F^{-1} [t_c] ; t = V-bar^T u
+  for (int lev = 2; lev <= L - 1; ++lev) {
+    BlockBatch cp;
+    TrsmBatch tb;
+    GemmBatch g(1, 0);
+    for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
+      const int rv = F.rho[v];
+      pl->u[v] = a.get_n<double>((size_t)std::max(rv, 1) * m);
+      if (rv == 0) continue;
+      cp.add(pl->u[v], rv, m, rv);
+      cp.term(pl->ts + F.par_off[v] * m, rv);
+      tb.add(F.F[v], rv, pl->u[v], rv, rv, m);
+      if (F.r[v] == 0) continue;
+      g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
+      g.term(F.V[v], rv, pl->u[v], rv, rv);
+    }
+    rec.block(a, s, cp);
+    rec.trsm(a, s, tb, 0);
+    rec.gemm(a, s, g);
+  }
+  // root: w = F_root^{-T} F_root^{-1} [t_c]
+  {
+    const int rv = F.rho[0];
+    if (rv > 0) {
+      BlockBatch cp;
+      cp.add(pl->ws + F.par_off[0] * m, rv, m, rv);
+      cp.term(pl->ts + F.par_off[0] * m, rv);
+      rec.block(a, s, cp);
+      TrsmBatch tb;
+      tb.add(F.F[0], rv, pl->ws + F.par_off[0] * m, rv, rv, m);
+      rec.trsm(a, s, tb, 0);
+      rec.trsm(a, s, tb, 1);
+    }
+  }
+  // downward: u += V-bar (w - t) ; [w_c] = F^{-T} u
+  for (int lev = L - 1; lev >= 2; --lev) {
+    GemmBatch g(0, 0);
+    BlockBatch cp;
+    TrsmBatch tb;
+    for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
+      const int rv = F.rho[v];
+      if (rv == 0) continue;
+      if (F.r[v] > 0) {
+        g.add(pl->u[v], rv, m, rv, 1.0);
+        g.term(F.V[v], rv, F.blk(pl->ws, v, m), F.blk_ld(v), F.r[v], 1.0);
+        g.term(F.V[v], rv, F.blk(pl->ts, v, m), F.blk_ld(v), F.r[v], -1.0);
+      }
+      cp.add(pl->ws + F.par_off[v] * m, rv, m, rv);
+      cp.term(pl->u[v], rv);
+      tb.add(F.F[v], rv, pl->ws + F.par_off[v] * m, rv, rv, m);
+    }
+    rec.gemm(a, s, g);
+    rec.block(a, s, cp);
+    rec.trsm(a, s, tb, 1);
+  }
+  // leaves: z += V (w - t) ; x = S^{-T} z
+  {
+    GemmBatch g(0, 0);
+    TrsmBatch tb;
+    for (int v = lf; v < lf + lc; ++v) {
+      const int nv = F.rho[v];
+      if (F.r[v] > 0) {
+        g.add(pl->z + T.start[v], nv, m, (int)N, 1.0);
+        g.term(F.V[v], nv, F.blk(pl->ws, v, m), F.blk_ld(v), F.r[v], 1.0);
+        g.term(F.V[v], nv, F.blk(pl->ts, v, m), F.blk_ld(v), F.r[v], -1.0);
+      }
+      tb.add(F.S[v], nv, pl->z + T.start[v], (int)N, nv, m);
+    }
+    rec.gemm(a, s, g);
+    rec.trsm(a, s, tb, 1);
+  }
+  SPD_HIP(hipStreamSynchronize(s));
+  U.plan = std::move(pl);
+}
+
+double* ulv_plan_z(ULVModel& U, int m) {
+  if (!U.plan || U.plan->ncols != m) {
+    U.plan.reset();
+    build_apply_plan(U, m);
+  }
+  return U.plan->z;
+}
+
+void ulv_apply_tree(ULVModel& U, const double* b, double* x, int m) {
+  double* z = ulv_plan_z(U, m);
+  const int64_t N = U.f->T.N;
+  if (b != z)
+    SPD_HIP(hipMemcpyAsync(z, b, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, U.s));
+  U.plan->rec.replay(U.s);
+  if (x != z)
+    SPD_HIP(hipMemcpyAsync(x, z, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, U.s));
+}
+
+// ------------------------------------------------------------------ PCG --
+
+PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m, double rtol,
+                   int maxit) {
+  hipStream_t s = H.s;
+  const int64_t N = H.T.N;
+  const size_t bytes = (size_t)N * m * sizeof(double);
+  Arena a;
+  double* r = a.get_n<double>((size_t)N * m);
+  double* z = a.get_n<double>((size_t)N * m);
+  double* p = h2_plan_x(H, m);   // the product reads p in place
+  double* q = h2_plan_y(H, m);   // and writes q in place
+  const int nblk = ceil_div(N, 8192);
+  double* partial = a.get_n<double>((size_t)nblk * m);
+  double* sc = a.get_n<double>((size_t)8 * m);
+  double* rz = sc, *rzn = sc + m, *pq = sc + 2 * m, *rr = sc + 3 * m, *bb = sc + 4 * m;
+  int* active = a.get_n<int>(m + 1);
+  int* any = active + m;
+  auto precond = [&](const double* in, double* out) {
+    if (U) {
+      ulv_apply_tree(*U, in, out, m);
+    } else {
+      SPD_HIP(hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s));
+    }
+  };
+  launch_fill(s, xt, 0.0, (int64_t)N * m);
+  SPD_HIP(hipMemcpyAsync(r, bt, bytes, hipMemcpyDeviceToDevice, s));
+  precond(r, z);
+  SPD_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, s));
+  launch_coldot(s, r, z, N, m, N, partial, rz);
+  launch_coldot(s, bt, bt, N, m, N, partial, bb);
+  launch_coldot(s, r, r, N, m, N, partial, rr);
+  {
+    std::vector<int> ones(m, 1);
+    SPD_HIP(hipMemcpyAsync(active, ones.data(), m * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  launch_pcg_active(s, rr, bb, rtol, active, m, any);
+  PcgResult res;
+  res.iters.assign(m, 0);
+  std::vector<int> act(m + 1);
+  for (int it = 0; it < maxit; ++it) {
+    SPD_HIP(hipMemcpyAsync(act.data(), active, (m + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+    SPD_HIP(hipStreamSynchronize(s));
+    if (!act[m]) break;
+    for (int c = 0; c < m; ++c) res.iters[c] += act[c];
+    h2_plan_run(H);  // q = A p
+    launch_coldot(s, p, q, N, m, N, partial, pq);
+    launch_pcg_update_xr(s, xt, r, p, q, rz, pq, active, N, m, N, nullptr);
+    launch_coldot(s, r, r, N, m, N, partial, rr);
+    launch_pcg_active(s, rr, bb, rtol, active, m, any);
+    precond(r, z);
+    launch_coldot(s, r, z, N, m, N, partial, rzn);
+    launch_pcg_update_p(s, p, z, rzn, rz, active, N, m, N);
+  }
+  SPD_HIP(hipMemcpyAsync(act.data(), active, (m + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+  // true residual
+  SPD_HIP(hipMemcpyAsync(p, xt, bytes, hipMemcpyDeviceToDevice, s));
+  h2_plan_run(H);
+  SPD_HIP(hipMemcpyAsync(r, bt, bytes, hipMemcpyDeviceToDevice, s));
+  launch_axpby(s, r, q, -1.0, 1.0, N, m, N);
+  launch_coldot(s, r, r, N, m, N, partial, rr);
+  std::vector<double> hrr(m), hbb(m);
+  SPD_HIP(hipMemcpyAsync(hrr.data(), rr, m * sizeof(double), hipMemcpyDeviceToHost, s));
+  SPD_HIP(hipMemcpyAsync(hbb.data(), bb, m * sizeof(double), hipMemcpyDeviceToHost, s));
+  SPD_HIP(hipStreamSynchronize(s));
+  res.relres.resize(m);
+  for (int c = 0; c < m; ++c) {
+    res.relres[c] = hbb[c] > 0 ? std::sqrt(hrr[c] / hbb[c]) : std::sqrt(hrr[c]);
+    if (act[c]) res.converged = false;
+  }
+  return res;
+}
+
+}  // namespace spd

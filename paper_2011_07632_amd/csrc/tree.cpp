@@ -1,0 +1,204 @@
+// Partition tree and admissibility lists (host).
+//
+// Perfect binary kd-tree (Section 2 assumes a perfect tree): depth D is the
+// smallest integer with N <= leaf * 2^D; a node is split on the axis of its
+// largest bounding-box extent (lowest axis on ties), its points ordered by
+// (coordinate, original index), the left child taking floor(n/2) of them.
+// Far-field sets (Section 5.1) use the admissibility rule
+// r_i + r_j <= eta * |c_i - c_j| on bounding-box centres c and half-diagonals
+// r; near (Type-1) and coupling (Type-3) lists are built top-down from the
+// children of the parent's near list (Section 5.2.2).
+//
+// Floating-point contraction is disabled here so that every comparison that
+// decides the tree or a list is evaluated in plain IEEE double arithmetic.
+#pragma clang fp contract(off)
+
+#include "model.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace spd {
+
+static int depth_for(int64_t n, int leaf) {
+  int d = 0;
+  while (n > (int64_t)leaf * ((int64_t)1 << d)) ++d;
+  return d;
+}
+
+void TreeHost::build(const double* pts, int64_t n, int leaf_size, double eta_) {
+  SPD_REQUIRE(n >= 1, SPD_E_INVALID, "empty point set");
+  SPD_REQUIRE(leaf_size >= 1, SPD_E_INVALID, "leaf size must be positive");
+  N = n;
+  leaf = leaf_size;
+  eta = eta_;
+  D = depth_for(n, leaf);
+  SPD_REQUIRE(D <= 24, SPD_E_INVALID, "tree too deep");
+  L = D + 1;
+  nnodes = (1 << (D + 1)) - 1;
+  perm.resize(n);
+  std::iota(perm.begin(), perm.end(), (int64_t)0);
+  start.assign(nnodes, 0);
+  end.assign(nnodes, 0);
+  end[0] = n;
+  for (int v = 0; v < (1 << D) - 1; ++v) {
+    const int64_t s = start[v], e = end[v];
+    double lo3[3] = {INFINITY, INFINITY, INFINITY}, hi3[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = s; i < e; ++i)
+      for (int a = 0; a < 3; ++a) {
+        const double x = pts[3 * perm[i] + a];
+        lo3[a] = std::min(lo3[a], x);
+        hi3[a] = std::max(hi3[a], x);
+      }
+    int axis = 0;
+    if (e > s) {
+      double best = hi3[0] - lo3[0];
+      for (int a = 1; a < 3; ++a)
+        if (hi3[a] - lo3[a] > best) { best = hi3[a] - lo3[a]; axis = a; }
+    }
+    std::sort(perm.begin() + s, perm.begin() + e, [&](int64_t a, int64_t b) {
+      const double xa = pts[3 * a + axis], xb = pts[3 * b + axis];
+      return xa < xb || (xa == xb && a < b);
+    });
+    const int64_t half = (e - s) / 2;
+    start[2 * v + 1] = s;
+    end[2 * v + 1] = s + half;
+    start[2 * v + 2] = s + half;
+    end[2 * v + 2] = e;
+  }
+  lo.assign(3 * nnodes, 0.0);
+  hi.assign(3 * nnodes, 0.0);
+  for (int v = nnodes - 1; v >= 0; --v) {
+    if (is_leaf(v)) {
+      if (end[v] > start[v]) {
+        for (int a = 0; a < 3; ++a) { lo[3 * v + a] = INFINITY; hi[3 * v + a] = -INFINITY; }
+        for (int64_t i = start[v]; i < end[v]; ++i)
+          for (int a = 0; a < 3; ++a) {
+            const double x = pts[3 * perm[i] + a];
+            lo[3 * v + a] = std::min(lo[3 * v + a], x);
+            hi[3 * v + a] = std::max(hi[3 * v + a], x);
+          }
+      }
+    } else {
+      const int c1 = 2 * v + 1, c2 = 2 * v + 2;
+      const bool e1 = end[c1] > start[c1], e2 = end[c2] > start[c2];
+      for (int a = 0; a < 3; ++a) {
+        if (e1 && e2) {
+          lo[3 * v + a] = std::min(lo[3 * c1 + a], lo[3 * c2 + a]);
+          hi[3 * v + a] = std::max(hi[3 * c1 + a], hi[3 * c2 + a]);
+        } else if (e1 || e2) {
+          const int c = e1 ? c1 : c2;
+          lo[3 * v + a] = lo[3 * c + a];
+          hi[3 * v + a] = hi[3 * c + a];
+        }
+      }
+    }
+  }
+  center.assign(3 * nnodes, 0.0);
+  radius.assign(nnodes, 0.0);
+  for (int v = 0; v < nnodes; ++v) {
+    double d[3];
+    for (int a = 0; a < 3; ++a) {
+      center[3 * v + a] = 0.5 * (lo[3 * v + a] + hi[3 * v + a]);
+      d[a] = hi[3 * v + a] - lo[3 * v + a];
+    }
+    radius[v] = 0.5 * std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  }
+  build_lists();
+}
+
+bool TreeHost::admissible(int i, int j) const {
+  if (i == j) return false;
+  const double dx = center[3 * i] - center[3 * j];
+  const double dy = center[3 * i + 1] - center[3 * j + 1];
+  const double dz = center[3 * i + 2] - center[3 * j + 2];
+  const double dist = std::sqrt(dx * dx + dy * dy + dz * dz);
+  return radius[i] + radius[j] <= eta * dist;
+}
+
+void TreeHost::build_lists() {
+  std::vector<std::vector<int>> nearl(nnodes), coupl(nnodes);
+  nearl[0] = {0};
+  for (int d = 1; d <= D; ++d) {
+    for (int v = (1 << d) - 1; v < (1 << (d + 1)) - 1; ++v) {
+      const int p = (v - 1) / 2;
+      for (int q : nearl[p])
+        for (int j = 2 * q + 1; j <= 2 * q + 2; ++j)
+          (admissible(v, j) ? coupl[v] : nearl[v]).push_back(j);
+      std::sort(nearl[v].begin(), nearl[v].end());
+      std::sort(coupl[v].begin(), coupl[v].end());
+    }
+  }
+  near_ptr.assign(nnodes + 1, 0);
+  coup_ptr.assign(nnodes + 1, 0);
+  near_idx.clear();
+  coup_idx.clear();
+  for (int v = 0; v < nnodes; ++v) {
+    near_ptr[v] = (int64_t)near_idx.size();
+    coup_ptr[v] = (int64_t)coup_idx.size();
+    near_idx.insert(near_idx.end(), nearl[v].begin(), nearl[v].end());
+    coup_idx.insert(coup_idx.end(), coupl[v].begin(), coupl[v].end());
+  }
+  near_ptr[nnodes] = (int64_t)near_idx.size();
+  coup_ptr[nnodes] = (int64_t)coup_idx.size();
+}
+
+int TreeHost::lca_level(int i, int j) const {
+  int k = level(i);
+  while (i != j) {
+    i = (i - 1) / 2;
+    j = (j - 1) / 2;
+    ++k;
+  }
+  return k;
+}
+
+int64_t TreeHost::near_pos(int i, int j) const {
+  const int* b = near_idx.data() + near_ptr[i];
+  const int* e = near_idx.data() + near_ptr[i + 1];
+  const int* it = std::lower_bound(b, e, j);
+  return (it != e && *it == j) ? near_ptr[i] + (it - b) : -1;
+}
+
+int64_t TreeHost::coup_pos(int i, int j) const {
+  const int* b = coup_idx.data() + coup_ptr[i];
+  const int* e = coup_idx.data() + coup_ptr[i + 1];
+  const int* it = std::lower_bound(b, e, j);
+  return (it != e && *it == j) ? coup_ptr[i] + (it - b) : -1;
+}
+
+// Proxy radii of a node: from the nearest box of its far field (couplings of
+// the node and all ancestors) to the farthest corner of the root box.
+bool TreeHost::proxy_radii(int v, double& rin, double& rout) const {
+  rin = INFINITY;
+  bool any = false;
+  const double* c = &center[3 * v];
+  int a = v;
+  while (true) {
+    for (int64_t e = coup_ptr[a]; e < coup_ptr[a + 1]; ++e) {
+      const int j = coup_idx[e];
+      double d[3];
+      for (int q = 0; q < 3; ++q)
+        d[q] = std::max(std::max(lo[3 * j + q] - c[q], 0.0), c[q] - hi[3 * j + q]);
+      rin = std::min(rin, std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+      any = true;
+    }
+    if (a == 0) break;
+    a = (a - 1) / 2;
+  }
+  if (!any) return false;
+  rout = 0.0;
+  for (int ix = 0; ix < 2; ++ix)
+    for (int iy = 0; iy < 2; ++iy)
+      for (int iz = 0; iz < 2; ++iz) {
+        const double dx = (ix ? hi[0] : lo[0]) - c[0];
+        const double dy = (iy ? hi[1] : lo[1]) - c[1];
+        const double dz = (iz ? hi[2] : lo[2]) - c[2];
+        rout = std::max(rout, std::sqrt(dx * dx + dy * dy + dz * dz));
+      }
+  rout = std::max(rout, rin);
+  return true;
+}
+
+}  // namespace spd

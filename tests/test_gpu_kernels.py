@@ -1,0 +1,122 @@
+"""Each batched HIP kernel against the CPU oracle's building blocks (GPU)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2011_07632_amd import binding
+    return binding
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def colmajor_batch(mats):
+    """list of (rows x cols) arrays -> (batch, cols, rows) contiguous array"""
+    return np.stack([m.T for m in mats])
+
+
+@pytest.mark.parametrize("m,n,k", [(70, 8, 33), (129, 24, 65), (245, 110, 245), (5, 3, 1)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm(B, m, n, k, ta, tb):
+    rng = np.random.default_rng(m * n + ta * 2 + tb)
+    bt = 3
+    As = [rng.standard_normal((k, m) if ta else (m, k)) for _ in range(bt)]
+    Bs = [rng.standard_normal((n, k) if tb else (k, n)) for _ in range(bt)]
+    Cs = [rng.standard_normal((m, n)) for _ in range(bt)]
+    dA, dB, dC = dev(colmajor_batch(As)), dev(colmajor_batch(Bs)), dev(colmajor_batch(Cs))
+    B.test_gemm(dA, dB, dC, ta, tb, alpha=0.5, beta=-2.0)
+    out = dC.cpu().numpy()
+    for b in range(bt):
+        a = As[b].T if ta else As[b]
+        bb = Bs[b].T if tb else Bs[b]
+        ref = 0.5 * a @ bb - 2.0 * Cs[b]
+        np.testing.assert_allclose(out[b].T, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n", [1, 31, 63, 245, 300])
+def test_cholesky(B, n):
+    rng = np.random.default_rng(n)
+    mats = []
+    for _ in range(3):
+        G = rng.standard_normal((n, n))
+        mats.append(G @ G.T + n * np.eye(n))
+    d = dev(colmajor_batch(mats))
+    fail = torch.zeros(3, dtype=torch.int32, device="cuda")
+    B.test_chol(d, fail)
+    assert fail.cpu().numpy().tolist() == [0, 0, 0]
+    out = d.cpu().numpy()
+    for b in range(3):
+        ref = np.linalg.cholesky(mats[b])
+        np.testing.assert_allclose(out[b].T, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_cholesky_reports_indefinite(B):
+    rng = np.random.default_rng(5)
+    n = 70
+    G = rng.standard_normal((n, n))
+    good = G @ G.T + n * np.eye(n)
+    bad = good.copy()
+    bad[40, 40] = -1e3
+    d = dev(colmajor_batch([good, bad]))
+    fail = torch.zeros(2, dtype=torch.int32, device="cuda")
+    B.test_chol(d, fail)
+    assert fail.cpu().numpy().tolist() == [0, 1]
+
+
+@pytest.mark.parametrize("n,nrhs", [(1, 3), (63, 110), (245, 16), (300, 40)])
+@pytest.mark.parametrize("trans,upper", [(0, 0), (1, 0), (1, 1)])
+def test_trsm(B, n, nrhs, trans, upper):
+    rng = np.random.default_rng(n + nrhs)
+    Ls, Bs = [], []
+    for _ in range(2):
+        Lm = np.tril(rng.standard_normal((n, n))) + n * np.eye(n)
+        if upper:
+            Lm = Lm.T
+        Ls.append(Lm)
+        Bs.append(rng.standard_normal((n, nrhs)))
+    dL, dB = dev(colmajor_batch(Ls)), dev(colmajor_batch(Bs))
+    B.test_trsm(dL, dB, trans, upper)
+    out = dB.cpu().numpy()
+    for b in range(2):
+        if upper:
+            ref = sla.solve_triangular(Ls[b], Bs[b], lower=False)
+        else:
+            ref = sla.solve_triangular(Ls[b], Bs[b], lower=True, trans="T" if trans else "N")
+        np.testing.assert_allclose(out[b].T, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("m,n,which", [(245, 110, 0), (63, 110, 0), (200, 110, 0), (300, 110, 0),
+                                       (1024, 245, 1), (512, 300, 1)])
+def test_cpqr(B, m, n, which):
+    from oracle.linalg import CPQR
+    rng = np.random.default_rng(m + n)
+    mats = [rng.standard_normal((m, n)) @ np.diag(np.exp(-0.05 * np.arange(n))) @
+            np.linalg.qr(rng.standard_normal((n, n)))[0] for _ in range(2)]
+    maxrank = min(m, n, 100 if which == 0 else 4096)
+    tol = 1e-3
+    bt = len(mats)
+    dA = dev(colmajor_batch(mats))
+    Q = torch.zeros((bt, max(maxrank, 1), m), dtype=torch.float64, device="cuda")
+    piv = torch.zeros((bt, n if which else max(maxrank, 1)), dtype=torch.int32, device="cuda")
+    rank = torch.zeros(bt, dtype=torch.int32, device="cuda")
+    diag = torch.zeros((bt, max(maxrank, 1)), dtype=torch.float64, device="cuda")
+    B.test_cpqr(dA, Q if which == 0 else None, piv, rank, diag, maxrank, tol, which)
+    for b in range(bt):
+        f = CPQR(mats[b], tol, maxrank)
+        r = int(rank[b])
+        assert r == f.rank
+        assert piv[b, :r].cpu().numpy().tolist() == f.piv.tolist()
+        np.testing.assert_allclose(diag[b, :r].cpu().numpy(), f.diag, rtol=1e-10)
+        if which == 0:
+            Qg = Q[b, :r].cpu().numpy().T
+            np.testing.assert_allclose(Qg, f.q(), rtol=0, atol=1e-10)

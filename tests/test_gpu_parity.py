@@ -1,0 +1,176 @@
+"""HIP path vs the CPU oracle, stage by stage, on seeded workloads (GPU).
+
+Tolerances: 1e-10 relative for FP64 quantities; exact equality for the tree,
+lists, skeleton sets, pivots and ranks (integer results)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle.h2 import H2 as OH2
+from oracle.pcg import pcg as opcg
+from oracle.spdhss import SPDHSS as OHSS
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+# Phi_v U_v^H2 contains the interpolation matrix W = [I; (R11^{-1} R12)^T] of the
+# proxy ID entry by entry.  With relative truncation at eps_H the triangular
+# R11 has condition number up to about 1/eps_H, so last-bit differences in the
+# proxy matrix can grow to u/eps_H in W (and Phi U).  Products that apply W to
+# data (matvec, samples, bases, couplings) stay at TOL.
+U_ROUND = 2.0 ** -53
+
+
+def phiu_tol(eps_h):
+    return max(TOL, 10 * U_ROUND / eps_h)
+
+CASES = {
+    # small Gaussian case: 2,000 cube points, 32 leaves of 62/63
+    "gauss2000": dict(w=workloads.SMALL, shells=8, per_shell=128),
+    # ragged Matern case spanning several tiles: 3,001 points, leaves of 46/47
+    "matern3001": dict(w=workloads.SMALL.with_(name="matern32-l0.15-N3001", n=3001, kernel="matern32",
+                                               ell=0.15, shift=1e-3, leaf=50, max_rank=40, seed_base=7),
+                       shells=6, per_shell=96),
+    # exponential kernel on the unit sphere, threshold form with a small cap
+    "exp1500": dict(w=workloads.SMALL.with_(name="exp-l0.2-N1500-sphere", n=1500, point_set="sphere",
+                                            kernel="exponential", ell=0.2, shift=1e-2, leaf=40,
+                                            max_rank=30, hss_tol=1e-3, seed_base=8),
+                    shells=6, per_shell=96),
+    # inverse multiquadric, fixed-rank form (tol = 0)
+    "imq1200": dict(w=workloads.SMALL.with_(name="imq-c0.1-N1200", n=1200, kernel="imq", ell=0.1,
+                                            shift=1e-3, leaf=30, max_rank=20, hss_tol=0.0, seed_base=9),
+                    shells=4, per_shell=64),
+}
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    d = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
+
+
+class Pair:
+    def __init__(self, name):
+        from paper_2011_07632_amd import binding as B
+        c = CASES[name]
+        w = c["w"]
+        print(f"\n[parity] case {name}: N={w.n} kernel={w.kernel}", flush=True)
+        self.w, self.B = w, B
+        X = w.points()
+        self.X = X
+        self.o_h2 = OH2(X, w.kernel, w.ell, w.shift, w.leaf, w.h2_tol, eta=w.eta,
+                        shells=c["shells"], per_shell=c["per_shell"])
+        self.T = self.o_h2.tree
+        om = w.omega()
+        self.o_hss = OHSS(self.o_h2, om[self.T.perm], w.hss_tol, w.max_rank, "chol")
+        self.g_h2 = B.h2_build(torch.from_numpy(X).cuda(), w.kernel, w.ell, w.shift, leaf=w.leaf,
+                               tol=w.h2_tol, eta=w.eta, proxy_shells=c["shells"],
+                               proxy_per_shell=c["per_shell"])
+        self.g_hss = B.spdhss_build(self.g_h2, w.hss_tol, w.max_rank, w.oversample,
+                                    omega=B.cols_like(w.n, w.s, "cuda").copy_(torch.from_numpy(om)))
+        self.g_ulv = B.ulv_factor(self.g_hss)
+
+
+_pairs = {}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def P(request):
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    if request.param not in _pairs:
+        _pairs[request.param] = Pair(request.param)
+    return _pairs[request.param]
+
+
+def test_tree_and_lists_exact(P):
+    T = P.T
+    assert P.g_h2.perm().tolist() == T.perm.tolist()
+    assert P.g_h2.node_start()[:-1].tolist() == T.start.tolist()
+    near, coup = P.g_h2.lists()
+    for v in range(T.nnodes):
+        assert near[v] == T.near[v], v
+        assert coup[v] == T.coup[v], v
+
+
+def test_h2_skeletons_exact(P):
+    T = P.T
+    k = P.g_h2.ranks()
+    sk = P.g_h2.skeletons()
+    for v in range(1, T.nnodes):
+        assert k[v] == P.o_h2.rank(v), v
+        assert sk[v].tolist() == P.o_h2.skel[v].tolist(), v
+
+
+def test_h2_matvec(P):
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((P.w.n, 3))
+    xg = P.B.cols_like(P.w.n, 3, "cuda").copy_(torch.from_numpy(x))
+    y = P.B.h2_matvec(P.g_h2, xg).cpu().numpy()
+    yo = np.empty_like(x)
+    yo[P.T.perm] = P.o_h2.matvec(x[P.T.perm])
+    assert rel(y, yo) <= TOL
+
+
+def test_hss_ranks_pivots_exact(P):
+    T = P.T
+    r = P.g_hss.ranks()
+    for v in range(1, T.nnodes):
+        assert r[v] == P.o_hss.rank[v], v
+        assert P.g_hss.pivots(v).tolist() == P.o_hss.piv[v].tolist(), v
+
+
+def test_hss_generators(P):
+    T, o = P.T, P.o_hss
+    for v in range(1, T.nnodes):
+        if o.rank[v] == 0:
+            continue
+        Vo = o.V[v] if T.is_leaf(v) else o.Vbar[v]
+        assert np.abs(P.g_hss.basis(v) - Vo).max() <= TOL, v
+        if not T.is_leaf(v):
+            assert rel(P.g_hss.transfer(v), o.R[v]) <= TOL, v
+        if P.o_h2.rank(v) > 0:
+            assert rel(P.g_hss.phiu(v), o.PhiU[v]) <= phiu_tol(P.w.h2_tol), v
+    for (i, j), Bo in o.Bc.items():
+        if o.rank[i] and o.rank[j]:
+            assert rel(P.g_hss.coupling(i, j), Bo) <= TOL, (i, j)
+
+
+def test_leaf_factors(P):
+    for v in P.T.leaves()[:8]:
+        assert rel(P.g_hss.factor(v), P.o_hss.S[v]) <= TOL
+
+
+def test_ulv_apply(P):
+    b = workloads.gaussian_matrix(P.w.n, 4, 77)
+    bg = P.B.cols_like(P.w.n, 4, "cuda").copy_(torch.from_numpy(b))
+    x = P.B.ulv_apply(P.g_ulv, bg).cpu().numpy()
+    xo = np.empty_like(b)
+    xo[P.T.perm] = P.o_hss.solve(b[P.T.perm])
+    assert rel(x, xo) <= TOL
+
+
+def test_pcg_fixed_iterations(P):
+    b = P.w.rhs()
+    bg = P.B.cols_like(P.w.n, b.shape[1], "cuda").copy_(torch.from_numpy(b))
+    for k in (1, 5):
+        x, it, _ = P.B.pcg_solve(P.g_h2, P.g_ulv, bg, rtol=0.0, maxit=k, raise_on_nonconvergence=False)
+        xo_t, ito, _ = opcg(P.o_h2.matvec, P.o_hss.solve, b[P.T.perm], 0.0, k)
+        xo = np.empty_like(b)
+        xo[P.T.perm] = xo_t
+        assert it.tolist() == ito.tolist()
+        assert rel(x.cpu().numpy(), xo) <= TOL
+
+
+def test_pcg_converges_like_oracle(P):
+    b = P.w.rhs()
+    bg = P.B.cols_like(P.w.n, b.shape[1], "cuda").copy_(torch.from_numpy(b))
+    x, it, res = P.B.pcg_solve(P.g_h2, P.g_ulv, bg, rtol=P.w.pcg_tol, maxit=500)
+    _, ito, reso = opcg(P.o_h2.matvec, P.o_hss.solve, b[P.T.perm], P.w.pcg_tol, 500)
+    assert np.abs(it - ito).max() <= 1
+    assert (res <= 2 * P.w.pcg_tol).all()
+    print(f"[parity] iterations gpu={it.tolist()} oracle={ito.tolist()} relres={res.tolist()}",
+          flush=True)
