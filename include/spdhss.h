@@ -180,6 +180,15 @@ typedef enum {
 spd_status spd_hss_query_get(spd_hss_t M, int32_t what, int32_t node,
                              int32_t node2, void* host_out, int64_t bytes);
 
+/* Time the dominant kernel of h2_matvec, the leaf-level pass y_i = U_i y-hat_i
+ * + sum_j A_ij x_j over all leaves, for nrhs columns: reps launches bracketed
+ * by HIP events on `stream`.  *ms = average milliseconds per launch; *bytes =
+ * algorithmic bytes per launch (every near block, leaf basis and skeleton
+ * input once, x read once, y written once).  Works on the handle's internal
+ * buffers; no caller data is touched. */
+spd_status spd_h2_time_near(spd_h2_t A, int32_t nrhs, int32_t reps, void* stream, double* ms,
+                            double* bytes);
+
 /* ---- kernel test hooks: run one batched device kernel on caller buffers.
  * All pointers are DEVICE pointers; shapes are uniform across the batch.
  * They exist so that each kernel can be compared on its own against the

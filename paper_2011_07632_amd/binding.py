@@ -63,6 +63,7 @@ def _load():
         "pcg_solve": [vp, vp, vp, vp, i32, i64, dbl, i32, vp, vp, vp],
         "spd_h2_query_get": [vp, i32, vp, i64],
         "spd_hss_query_get": [vp, i32, i32, i32, vp, i64],
+        "spd_h2_time_near": [vp, i32, i32, vp, vp, vp],
         "spd_test_gemm": [vp, vp, vp, i32, i32, i32, i32, i32, i32, dbl, dbl, vp],
         "spd_test_chol": [vp, i32, i32, vp, vp],
         "spd_test_trsm": [vp, vp, i32, i32, i32, i32, i32, vp],
@@ -332,6 +333,13 @@ def pcg_solve(A: H2Matrix, M: ULVFactor | None, b: torch.Tensor, rtol: float = 1
         return out, iters, relres
     _check(code)
     return out, iters, relres
+
+
+def near_field_roofline(A: H2Matrix, nrhs: int, reps: int = 20, stream=None) -> dict:
+    """Average time and algorithmic bytes of the product's dominant kernel."""
+    ms, b = C.c_double(), C.c_double()
+    _check(lib.spd_h2_time_near(A._h, int(nrhs), int(reps), _stream(stream), C.byref(ms), C.byref(b)))
+    return {"ms": ms.value, "bytes": b.value, "gbs": b.value / (ms.value * 1e-3) / 1e9}
 
 
 # ------------------------------------------------------------------ kernel hooks --

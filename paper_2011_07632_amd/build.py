@@ -1,6 +1,9 @@
 """Compile the HIP library libspdhss.so for gfx950 (in-tree).
 
-    python -m paper_2011_07632_amd.build
+    python paper_2011_07632_amd/build.py
+
+(Run by path: importing the package loads the library, so the build script
+must not be imported through it.)
 
 Every source is compiled by hipcc with packed FP32 instructions disabled for
 the device; the library is linked next to this file.

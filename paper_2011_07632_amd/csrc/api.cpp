@@ -164,6 +164,15 @@ spd_status pcg_solve(spd_h2_t A, spd_ulv_t M, const double* b, double* x, int32_
   SPD_API_END
 }
 
+spd_status spd_h2_time_near(spd_h2_t A, int32_t nrhs, int32_t reps, void* stream, double* ms,
+                            double* bytes) {
+  SPD_API_BEGIN
+  SPD_REQUIRE(A && ms && bytes && nrhs >= 1 && reps >= 1, SPD_E_INVALID, "bad args");
+  A->m.s = as_stream(stream);
+  h2_time_near(A->m, nrhs, reps, ms, bytes);
+  SPD_API_END
+}
+
 void h2_destroy(spd_h2_t A) {
   try { delete A; } catch (...) {}
 }
@@ -310,7 +319,7 @@ spd_status spd_test_chol(double* A, int32_t batch, int32_t n, int32_t* fail, voi
 spd_status spd_test_trsm(const double* L, double* B, int32_t batch, int32_t n, int32_t nrhs,
                          int32_t trans, int32_t upper, void* stream) {
   SPD_API_BEGIN
-  SPD_REQUIRE(L && B && batch >= 1 && n >= 1 && n <= 1024 && nrhs >= 1, SPD_E_INVALID, "bad args");
+  SPD_REQUIRE(L && B && batch >= 1 && n >= 1 && n <= 2048 && nrhs >= 1, SPD_E_INVALID, "bad args");
   hipStream_t s = as_stream(stream);
   Stage st;
   TrsmBatch tb;

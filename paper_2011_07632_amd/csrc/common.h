@@ -139,7 +139,7 @@ void launch_coldot(hipStream_t s, const double* x, const double* y, int64_t n,
 void launch_pcg_update_xr(hipStream_t s, double* x, double* r, const double* p,
                           const double* q, const double* rz, const double* pq,
                           const int* active, int64_t n, int ncols, int64_t ld,
-                          double* alpha_out);
+                          int* iters);
 void launch_pcg_update_p(hipStream_t s, double* p, const double* z,
                          const double* rz_new, double* rz, const int* active,
                          int64_t n, int ncols, int64_t ld);

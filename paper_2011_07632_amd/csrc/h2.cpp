@@ -339,4 +339,27 @@ double* h2_plan_y(H2Model& H, int m) {
 }
 void h2_plan_run(H2Model& H) { H.plan->rec.replay(H.s); }
 
+// the last recorded launch of the product is the leaf pass: y = U y-hat + near
+void h2_plan_run_last(H2Model& H) {
+  Recorder one;
+  one.recs.push_back(H.plan->rec.recs.back());
+  one.replay(H.s);
+}
+
+// Algorithmic bytes of the leaf pass: every stored near block once, the leaf
+// bases and skeleton-space inputs once, x read once and y written once.
+H2Model::NearStats h2_near_stats(H2Model& H, int m) {
+  const TreeHost& T = H.T;
+  double b = 0;
+  for (int v = T.first_at(1); v < T.first_at(1) + T.count_at(1); ++v) {
+    for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e)
+      b += 8.0 * (double)T.size(v) * (double)T.size(T.near_idx[e]);
+    if (T.L > 1) b += 8.0 * (double)H.cand[v] * H.k[v] + 8.0 * (double)H.k[v] * m;
+  }
+  b += 2.0 * 8.0 * (double)T.N * m;
+  H2Model::NearStats st;
+  st.bytes = b;
+  return st;
+}
+
 }  // namespace spd

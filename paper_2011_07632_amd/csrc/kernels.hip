@@ -478,7 +478,7 @@ void launch_trsm(hipStream_t s, const TrsmProblem* d_p, int nprob, int max_n, in
     hipLaunchKernelGGL((k_trsm<CB>), dim3((unsigned)np8 * ncb), dim3(256),
                        (size_t)max_n * CB * sizeof(double), s, d_p, nprob, ncb, trans, upper);
   } else {
-    SPD_REQUIRE(max_n <= 1024, SPD_E_INVALID, "triangular solve: order above 1024");
+    SPD_REQUIRE(max_n <= 2048, SPD_E_INVALID, "triangular solve: order above 2048");
     constexpr int CB = 8;
     const int ncb = ceil_div(max_nrhs, CB);
     hipLaunchKernelGGL((k_trsm<CB>), dim3((unsigned)np8 * ncb), dim3(256),
@@ -927,12 +927,12 @@ __global__ void k_pcg_update_xr(double* __restrict__ x, double* __restrict__ r,
                                 const double* __restrict__ p, const double* __restrict__ q,
                                 const double* __restrict__ rz, const double* __restrict__ pq,
                                 const int* __restrict__ active, int64_t n, int64_t ld,
-                                double* alpha_out) {
+                                int* __restrict__ iters) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (!active[c]) return;
   const double alpha = rz[c] / pq[c];
-  if (i == 0 && alpha_out) alpha_out[c] = alpha;
+  if (i == 0 && iters) iters[c] += 1;
   if (i < n) {
     x[i + c * ld] += alpha * p[i + c * ld];
     r[i + c * ld] -= alpha * q[i + c * ld];
@@ -940,9 +940,9 @@ __global__ void k_pcg_update_xr(double* __restrict__ x, double* __restrict__ r,
 }
 void launch_pcg_update_xr(hipStream_t s, double* x, double* r, const double* p, const double* q,
                           const double* rz, const double* pq, const int* active, int64_t n,
-                          int ncols, int64_t ld, double* alpha_out) {
+                          int ncols, int64_t ld, int* iters) {
   hipLaunchKernelGGL(k_pcg_update_xr, dim3(ceil_div(n, 256), ncols), dim3(256), 0, s, x, r, p, q,
-                     rz, pq, active, n, ld, alpha_out);
+                     rz, pq, active, n, ld, iters);
   SPD_HIP(hipGetLastError());
 }
 

@@ -35,19 +35,23 @@ struct TreeHost {
 
 // --------------------------------------------------- descriptor staging --
 // Collects descriptor arrays on the host and copies them to device memory.
-// Device copies stay valid until reset(), which the owner calls only after
-// synchronizing the stream.
+// A device copy stays valid until reset(), which the owner calls only after
+// synchronizing the stream; filling a chunk opens a new one and never frees
+// an earlier chunk, whose descriptors may still be waiting for their launch.
 class Stage {
  public:
   ~Stage();
   void* push(hipStream_t s, const void* data, size_t bytes);
-  void reset() { off_ = 0; }
+  void reset();
 
  private:
-  void grow(hipStream_t s, size_t need);
-  char* dev_ = nullptr;
-  char* host_ = nullptr;
-  size_t cap_ = 0, off_ = 0;
+  struct Chunk {
+    char* dev = nullptr;
+    char* host = nullptr;
+    size_t cap = 0;
+  };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0, off_ = 0;
 };
 
 struct GemmBatch {
@@ -119,6 +123,9 @@ struct H2Model {
   int64_t stack_rows = 0;
   struct MatvecPlan;
   std::unique_ptr<MatvecPlan> plan;
+  struct NearStats {
+    double bytes = 0;  // algorithmic bytes of one near-field launch
+  };
 
   H2Model();
   ~H2Model();
@@ -197,6 +204,9 @@ double* ulv_plan_z(ULVModel& U, int m);
 double* h2_plan_x(H2Model& H, int m);
 double* h2_plan_y(H2Model& H, int m);
 void h2_plan_run(H2Model& H);
+void h2_plan_run_last(H2Model& H);
+H2Model::NearStats h2_near_stats(H2Model& H, int m);
+void h2_time_near(H2Model& H, int m, int reps, double* ms, double* bytes);
 
 struct PcgResult {
   std::vector<int> iters;

@@ -54,34 +54,51 @@ void* Arena::get(size_t bytes) {
 
 // ---------------------------------------------------------------- stage --
 Stage::~Stage() {
-  if (dev_) (void)hipFree(dev_);
-  if (host_) (void)hipHostFree(host_);
+  for (Chunk& c : chunks_) {
+    if (c.dev) (void)hipFree(c.dev);
+    if (c.host) (void)hipHostFree(c.host);
+  }
 }
 
-void Stage::grow(hipStream_t s, size_t need) {
-  size_t cap = cap_ ? cap_ : (size_t(4) << 20);
-  while (cap < need) cap *= 2;
-  SPD_HIP(hipStreamSynchronize(s));
-  if (dev_) SPD_HIP(hipFree(dev_));
-  if (host_) SPD_HIP(hipHostFree(host_));
-  dev_ = nullptr;
-  host_ = nullptr;
-  SPD_HIP(hipMalloc(&dev_, cap));
-  SPD_HIP(hipHostMalloc((void**)&host_, cap, hipHostMallocDefault));
-  cap_ = cap;
+void Stage::reset() {
+  // keep only the largest chunk for reuse; the caller has synchronized
+  if (chunks_.size() > 1) {
+    size_t best = 0;
+    for (size_t i = 1; i < chunks_.size(); ++i)
+      if (chunks_[i].cap > chunks_[best].cap) best = i;
+    for (size_t i = 0; i < chunks_.size(); ++i)
+      if (i != best) {
+        (void)hipFree(chunks_[i].dev);
+        (void)hipHostFree(chunks_[i].host);
+      }
+    Chunk keep = chunks_[best];
+    chunks_.assign(1, keep);
+  }
+  cur_ = 0;
   off_ = 0;
 }
 
 void* Stage::push(hipStream_t s, const void* data, size_t bytes) {
   const size_t aligned = (bytes + 255) & ~size_t(255);
-  if (off_ + aligned > cap_) {
-    // everything already pushed must have been consumed before the buffer is
-    // replaced; grow() synchronizes the stream first
-    grow(s, std::max(aligned, cap_ * 2));
+  if (chunks_.empty() || off_ + aligned > chunks_[cur_].cap) {
+    if (!chunks_.empty() && cur_ + 1 < chunks_.size() && chunks_[cur_ + 1].cap >= aligned) {
+      ++cur_;
+    } else {
+      size_t cap = size_t(4) << 20;
+      while (cap < aligned) cap *= 2;
+      Chunk c;
+      SPD_HIP(hipMalloc(&c.dev, cap));
+      SPD_HIP(hipHostMalloc((void**)&c.host, cap, hipHostMallocDefault));
+      c.cap = cap;
+      chunks_.push_back(c);
+      cur_ = chunks_.size() - 1;
+    }
+    off_ = 0;
   }
-  std::memcpy(host_ + off_, data, bytes);
-  void* d = dev_ + off_;
-  SPD_HIP(hipMemcpyAsync(d, host_ + off_, bytes, hipMemcpyHostToDevice, s));
+  Chunk& c = chunks_[cur_];
+  std::memcpy(c.host + off_, data, bytes);
+  void* d = c.dev + off_;
+  SPD_HIP(hipMemcpyAsync(d, c.host + off_, bytes, hipMemcpyHostToDevice, s));
   off_ += aligned;
   return d;
 }

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 namespace spd {
 
@@ -208,10 +209,39 @@ void ulv_apply_tree(ULVModel& U, const double* b, double* x, int m) {
 }
 
 // ------------------------------------------------------------------ PCG --
+// One iteration (product, preconditioner sweeps, dot products, updates) is
+// captured into a HIP graph on a private stream and replayed; the host reads
+// the convergence flags every few iterations.  Columns that have converged are
+// frozen by the kernels themselves (they test the device-side active flags),
+// so iterations run past convergence change nothing and the per-column
+// iteration counters, kept on the device, stay exact.
+static constexpr int kCheckEvery = 8;
 
 PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m, double rtol,
                    int maxit) {
-  hipStream_t s = H.s;
+  hipStream_t caller = H.s;
+  hipStream_t s = nullptr;
+  SPD_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipEvent_t ev = nullptr;
+  struct Restore {
+    H2Model& H;
+    ULVModel* U;
+    hipStream_t caller, s;
+    hipEvent_t ev;
+    ~Restore() {
+      H.s = caller;
+      if (U) U->s = caller;
+      if (ev) (void)hipEventDestroy(ev);
+      if (s) (void)hipStreamDestroy(s);
+    }
+  } restore{H, U, caller, s, nullptr};
+  SPD_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  restore.ev = ev;
+  SPD_HIP(hipEventRecord(ev, caller));
+  SPD_HIP(hipStreamWaitEvent(s, ev, 0));
+  H.s = s;
+  if (U) U->s = s;
+
   const int64_t N = H.T.N;
   const size_t bytes = (size_t)N * m * sizeof(double);
   Arena a;
@@ -219,18 +249,17 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   double* z = a.get_n<double>((size_t)N * m);
   double* p = h2_plan_x(H, m);   // the product reads p in place
   double* q = h2_plan_y(H, m);   // and writes q in place
+  if (U) ulv_plan_z(*U, m);
   const int nblk = ceil_div(N, 8192);
   double* partial = a.get_n<double>((size_t)nblk * m);
   double* sc = a.get_n<double>((size_t)8 * m);
   double* rz = sc, *rzn = sc + m, *pq = sc + 2 * m, *rr = sc + 3 * m, *bb = sc + 4 * m;
-  int* active = a.get_n<int>(m + 1);
+  int* active = a.get_n<int>(2 * m + 1);
   int* any = active + m;
+  int* iters = active + m + 1;
   auto precond = [&](const double* in, double* out) {
-    if (U) {
-      ulv_apply_tree(*U, in, out, m);
-    } else {
-      SPD_HIP(hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s));
-    }
+    if (U) ulv_apply_tree(*U, in, out, m);
+    else SPD_HIP(hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s));
   };
   launch_fill(s, xt, 0.0, (int64_t)N * m);
   SPD_HIP(hipMemcpyAsync(r, bt, bytes, hipMemcpyDeviceToDevice, s));
@@ -240,28 +269,57 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   launch_coldot(s, bt, bt, N, m, N, partial, bb);
   launch_coldot(s, r, r, N, m, N, partial, rr);
   {
-    std::vector<int> ones(m, 1);
-    SPD_HIP(hipMemcpyAsync(active, ones.data(), m * sizeof(int), hipMemcpyHostToDevice, s));
+    std::vector<int> init(2 * m + 1, 0);
+    for (int c = 0; c < m; ++c) init[c] = 1;
+    SPD_HIP(hipMemcpyAsync(active, init.data(), init.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    SPD_HIP(hipStreamSynchronize(s));
   }
   launch_pcg_active(s, rr, bb, rtol, active, m, any);
-  PcgResult res;
-  res.iters.assign(m, 0);
-  std::vector<int> act(m + 1);
-  for (int it = 0; it < maxit; ++it) {
-    SPD_HIP(hipMemcpyAsync(act.data(), active, (m + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
-    SPD_HIP(hipStreamSynchronize(s));
-    if (!act[m]) break;
-    for (int c = 0; c < m; ++c) res.iters[c] += act[c];
+  auto body = [&]() {
     h2_plan_run(H);  // q = A p
     launch_coldot(s, p, q, N, m, N, partial, pq);
-    launch_pcg_update_xr(s, xt, r, p, q, rz, pq, active, N, m, N, nullptr);
+    launch_pcg_update_xr(s, xt, r, p, q, rz, pq, active, N, m, N, iters);
     launch_coldot(s, r, r, N, m, N, partial, rr);
     launch_pcg_active(s, rr, bb, rtol, active, m, any);
     precond(r, z);
     launch_coldot(s, r, z, N, m, N, partial, rzn);
     launch_pcg_update_p(s, p, z, rzn, rz, active, N, m, N);
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = getenv("SPDHSS_NO_GRAPH") == nullptr;
+  if (use_graph) {
+    SPD_HIP(hipStreamSynchronize(s));
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      body();
+      if (hipStreamEndCapture(s, &graph) != hipSuccess ||
+          hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        use_graph = false;
+      }
+    } else {
+      (void)hipGetLastError();
+      use_graph = false;
+    }
   }
-  SPD_HIP(hipMemcpyAsync(act.data(), active, (m + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+  int h_any = 1;
+  int done = 0;
+  while (done < maxit) {
+    SPD_HIP(hipMemcpyAsync(&h_any, any, sizeof(int), hipMemcpyDeviceToHost, s));
+    SPD_HIP(hipStreamSynchronize(s));
+    if (!h_any) break;
+    const int chunk = std::min(kCheckEvery, maxit - done);
+    for (int c = 0; c < chunk; ++c) {
+      if (use_graph) SPD_HIP(hipGraphLaunch(exec, s));
+      else body();
+    }
+    done += chunk;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  PcgResult res;
+  std::vector<int> act(2 * m + 1);
+  SPD_HIP(hipMemcpyAsync(act.data(), active, act.size() * sizeof(int), hipMemcpyDeviceToHost, s));
   // true residual
   SPD_HIP(hipMemcpyAsync(p, xt, bytes, hipMemcpyDeviceToDevice, s));
   h2_plan_run(H);
@@ -272,12 +330,35 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   SPD_HIP(hipMemcpyAsync(hrr.data(), rr, m * sizeof(double), hipMemcpyDeviceToHost, s));
   SPD_HIP(hipMemcpyAsync(hbb.data(), bb, m * sizeof(double), hipMemcpyDeviceToHost, s));
   SPD_HIP(hipStreamSynchronize(s));
+  res.iters.assign(act.begin() + m + 1, act.end());
   res.relres.resize(m);
   for (int c = 0; c < m; ++c) {
     res.relres[c] = hbb[c] > 0 ? std::sqrt(hrr[c] / hbb[c]) : std::sqrt(hrr[c]);
     if (act[c]) res.converged = false;
   }
   return res;
+}
+
+// Time the dominant kernel of the product (the leaf-level near-field pass)
+// with HIP events on the stream it runs on.
+void h2_time_near(H2Model& H, int m, int reps, double* ms, double* bytes) {
+  double* x = h2_plan_x(H, m);
+  (void)x;
+  H2Model::NearStats st = h2_near_stats(H, m);
+  hipEvent_t e0, e1;
+  SPD_HIP(hipEventCreate(&e0));
+  SPD_HIP(hipEventCreate(&e1));
+  h2_plan_run_last(H);  // warm
+  SPD_HIP(hipEventRecord(e0, H.s));
+  for (int i = 0; i < reps; ++i) h2_plan_run_last(H);
+  SPD_HIP(hipEventRecord(e1, H.s));
+  SPD_HIP(hipEventSynchronize(e1));
+  float t = 0;
+  SPD_HIP(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = t / reps;
+  *bytes = st.bytes;
 }
 
 }  // namespace spd

@@ -39,6 +39,11 @@ CASES = {
                                             kernel="exponential", ell=0.2, shift=1e-2, leaf=40,
                                             max_rank=30, hss_tol=1e-3, seed_base=8),
                     shells=6, per_shell=96),
+    # deep tree (12 levels, 2,048 leaves of 9/10 points): exercises the level
+    # recursions far beyond the shallow cases
+    "deep20000": dict(w=workloads.SMALL.with_(name="gaussian-l0.2-N20000-deep", n=20000, ell=0.2, shift=1e-1,
+                                              leaf=10, max_rank=30, hss_tol=1e-1, seed_base=10),
+                      shells=4, per_shell=64, pcg_maxit=60),
     # inverse multiquadric, fixed-rank form (tol = 0)
     "imq1200": dict(w=workloads.SMALL.with_(name="imq-c0.1-N1200", n=1200, kernel="imq", ell=0.1,
                                             shift=1e-3, leaf=30, max_rank=20, hss_tol=0.0, seed_base=9),
@@ -58,7 +63,7 @@ class Pair:
         c = CASES[name]
         w = c["w"]
         print(f"\n[parity] case {name}: N={w.n} kernel={w.kernel}", flush=True)
-        self.w, self.B = w, B
+        self.w, self.B, self.name = w, B, name
         X = w.points()
         self.X = X
         self.o_h2 = OH2(X, w.kernel, w.ell, w.shift, w.leaf, w.h2_tol, eta=w.eta,
@@ -166,11 +171,17 @@ def test_pcg_fixed_iterations(P):
 
 
 def test_pcg_converges_like_oracle(P):
+    """Same stopping behaviour as the oracle: equal iteration counts (within one
+    for rounding at the threshold) and, when the oracle converges, a true
+    residual at the tolerance."""
     b = P.w.rhs()
     bg = P.B.cols_like(P.w.n, b.shape[1], "cuda").copy_(torch.from_numpy(b))
-    x, it, res = P.B.pcg_solve(P.g_h2, P.g_ulv, bg, rtol=P.w.pcg_tol, maxit=500)
-    _, ito, reso = opcg(P.o_h2.matvec, P.o_hss.solve, b[P.T.perm], P.w.pcg_tol, 500)
+    maxit = CASES[P.name].get("pcg_maxit", 500)
+    x, it, res = P.B.pcg_solve(P.g_h2, P.g_ulv, bg, rtol=P.w.pcg_tol, maxit=maxit,
+                               raise_on_nonconvergence=False)
+    _, ito, reso = opcg(P.o_h2.matvec, P.o_hss.solve, b[P.T.perm], P.w.pcg_tol, maxit)
     assert np.abs(it - ito).max() <= 1
-    assert (res <= 2 * P.w.pcg_tol).all()
-    print(f"[parity] iterations gpu={it.tolist()} oracle={ito.tolist()} relres={res.tolist()}",
-          flush=True)
+    if (ito < maxit).all():
+        assert (res <= 2 * P.w.pcg_tol).all()
+    print(f"[parity] iterations gpu={it.tolist()} oracle={ito.tolist()} relres={res.tolist()} "
+          f"oracle relres={reso.tolist()}", flush=True)
