@@ -189,6 +189,15 @@ spd_status spd_hss_query_get(spd_hss_t M, int32_t what, int32_t node,
 spd_status spd_h2_time_near(spd_h2_t A, int32_t nrhs, int32_t reps, void* stream, double* ms,
                             double* bytes);
 
+/* Time each kernel launch of h2_matvec for nrhs columns separately, in the
+ * order the product issues them (upward levels, coupling, downward levels,
+ * leaf pass): reps launches each, bracketed by HIP events on `stream`.
+ * ms[i], bytes[i] (HOST arrays of cap entries): average milliseconds and
+ * algorithmic bytes (every A operand once, every distinct B operand once, C
+ * once) of launch i; *count = number of launches written. */
+spd_status spd_h2_time_launches(spd_h2_t A, int32_t nrhs, int32_t reps, void* stream, double* ms,
+                                double* bytes, int32_t cap, int32_t* count);
+
 /* ---- kernel test hooks: run one batched device kernel on caller buffers.
  * All pointers are DEVICE pointers; shapes are uniform across the batch.
  * They exist so that each kernel can be compared on its own against the

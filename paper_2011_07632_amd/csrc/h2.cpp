@@ -362,4 +362,31 @@ H2Model::NearStats h2_near_stats(H2Model& H, int m) {
   return st;
 }
 
+// Time every launch of the product separately (HIP events on the product's
+// stream); returns the number of launches written.
+int h2_time_launches(H2Model& H, int m, int reps, double* ms, double* bytes, int cap) {
+  h2_plan_x(H, m);
+  const auto& recs = H.plan->rec.recs;
+  hipEvent_t e0, e1;
+  SPD_HIP(hipEventCreate(&e0));
+  SPD_HIP(hipEventCreate(&e1));
+  const int n = std::min<int>((int)recs.size(), cap);
+  for (int i = 0; i < n; ++i) {
+    Recorder one;
+    one.recs.push_back(recs[i]);
+    one.replay(H.s);
+    SPD_HIP(hipEventRecord(e0, H.s));
+    for (int r = 0; r < reps; ++r) one.replay(H.s);
+    SPD_HIP(hipEventRecord(e1, H.s));
+    SPD_HIP(hipEventSynchronize(e1));
+    float t = 0;
+    SPD_HIP(hipEventElapsedTime(&t, e0, e1));
+    ms[i] = t / reps;
+    bytes[i] = recs[i].bytes;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return n;
+}
+
 }  // namespace spd

@@ -127,13 +127,90 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem* __restrict__ pr
       }
 }
 
+// Skinny grouped GEMM for at most 16 right-hand columns: bandwidth-bound
+// streaming of A.  A workgroup owns 64 rows of one problem; lane l owns row
+// i0 + l, and the four waves split every term's inner dimension into four
+// contiguous quarters.  The quarters are summed in wave order through LDS, so
+// results are deterministic.  B entries are the same for all lanes of a wave.
+template <int NC>
+__global__ __launch_bounds__(256) void k_gemm_skinny(const GemmProblem* __restrict__ probs,
+                                                     const GemmTerm* __restrict__ terms,
+                                                     int tiles_max, int transA, int transB) {
+  __shared__ double red[3][64][NC];
+  const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
+  const GemmProblem P = probs[p];
+  const int tm = (P.m + 63) / 64;
+  if (tile >= tm) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = tile * 64 + lane;
+  const bool rowok = row < P.m;
+  const int n = P.n;
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  for (int t = P.term_begin; t < P.term_end; ++t) {
+    const GemmTerm T = terms[t];
+    const int q = (T.k + 3) / 4;
+    const int k0 = w * q, k1 = min(T.k, k0 + q);
+    const double* __restrict__ A = T.A;
+    const double* __restrict__ B = T.B;
+    const int64_t lda = T.lda, ldb = T.ldb;
+    const double sc = T.scale;
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
+      double a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        a[u] = rowok ? (transA ? A[(k + u) + row * lda] : A[row + (k + u) * lda]) : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double av = sc * a[u];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (c < n) acc[c] += av * (transB ? B[c + (k + u) * ldb] : B[(k + u) + c * ldb]);
+      }
+    }
+    for (; k < k1; ++k) {
+      const double av = rowok ? sc * (transA ? A[k + row * lda] : A[row + k * lda]) : 0.0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (c < n) acc[c] += av * (transB ? B[c + k * ldb] : B[k + c * ldb]);
+    }
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) red[w - 1][lane][c] = acc[c];
+  }
+  __syncthreads();
+  if (w == 0 && rowok) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (c >= n) continue;
+      const double v = ((acc[c] + red[0][lane][c]) + red[1][lane][c]) + red[2][lane][c];
+      double* cp = P.C + row + (int64_t)c * P.ldc;
+      double val = P.alpha * v;
+      if (P.beta != 0.0) val += P.beta * (*cp);
+      *cp = val;
+    }
+  }
+}
+
 void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
                  int max_m, int max_n, int transA, int transB) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
   if (max_n <= 16) {
-    const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 16);
-    hipLaunchKernelGGL((k_gemm<64, 16, 16, 16>), dim3((unsigned)nprob * tiles), dim3(256), 0, s,
-                       d_p, d_t, tiles, transA, transB);
+    const int tiles = ceil_div(max_m, 64);
+    const dim3 grid((unsigned)nprob * tiles);
+    if (max_n == 1)
+      hipLaunchKernelGGL((k_gemm_skinny<1>), grid, dim3(256), 0, s, d_p, d_t, tiles, transA, transB);
+    else if (max_n <= 2)
+      hipLaunchKernelGGL((k_gemm_skinny<2>), grid, dim3(256), 0, s, d_p, d_t, tiles, transA, transB);
+    else if (max_n <= 4)
+      hipLaunchKernelGGL((k_gemm_skinny<4>), grid, dim3(256), 0, s, d_p, d_t, tiles, transA, transB);
+    else if (max_n <= 8)
+      hipLaunchKernelGGL((k_gemm_skinny<8>), grid, dim3(256), 0, s, d_p, d_t, tiles, transA, transB);
+    else
+      hipLaunchKernelGGL((k_gemm_skinny<16>), grid, dim3(256), 0, s, d_p, d_t, tiles, transA, transB);
   } else if (max_n <= 32) {
     const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 32);
     hipLaunchKernelGGL((k_gemm<64, 32, 32, 16>), dim3((unsigned)nprob * tiles), dim3(256), 0, s,

@@ -88,6 +88,7 @@ struct LaunchRec {
   const void* probs;
   const void* terms;
   int nprob, max_m, max_n, transA, transB;
+  double bytes;  // algorithmic bytes: every A operand once, distinct B operands once, C once
 };
 struct Recorder {
   std::vector<LaunchRec> recs;
@@ -156,7 +157,9 @@ struct Factors {
   std::vector<double*> S; // leaf Cholesky factors S_v (n_v x n_v)
   std::vector<double*> V; // V_v (leaf, n_v x r_v) or V-bar_v (rho_v x r_v)
   std::vector<double*> F; // factor of I + bold B_v (rho_v x rho_v), nonleaf incl. root
+  std::vector<double*> Sinv, Finv;  // explicit inverses of S_v and F_v (lower)
   bool root_factored = false;
+  bool inverted = false;
   // stacked rank-space layout: the children of p share a rho_p-row buffer
   std::vector<int64_t> par_off;
   int64_t stack_rows = 0;
@@ -207,6 +210,7 @@ void h2_plan_run(H2Model& H);
 void h2_plan_run_last(H2Model& H);
 H2Model::NearStats h2_near_stats(H2Model& H, int m);
 void h2_time_near(H2Model& H, int m, int reps, double* ms, double* bytes);
+int h2_time_launches(H2Model& H, int m, int reps, double* ms, double* bytes, int cap);
 
 struct PcgResult {
   std::vector<int> iters;

@@ -2,7 +2,9 @@
 // builders and error bookkeeping.
 #include "model.h"
 
+#include <algorithm>
 #include <chrono>
+#include <unordered_set>
 #include <cstring>
 
 namespace spd {
@@ -204,8 +206,18 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
   if (b.probs.empty() || b.max_m == 0 || b.max_n == 0) return;
   std::vector<GemmTerm> t = b.terms;
   if (t.empty()) t.push_back(GemmTerm{});
+  double bytes = 0;
+  std::unordered_set<const double*> seen;
+  for (const GemmProblem& p : b.probs) {
+    bytes += 8.0 * p.m * p.n * (p.beta != 0.0 ? 2.0 : 1.0);
+    for (int q = p.term_begin; q < p.term_end; ++q) {
+      const GemmTerm& g = b.terms[q];
+      bytes += 8.0 * p.m * g.k;                            // every A operand once
+      if (seen.insert(g.B).second) bytes += 8.0 * g.k * p.n;  // distinct B operands once
+    }
+  }
   recs.push_back({0, keep(a, s, b.probs), keep(a, s, t), (int)b.probs.size(), b.max_m, b.max_n,
-                  b.transA, b.transB});
+                  b.transA, b.transB, bytes});
 }
 
 void Recorder::block(Arena& a, hipStream_t s, const BlockBatch& b) {
@@ -213,13 +225,13 @@ void Recorder::block(Arena& a, hipStream_t s, const BlockBatch& b) {
   std::vector<BlockTerm> t = b.terms;
   if (t.empty()) t.push_back(BlockTerm{});
   recs.push_back({1, keep(a, s, b.probs), keep(a, s, t), (int)b.probs.size(), b.max_m, b.max_n, 0,
-                  0});
+                  0, 0.0});
 }
 
 void Recorder::trsm(Arena& a, hipStream_t s, const TrsmBatch& b, int trans) {
   if (b.probs.empty()) return;
   recs.push_back({2, keep(a, s, b.probs), nullptr, (int)b.probs.size(), b.max_n, b.max_nrhs, trans,
-                  0});
+                  0, 0.0});
 }
 
 void Recorder::replay(hipStream_t s) const {

@@ -34,6 +34,33 @@ struct ULVModel::ApplyPlan {
 ULVModel::ULVModel() = default;
 ULVModel::~ULVModel() = default;
 
+// Explicit inverses of the triangular factors (S_v at the leaves, F_v above),
+// formed once by triangular solves against the identity, so that every sweep
+// of the solve is a batched product.
+static void invert_factors(Factors& F, Stage& st, hipStream_t s) {
+  if (F.inverted) return;
+  const TreeHost& T = F.T;
+  F.Sinv.assign(T.nnodes, nullptr);
+  F.Finv.assign(T.nnodes, nullptr);
+  BlockBatch eye;
+  TrsmBatch tb;
+  for (int v = 0; v < T.nnodes; ++v) {
+    const bool leaf = T.is_leaf(v);
+    const double* L = leaf ? F.S[v] : F.F[v];
+    const int n = F.rho[v];
+    if (!L || n <= 0) continue;
+    double* X = F.arena.get_n<double>((size_t)n * n);
+    (leaf ? F.Sinv : F.Finv)[v] = X;
+    eye.add(X, n, n, n, 0.0, 1);
+    tb.add(L, n, X, n, n, n);
+  }
+  eye.run(s, st);
+  tb.run(s, st, 0);
+  SPD_HIP(hipStreamSynchronize(s));
+  st.reset();
+  F.inverted = true;
+}
+
 void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
   U.f = M.f;
   U.s = s;
@@ -41,6 +68,7 @@ void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
   const TreeHost& T = F.T;
   if (T.L == 1 || F.root_factored) {
     F.root_factored = true;
+    invert_factors(F, U.stage, s);
     return;
   }
   const int c1 = 1, c2 = 2, r1 = F.r[c1], r2 = F.r[c2], rv = r1 + r2;
@@ -74,6 +102,7 @@ void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
   }
   SPD_HIP(hipStreamSynchronize(s));
   F.root_factored = true;
+  invert_factors(F, U.stage, s);
 }
 
 static void build_apply_plan(ULVModel& U, int m) {
@@ -87,12 +116,17 @@ static void build_apply_plan(ULVModel& U, int m) {
   Arena& a = pl->arena;
   Recorder& rec = pl->rec;
   pl->z = a.get_n<double>((size_t)N * m);
+  double* z2 = a.get_n<double>((size_t)N * m);
   const int lf = T.first_at(1), lc = T.count_at(1);
+  const int Ni = (int)N;
   if (L == 1) {
-    TrsmBatch tb;
-    tb.add(F.S[0], (int)N, pl->z, (int)N, (int)N, m);
-    rec.trsm(a, s, tb, 0);
-    rec.trsm(a, s, tb, 1);
+    GemmBatch g1(0, 0), g2(1, 0);
+    g1.add(z2, Ni, m, Ni);
+    g1.term(F.Sinv[0], Ni, pl->z, Ni, Ni);
+    g2.add(pl->z, Ni, m, Ni);
+    g2.term(F.Sinv[0], Ni, z2, Ni, Ni);
+    rec.gemm(a, s, g1);
+    rec.gemm(a, s, g2);
     SPD_HIP(hipStreamSynchronize(s));
     U.plan = std::move(pl);
     return;
@@ -101,90 +135,82 @@ static void build_apply_plan(ULVModel& U, int m) {
   pl->ts = a.get_n<double>((size_t)rows * m);
   pl->ws = a.get_n<double>((size_t)rows * m);
   pl->u.assign(nn, nullptr);
-  // leaves: z = S^{-1} b ; t = V^T z
+  double* rt = a.get_n<double>((size_t)std::max(F.rho[0], 1) * m);
+  // leaves: z2 = S^{-1} b ; t = V^T z2
   {
-    TrsmBatch tb;
-    GemmBatch g(1, 0);
+    GemmBatch g1(0, 0), g2(1, 0);
     for (int v = lf; v < lf + lc; ++v) {
       const int nv = F.rho[v];
-      tb.add(F.S[v], nv, pl->z + T.start[v], (int)N, nv, m);
+      g1.add(z2 + T.start[v], nv, m, Ni);
+      g1.term(F.Sinv[v], nv, pl->z + T.start[v], Ni, nv);
       if (F.r[v] == 0) continue;
-      g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
-      g.term(F.V[v], nv, pl->z + T.start[v], (int)N, nv);
+      g2.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
+      g2.term(F.V[v], nv, z2 + T.start[v], Ni, nv);
     }
-    rec.trsm(a, s, tb, 0);
-    rec.gemm(a, s, g);
+    rec.gemm(a, s, g1);
+    rec.gemm(a, s, g2);
   }
   // upward: u = F^{-1} [t_c] ; t = V-bar^T u
   for (int lev = 2; lev <= L - 1; ++lev) {
-    BlockBatch cp;
-    TrsmBatch tb;
-    GemmBatch g(1, 0);
+    GemmBatch g1(0, 0), g2(1, 0);
     for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
       const int rv = F.rho[v];
       pl->u[v] = a.get_n<double>((size_t)std::max(rv, 1) * m);
       if (rv == 0) continue;
-      cp.add(pl->u[v], rv, m, rv);
-      cp.term(pl->ts + F.par_off[v] * m, rv);
-      tb.add(F.F[v], rv, pl->u[v], rv, rv, m);
+      g1.add(pl->u[v], rv, m, rv);
+      g1.term(F.Finv[v], rv, pl->ts + F.par_off[v] * m, rv, rv);
       if (F.r[v] == 0) continue;
-      g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
-      g.term(F.V[v], rv, pl->u[v], rv, rv);
+      g2.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
+      g2.term(F.V[v], rv, pl->u[v], rv, rv);
     }
-    rec.block(a, s, cp);
-    rec.trsm(a, s, tb, 0);
-    rec.gemm(a, s, g);
+    rec.gemm(a, s, g1);
+    rec.gemm(a, s, g2);
   }
   // root: w = F_root^{-T} F_root^{-1} [t_c]
   {
     const int rv = F.rho[0];
     if (rv > 0) {
-      BlockBatch cp;
-      cp.add(pl->ws + F.par_off[0] * m, rv, m, rv);
-      cp.term(pl->ts + F.par_off[0] * m, rv);
-      rec.block(a, s, cp);
-      TrsmBatch tb;
-      tb.add(F.F[0], rv, pl->ws + F.par_off[0] * m, rv, rv, m);
-      rec.trsm(a, s, tb, 0);
-      rec.trsm(a, s, tb, 1);
+      GemmBatch g1(0, 0), g2(1, 0);
+      g1.add(rt, rv, m, rv);
+      g1.term(F.Finv[0], rv, pl->ts + F.par_off[0] * m, rv, rv);
+      g2.add(pl->ws + F.par_off[0] * m, rv, m, rv);
+      g2.term(F.Finv[0], rv, rt, rv, rv);
+      rec.gemm(a, s, g1);
+      rec.gemm(a, s, g2);
     }
   }
   // downward: u += V-bar (w - t) ; [w_c] = F^{-T} u
   for (int lev = L - 1; lev >= 2; --lev) {
-    GemmBatch g(0, 0);
-    BlockBatch cp;
-    TrsmBatch tb;
+    GemmBatch g1(0, 0), g2(1, 0);
     for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
       const int rv = F.rho[v];
       if (rv == 0) continue;
       if (F.r[v] > 0) {
-        g.add(pl->u[v], rv, m, rv, 1.0);
-        g.term(F.V[v], rv, F.blk(pl->ws, v, m), F.blk_ld(v), F.r[v], 1.0);
-        g.term(F.V[v], rv, F.blk(pl->ts, v, m), F.blk_ld(v), F.r[v], -1.0);
+        g1.add(pl->u[v], rv, m, rv, 1.0);
+        g1.term(F.V[v], rv, F.blk(pl->ws, v, m), F.blk_ld(v), F.r[v], 1.0);
+        g1.term(F.V[v], rv, F.blk(pl->ts, v, m), F.blk_ld(v), F.r[v], -1.0);
       }
-      cp.add(pl->ws + F.par_off[v] * m, rv, m, rv);
-      cp.term(pl->u[v], rv);
-      tb.add(F.F[v], rv, pl->ws + F.par_off[v] * m, rv, rv, m);
+      g2.add(pl->ws + F.par_off[v] * m, rv, m, rv);
+      g2.term(F.Finv[v], rv, pl->u[v], rv, rv);
     }
-    rec.gemm(a, s, g);
-    rec.block(a, s, cp);
-    rec.trsm(a, s, tb, 1);
+    rec.gemm(a, s, g1);
+    rec.gemm(a, s, g2);
   }
-  // leaves: z += V (w - t) ; x = S^{-T} z
+  // leaves: z2 += V (w - t) ; x = S^{-T} z2
   {
-    GemmBatch g(0, 0);
-    TrsmBatch tb;
+    GemmBatch g1(0, 0), g2(1, 0);
     for (int v = lf; v < lf + lc; ++v) {
       const int nv = F.rho[v];
       if (F.r[v] > 0) {
-        g.add(pl->z + T.start[v], nv, m, (int)N, 1.0);
-        g.term(F.V[v], nv, F.blk(pl->ws, v, m), F.blk_ld(v), F.r[v], 1.0);
-        g.term(F.V[v], nv, F.blk(pl->ts, v, m), F.blk_ld(v), F.r[v], -1.0);
+        g1.add(z2 + T.start[v], nv, m, Ni, 1.0);
+        g1.term(F.V[v], nv, F.blk(pl->ws, v, m), F.blk_ld(v), F.r[v], 1.0);
+        g1.term(F.V[v], nv, F.blk(pl->ts, v, m), F.blk_ld(v), F.r[v], -1.0);
       }
-      tb.add(F.S[v], nv, pl->z + T.start[v], (int)N, nv, m);
+      g2.add(pl->z + T.start[v], nv, m, Ni);
+      g2.term(F.Sinv[v], nv, z2 + T.start[v], Ni, nv);
     }
-    rec.gemm(a, s, g);
-    rec.trsm(a, s, tb, 1);
+    rec.gemm(a, s, g1);
+    rec.gemm(a, s, g2);
   }
   SPD_HIP(hipStreamSynchronize(s));
   U.plan = std::move(pl);
