@@ -190,13 +190,15 @@ spd_status spd_h2_time_near(spd_h2_t A, int32_t nrhs, int32_t reps, void* stream
                             double* bytes);
 
 /* Time each kernel launch of h2_matvec for nrhs columns separately, in the
- * order the product issues them (upward levels, coupling, downward levels,
- * leaf pass): reps launches each, bracketed by HIP events on `stream`.
- * ms[i], bytes[i] (HOST arrays of cap entries): average milliseconds and
- * algorithmic bytes (every A operand once, every distinct B operand once, C
- * once) of launch i; *count = number of launches written. */
+ * order the product issues them: reps launches each, bracketed by HIP events
+ * on `stream`.  ms[i], bytes[i], tags[i] (HOST arrays of cap entries; tags may
+ * be NULL): average milliseconds, algorithmic bytes (every A operand once,
+ * every distinct B operand once, C once; 0 for the partial-sum reductions
+ * that follow a split product) and pass of launch i: 100 + l upward pass at
+ * level l, 200 coupling pass, 300 + l downward pass at level l, 400 leaf pass
+ * (near field and leaf bases).  *count = number of launches written. */
 spd_status spd_h2_time_launches(spd_h2_t A, int32_t nrhs, int32_t reps, void* stream, double* ms,
-                                double* bytes, int32_t cap, int32_t* count);
+                                double* bytes, int32_t* tags, int32_t cap, int32_t* count);
 
 /* ---- kernel test hooks: run one batched device kernel on caller buffers.
  * All pointers are DEVICE pointers; shapes are uniform across the batch.

@@ -64,7 +64,7 @@ def _load():
         "spd_h2_query_get": [vp, i32, vp, i64],
         "spd_hss_query_get": [vp, i32, i32, i32, vp, i64],
         "spd_h2_time_near": [vp, i32, i32, vp, vp, vp],
-        "spd_h2_time_launches": [vp, i32, i32, vp, vp, vp, i32, vp],
+        "spd_h2_time_launches": [vp, i32, i32, vp, vp, vp, vp, i32, vp],
         "spd_test_gemm": [vp, vp, vp, i32, i32, i32, i32, i32, i32, dbl, dbl, vp],
         "spd_test_chol": [vp, i32, i32, vp, vp],
         "spd_test_trsm": [vp, vp, i32, i32, i32, i32, i32, vp],
@@ -344,15 +344,25 @@ def near_field_roofline(A: H2Matrix, nrhs: int, reps: int = 20, stream=None) -> 
 
 
 def product_launch_times(A: H2Matrix, nrhs: int, reps: int = 10, stream=None) -> list[dict]:
-    """Per-launch average time and algorithmic bytes of h2_matvec, in issue order."""
-    cap = 256
+    """Per-launch average time, algorithmic bytes and pass of h2_matvec, in issue order."""
+    cap = 512
     ms = np.zeros(cap)
     by = np.zeros(cap)
+    tg = np.zeros(cap, dtype=np.int32)
     cnt = C.c_int32()
     _check(lib.spd_h2_time_launches(A._h, int(nrhs), int(reps), _stream(stream), ms.ctypes.data,
-                                    by.ctypes.data, cap, C.byref(cnt)))
-    return [{"index": i, "ms": float(ms[i]), "bytes": float(by[i]),
-             "gbs": float(by[i] / (ms[i] * 1e-3) / 1e9) if ms[i] > 0 else 0.0} for i in range(cnt.value)]
+                                    by.ctypes.data, tg.ctypes.data, cap, C.byref(cnt)))
+    out = []
+    for i in range(cnt.value):
+        t = int(tg[i])
+        name = {2: "coupling", 4: "leaf pass"}.get(t // 100, "")
+        if t // 100 == 1:
+            name = f"upward level {t % 100}"
+        elif t // 100 == 3:
+            name = f"downward level {t % 100}"
+        out.append({"index": i, "pass": name or f"launch {i}", "ms": float(ms[i]), "bytes": float(by[i]),
+                    "gbs": float(by[i] / (ms[i] * 1e-3) / 1e9) if ms[i] > 0 else 0.0})
+    return out
 
 
 # ------------------------------------------------------------------ kernel hooks --

@@ -174,12 +174,12 @@ spd_status spd_h2_time_near(spd_h2_t A, int32_t nrhs, int32_t reps, void* stream
 }
 
 spd_status spd_h2_time_launches(spd_h2_t A, int32_t nrhs, int32_t reps, void* stream, double* ms,
-                                double* bytes, int32_t cap, int32_t* count) {
+                                double* bytes, int32_t* tags, int32_t cap, int32_t* count) {
   SPD_API_BEGIN
   SPD_REQUIRE(A && ms && bytes && count && nrhs >= 1 && reps >= 1 && cap >= 1, SPD_E_INVALID,
               "bad args");
   A->m.s = as_stream(stream);
-  *count = h2_time_launches(A->m, nrhs, reps, ms, bytes, cap);
+  *count = h2_time_launches(A->m, nrhs, reps, ms, bytes, tags, cap);
   SPD_API_END
 }
 

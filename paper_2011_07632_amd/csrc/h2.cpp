@@ -175,6 +175,20 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
       H.cand_h[p] = std::move(cc);
     }
   }
+  // W_v^T for the upward pass
+  H.WT.assign(nn, nullptr);
+  {
+    BlockBatch tr;
+    for (int v = 1; v < nn; ++v) {
+      if (H.k[v] == 0 || H.cand[v] == 0) continue;
+      H.WT[v] = H.arena.get_n<double>((size_t)H.k[v] * H.cand[v]);
+      tr.add(H.WT[v], H.k[v], H.cand[v], H.k[v]);
+      tr.term(H.W[v], H.cand[v], 1.0, 1);
+    }
+    tr.run(s, st);
+    SPD_HIP(hipStreamSynchronize(s));
+    st.reset();
+  }
   const double t2 = now_seconds();
 
   // coupling blocks B_ij = K(skel_i, skel_j) and dense near blocks
@@ -259,16 +273,18 @@ static void build_plan(H2Model& H, int m) {
   if (L > 1) {
     // upward: x-hat_v = W_v^T x_v (leaf) or W_v^T [x-hat_c1; x-hat_c2]
     for (int lev = 1; lev < L; ++lev) {
-      GemmBatch g(1, 0);
+      GemmBatch g(0, 0);
       for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
         if (H.k[v] == 0) continue;
         g.add(H.hat(pl->xh, v, m), H.k[v], m, H.hat_ld(v));
         if (lev == 1)
-          g.term(H.W[v], H.cand[v], pl->xt + T.start[v], (int)N, H.cand[v]);
+          g.term(H.WT[v], H.k[v], pl->xt + T.start[v], (int)N, H.cand[v]);
         else
-          g.term(H.W[v], H.cand[v], pl->xh + H.par_off[v] * m, H.cand[v], H.cand[v]);
+          g.term(H.WT[v], H.k[v], pl->xh + H.par_off[v] * m, H.cand[v], H.cand[v]);
       }
+      const size_t first = rec.recs.size();
       rec.gemm(a, s, g);
+      rec.tag_from(first, 100 + lev);
     }
     // coupling: y-hat_v = sum_j B_vj x-hat_j
     {
@@ -282,7 +298,9 @@ static void build_plan(H2Model& H, int m) {
           g.term(H.Bh[e], H.k[v], H.hat(pl->xh, j, m), H.hat_ld(j), H.k[j]);
         }
       }
+      const size_t first = rec.recs.size();
       rec.gemm(a, s, g);
+      rec.tag_from(first, 200);
     }
     // downward: [y-hat_c1; y-hat_c2] += W_v y-hat_v
     for (int lev = L - 1; lev >= 2; --lev) {
@@ -292,7 +310,9 @@ static void build_plan(H2Model& H, int m) {
         g.add(pl->yh + H.par_off[v] * m, H.cand[v], m, H.cand[v], 1.0);
         g.term(H.W[v], H.cand[v], H.hat(pl->yh, v, m), H.hat_ld(v), H.k[v]);
       }
+      const size_t first = rec.recs.size();
       rec.gemm(a, s, g);
+      rec.tag_from(first, 300 + lev);
     }
   }
   // leaves: y_v = W_v y-hat_v + sum_{j near v} A_vj x_j
@@ -306,7 +326,9 @@ static void build_plan(H2Model& H, int m) {
         g.term(H.nearA[e], (int)T.size(v), pl->xt + T.start[j], (int)N, (int)T.size(j));
       }
     }
+    const size_t first = rec.recs.size();
     rec.gemm(a, s, g);
+    rec.tag_from(first, 400);
   }
   SPD_HIP(hipStreamSynchronize(s));
   H.plan = std::move(pl);
@@ -342,7 +364,8 @@ void h2_plan_run(H2Model& H) { H.plan->rec.replay(H.s); }
 // the last recorded launch of the product is the leaf pass: y = U y-hat + near
 void h2_plan_run_last(H2Model& H) {
   Recorder one;
-  one.recs.push_back(H.plan->rec.recs.back());
+  for (const LaunchRec& r : H.plan->rec.recs)
+    if (r.tag == 400) one.recs.push_back(r);
   one.replay(H.s);
 }
 
@@ -364,7 +387,7 @@ H2Model::NearStats h2_near_stats(H2Model& H, int m) {
 
 // Time every launch of the product separately (HIP events on the product's
 // stream); returns the number of launches written.
-int h2_time_launches(H2Model& H, int m, int reps, double* ms, double* bytes, int cap) {
+int h2_time_launches(H2Model& H, int m, int reps, double* ms, double* bytes, int* tags, int cap) {
   h2_plan_x(H, m);
   const auto& recs = H.plan->rec.recs;
   hipEvent_t e0, e1;
@@ -383,6 +406,7 @@ int h2_time_launches(H2Model& H, int m, int reps, double* ms, double* bytes, int
     SPD_HIP(hipEventElapsedTime(&t, e0, e1));
     ms[i] = t / reps;
     bytes[i] = recs[i].bytes;
+    if (tags) tags[i] = recs[i].tag;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

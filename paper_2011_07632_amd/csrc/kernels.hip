@@ -128,20 +128,24 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem* __restrict__ pr
 }
 
 // Skinny grouped GEMM for at most 16 right-hand columns: bandwidth-bound
-// streaming of A.  A workgroup owns 64 rows of one problem; lane l owns row
-// i0 + l, and the four waves split every term's inner dimension into four
-// contiguous quarters.  The quarters are summed in wave order through LDS, so
-// results are deterministic.  B entries are the same for all lanes of a wave.
+// streaming of A.  A workgroup owns 64 rows of one problem (lane l owns row
+// i0 + l) and the four waves split every term's inner dimension into four
+// contiguous quarters; the quarters are summed in wave order through LDS, so
+// results are deterministic.  The wave index is made wave-uniform so that the
+// B entries, the same for every lane, come from scalar loads.  Long term
+// lists are split into several problems by the host (see Recorder::gemm).
 template <int NC>
 __global__ __launch_bounds__(256) void k_gemm_skinny(const GemmProblem* __restrict__ probs,
                                                      const GemmTerm* __restrict__ terms,
                                                      int tiles_max, int transA, int transB) {
+  constexpr int U = 8;
   __shared__ double red[3][64][NC];
   const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
   const GemmProblem P = probs[p];
   const int tm = (P.m + 63) / 64;
   if (tile >= tm) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row = tile * 64 + lane;
   const bool rowok = row < P.m;
   const int n = P.n;
@@ -152,29 +156,38 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(const GemmProblem* __restri
     const GemmTerm T = terms[t];
     const int q = (T.k + 3) / 4;
     const int k0 = w * q, k1 = min(T.k, k0 + q);
-    const double* __restrict__ A = T.A;
-    const double* __restrict__ B = T.B;
+    if (k0 >= k1) continue;
     const int64_t lda = T.lda, ldb = T.ldb;
     const double sc = T.scale;
+    // A walks down a column (no transpose) or along a row (transpose)
+    const int64_t astep = transA ? 1 : lda;
+    const double* __restrict__ ap =
+        T.A + (transA ? (int64_t)k0 + (int64_t)(rowok ? row : 0) * lda : (int64_t)(rowok ? row : 0) + k0 * lda);
+    const int64_t bstep = transB ? ldb : 1;
+    const int64_t bcol = transB ? 1 : ldb;
+    const double* __restrict__ bp = T.B + (transB ? (int64_t)k0 * ldb : (int64_t)k0);
     int k = k0;
-    for (; k + 4 <= k1; k += 4) {
-      double a[4];
+    for (; k + U <= k1; k += U) {
+      double a[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        a[u] = rowok ? (transA ? A[(k + u) + row * lda] : A[row + (k + u) * lda]) : 0.0;
+      for (int u = 0; u < U; ++u) a[u] = rowok ? ap[u * astep] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         const double av = sc * a[u];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-          if (c < n) acc[c] += av * (transB ? B[c + (k + u) * ldb] : B[(k + u) + c * ldb]);
+          if (c < n) acc[c] += av * bp[u * bstep + c * bcol];
       }
+      ap += U * astep;
+      bp += U * bstep;
     }
     for (; k < k1; ++k) {
-      const double av = rowok ? sc * (transA ? A[k + row * lda] : A[row + k * lda]) : 0.0;
+      const double av = rowok ? sc * ap[0] : 0.0;
 #pragma unroll
       for (int c = 0; c < NC; ++c)
-        if (c < n) acc[c] += av * (transB ? B[c + k * ldb] : B[k + c * ldb]);
+        if (c < n) acc[c] += av * bp[c * bcol];
+      ap += astep;
+      bp += bstep;
     }
   }
   if (w > 0) {
@@ -195,22 +208,25 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(const GemmProblem* __restri
   }
 }
 
+template <int NC>
+static void launch_skinny(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
+                          int max_m, int transA, int transB) {
+  const int tiles = ceil_div(max_m, 64);
+  hipLaunchKernelGGL((k_gemm_skinny<NC>), dim3((unsigned)nprob * tiles), dim3(256), 0, s, d_p, d_t,
+                     tiles, transA, transB);
+}
+
 void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
                  int max_m, int max_n, int transA, int transB) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
-  if (max_n <= 16) {
-    const int tiles = ceil_div(max_m, 64);
-    const dim3 grid((unsigned)nprob * tiles);
-    if (max_n == 1)
-      hipLaunchKernelGGL((k_gemm_skinny<1>), grid, dim3(256), 0, s, d_p, d_t, tiles, transA, transB);
-    else if (max_n <= 2)
-      hipLaunchKernelGGL((k_gemm_skinny<2>), grid, dim3(256), 0, s, d_p, d_t, tiles, transA, transB);
-    else if (max_n <= 4)
-      hipLaunchKernelGGL((k_gemm_skinny<4>), grid, dim3(256), 0, s, d_p, d_t, tiles, transA, transB);
-    else if (max_n <= 8)
-      hipLaunchKernelGGL((k_gemm_skinny<8>), grid, dim3(256), 0, s, d_p, d_t, tiles, transA, transB);
-    else
-      hipLaunchKernelGGL((k_gemm_skinny<16>), grid, dim3(256), 0, s, d_p, d_t, tiles, transA, transB);
+  if (max_n <= 4) {
+    if (max_n == 1) launch_skinny<1>(s, d_p, d_t, nprob, max_m, transA, transB);
+    else if (max_n <= 2) launch_skinny<2>(s, d_p, d_t, nprob, max_m, transA, transB);
+    else launch_skinny<4>(s, d_p, d_t, nprob, max_m, transA, transB);
+  } else if (max_n <= 16) {
+    const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 16);
+    hipLaunchKernelGGL((k_gemm<64, 16, 16, 16>), dim3((unsigned)nprob * tiles), dim3(256), 0, s,
+                       d_p, d_t, tiles, transA, transB);
   } else if (max_n <= 32) {
     const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 32);
     hipLaunchKernelGGL((k_gemm<64, 32, 32, 16>), dim3((unsigned)nprob * tiles), dim3(256), 0, s,

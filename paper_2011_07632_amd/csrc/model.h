@@ -89,6 +89,7 @@ struct LaunchRec {
   const void* terms;
   int nprob, max_m, max_n, transA, transB;
   double bytes;  // algorithmic bytes: every A operand once, distinct B operands once, C once
+  int tag = -1;  // caller-defined label (which pass of a product)
 };
 struct Recorder {
   std::vector<LaunchRec> recs;
@@ -96,6 +97,9 @@ struct Recorder {
   void block(Arena& a, hipStream_t s, const BlockBatch& b);
   void trsm(Arena& a, hipStream_t s, const TrsmBatch& b, int trans);
   void replay(hipStream_t s) const;
+  void tag_from(size_t first, int tag) {
+    for (size_t i = first; i < recs.size(); ++i) recs[i].tag = tag;
+  }
 };
 
 // ---------------------------------------------------------------- H^2 --
@@ -115,6 +119,7 @@ struct H2Model {
   std::vector<std::vector<int>> cand_h;  // host copy (tree positions)
   std::vector<std::vector<int>> skel_h;  // skeleton of every node (tree positions)
   std::vector<double*> W;         // U_v (leaf) or R_v (nonleaf): cand_v x k_v, ld cand_v
+  std::vector<double*> WT;        // W_v^T (k_v x cand_v, ld k_v): coalesced upward pass
   std::vector<double*> Bh;        // per coupling entry: K(skel_i, skel_j), k_i x k_j
   std::vector<double*> nearA;     // per leaf near entry: n_i x n_j, ld n_i
   double times[4] = {0, 0, 0, 0};
@@ -210,7 +215,7 @@ void h2_plan_run(H2Model& H);
 void h2_plan_run_last(H2Model& H);
 H2Model::NearStats h2_near_stats(H2Model& H, int m);
 void h2_time_near(H2Model& H, int m, int reps, double* ms, double* bytes);
-int h2_time_launches(H2Model& H, int m, int reps, double* ms, double* bytes, int cap);
+int h2_time_launches(H2Model& H, int m, int reps, double* ms, double* bytes, int* tags, int cap);
 
 struct PcgResult {
   std::vector<int> iters;

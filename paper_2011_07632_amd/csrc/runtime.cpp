@@ -202,22 +202,78 @@ static const void* keep(Arena& a, hipStream_t s, const std::vector<T>& v) {
   return upload(a, s, v);
 }
 
-void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
-  if (b.probs.empty() || b.max_m == 0 || b.max_n == 0) return;
-  std::vector<GemmTerm> t = b.terms;
-  if (t.empty()) t.push_back(GemmTerm{});
+// Products with at most 16 columns are bandwidth-bound; a problem whose term
+// list streams more than kSplitBytes of A is cut into consecutive groups of
+// terms, each written to its own partial result, and a second launch sums the
+// partials in group order into C (deterministic).  This balances the work over
+// workgroups when per-problem work is uneven (the coupling pass).
+static constexpr double kSplitBytes = 4.0 * (1 << 20);
+
+static double batch_bytes(const GemmBatch& b) {
   double bytes = 0;
   std::unordered_set<const double*> seen;
   for (const GemmProblem& p : b.probs) {
     bytes += 8.0 * p.m * p.n * (p.beta != 0.0 ? 2.0 : 1.0);
     for (int q = p.term_begin; q < p.term_end; ++q) {
       const GemmTerm& g = b.terms[q];
-      bytes += 8.0 * p.m * g.k;                            // every A operand once
-      if (seen.insert(g.B).second) bytes += 8.0 * g.k * p.n;  // distinct B operands once
+      bytes += 8.0 * p.m * g.k;                                // every A operand once
+      if (seen.insert(g.B).second) bytes += 8.0 * g.k * p.n;   // distinct B operands once
     }
   }
-  recs.push_back({0, keep(a, s, b.probs), keep(a, s, t), (int)b.probs.size(), b.max_m, b.max_n,
-                  b.transA, b.transB, bytes});
+  return bytes;
+}
+
+void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
+  if (b.probs.empty() || b.max_m == 0 || b.max_n == 0) return;
+  const double bytes = batch_bytes(b);
+  bool split = false;
+  if (b.max_n <= 16)
+    for (const GemmProblem& p : b.probs) {
+      double w = 0;
+      for (int q = p.term_begin; q < p.term_end; ++q) w += 8.0 * p.m * b.terms[q].k;
+      if (w > kSplitBytes && p.term_end - p.term_begin > 1) { split = true; break; }
+    }
+  if (!split) {
+    std::vector<GemmTerm> t = b.terms;
+    if (t.empty()) t.push_back(GemmTerm{});
+    recs.push_back({0, keep(a, s, b.probs), keep(a, s, t), (int)b.probs.size(), b.max_m, b.max_n,
+                    b.transA, b.transB, bytes, -1});
+    return;
+  }
+  GemmBatch parts(b.transA, b.transB);
+  BlockBatch red;
+  // partial results live in this recorder's arena for its lifetime
+  for (const GemmProblem& p : b.probs) {
+    double w = 0;
+    for (int q = p.term_begin; q < p.term_end; ++q) w += 8.0 * p.m * b.terms[q].k;
+    if (w <= kSplitBytes || p.term_end - p.term_begin <= 1) {
+      parts.probs.push_back(p);
+      parts.probs.back().term_begin = (int)parts.terms.size();
+      for (int q = p.term_begin; q < p.term_end; ++q) parts.terms.push_back(b.terms[q]);
+      parts.probs.back().term_end = (int)parts.terms.size();
+      parts.max_m = std::max(parts.max_m, p.m);
+      parts.max_n = std::max(parts.max_n, p.n);
+      continue;
+    }
+    red.add(p.C, p.m, p.n, p.ldc, p.beta);
+    int q = p.term_begin;
+    while (q < p.term_end) {
+      double g = 0;
+      const int q0 = q;
+      while (q < p.term_end && (q == q0 || g + 8.0 * p.m * b.terms[q].k <= kSplitBytes)) {
+        g += 8.0 * p.m * b.terms[q].k;
+        ++q;
+      }
+      double* part = a.get_n<double>((size_t)p.m * p.n);
+      parts.add(part, p.m, p.n, p.m, 0.0, 1.0);
+      for (int r = q0; r < q; ++r) parts.terms.push_back(b.terms[r]);
+      parts.probs.back().term_end = (int)parts.terms.size();
+      red.term(part, p.m, p.alpha);
+    }
+  }
+  recs.push_back({0, keep(a, s, parts.probs), keep(a, s, parts.terms), (int)parts.probs.size(),
+                  parts.max_m, parts.max_n, parts.transA, parts.transB, bytes, -1});
+  block(a, s, red);
 }
 
 void Recorder::block(Arena& a, hipStream_t s, const BlockBatch& b) {
@@ -225,13 +281,13 @@ void Recorder::block(Arena& a, hipStream_t s, const BlockBatch& b) {
   std::vector<BlockTerm> t = b.terms;
   if (t.empty()) t.push_back(BlockTerm{});
   recs.push_back({1, keep(a, s, b.probs), keep(a, s, t), (int)b.probs.size(), b.max_m, b.max_n, 0,
-                  0, 0.0});
+                  0, 0.0, -1});
 }
 
 void Recorder::trsm(Arena& a, hipStream_t s, const TrsmBatch& b, int trans) {
   if (b.probs.empty()) return;
   recs.push_back({2, keep(a, s, b.probs), nullptr, (int)b.probs.size(), b.max_n, b.max_nrhs, trans,
-                  0, 0.0});
+                  0, 0.0, -1});
 }
 
 void Recorder::replay(hipStream_t s) const {
