@@ -23,6 +23,32 @@ import numpy as np  # noqa: E402
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2011_07632_amd/csrc/kernels.hip", "paper_2011_07632_amd/csrc/runtime.cpp",
+                  "paper_2011_07632_amd/csrc/h2.cpp"]
+
+
+def source_hash() -> str:
+    """Hash of the sources that determine the product's kernels and launches."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload: str, pass_name: str):
+    """HBM bytes per launch of the dominant pass measured with rocprofv3 counters
+    (profiles/hbm_traffic_<workload>.json), or None when the kernel sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha") != source_hash() or rec.get("pass") != pass_name:
+        return None
+    return round(rec["fetch_bytes"] + rec["write_bytes"], 1)
 
 
 def log(*a):
@@ -72,6 +98,9 @@ def main():
     ap.add_argument("--maxit", type=int, default=20000)
     ap.add_argument("--cpu-sample", type=int, default=6000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="counter-collection mode: build the H^2 matrix, run a 2 GiB copy (counter "
+                         "calibration) and one product, then exit; run under rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
@@ -94,6 +123,16 @@ def main():
     torch.cuda.synchronize()
     t_h2 = time.perf_counter() - t0
     log(f"[bench] {w.name}: h2_build {t_h2:.3f} s, levels {h2.levels}")
+    if args.counters:
+        src = torch.ones(1 << 28, dtype=torch.float64, device=dev)   # 2 GiB read, 2 GiB written
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        P.h2_matvec(h2, b)
+        torch.cuda.synchronize()
+        log(f"[bench] counters mode done (source {source_hash()})")
+        return
 
     def step():
         t0 = time.perf_counter()
@@ -131,7 +170,8 @@ def main():
         passes[d["pass"]] = round(passes.get(d["pass"], 0.0) + d["ms"], 4)
     kern = "k_gemm_skinny" if w.nrhs <= 16 else "k_gemm (MFMA)"
     roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
+                "traffic": recorded_traffic(w.name, dom["pass"]),
                 "kernel": f"{kern}: {dom['pass']} of h2_matvec",
                 "bytes_per_launch": dom["bytes"], "ms_per_launch": round(dom["ms"], 4),
                 "product_passes_ms": passes}

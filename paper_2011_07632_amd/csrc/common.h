@@ -8,7 +8,7 @@
 #include <vector>
 #include <stdexcept>
 
-#include "../../include/spdhss.h"
+#include "spdhss.h"
 
 namespace spd {
 
