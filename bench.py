@@ -165,9 +165,11 @@ def main():
     # that PCG calls every iteration, timed with HIP events on its stream
     launches = P.binding.product_launch_times(h2, w.nrhs, reps=10)
     dom = max(launches, key=lambda d: d["ms"])
-    passes = {}
+    acc = {}
     for d in launches:
-        passes[d["pass"]] = round(passes.get(d["pass"], 0.0) + d["ms"], 4)
+        ms_, by_ = acc.get(d["pass"], (0.0, 0.0))
+        acc[d["pass"]] = (ms_ + d["ms"], by_ + d["bytes"])
+    passes = {k: {"ms": round(v[0], 4), "gbs": round(v[1] / v[0] / 1e6, 1)} for k, v in acc.items()}
     kern = "k_gemm_skinny" if w.nrhs <= 16 else "k_gemm (MFMA)"
     roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),

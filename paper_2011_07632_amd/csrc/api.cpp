@@ -112,10 +112,11 @@ spd_status ulv_apply(spd_ulv_t F, const double* b, double* x, int32_t nrhs, int6
   SPD_REQUIRE(nrhs >= 1 && ld >= N, SPD_E_INVALID, "bad nrhs or ld");
   hipStream_t s = as_stream(stream);
   F->m.s = s;
-  double* z = ulv_plan_z(F->m, nrhs);
-  launch_gather_rows(s, b, ld, z, N, F->m.f->perm_d, N, nrhs);
-  ulv_apply_tree(F->m, z, z, nrhs);
-  launch_scatter_rows(s, z, N, x, ld, F->m.f->perm_d, N, nrhs);
+  double* in = ulv_plan_in(F->m, nrhs);
+  double* out = ulv_plan_out(F->m, nrhs);
+  launch_gather_rows(s, b, ld, in, N, F->m.f->perm_d, N, nrhs);
+  ulv_apply_tree(F->m, in, out, nrhs);
+  launch_scatter_rows(s, out, N, x, ld, F->m.f->perm_d, N, nrhs);
   SPD_HIP(hipStreamSynchronize(s));
   SPD_API_END
 }

@@ -197,11 +197,17 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
   {
     std::vector<KBlockProblem> kb;
     int mm = 0, mn = 0;
-    for (int v = 1; v < nn; ++v)
+    // the blocks of one block row are adjacent in memory (one allocation), so
+    // the product streams a row's couplings with adjacent columns as one
+    for (int v = 1; v < nn; ++v) {
+      size_t row = 0;
+      for (int64_t e = T.coup_ptr[v]; e < T.coup_ptr[v + 1]; ++e) row += (size_t)H.k[T.coup_idx[e]];
+      double* base = (H.k[v] > 0 && row > 0) ? H.arena.get_n<double>((size_t)H.k[v] * row) : nullptr;
       for (int64_t e = T.coup_ptr[v]; e < T.coup_ptr[v + 1]; ++e) {
         const int j = T.coup_idx[e];
         if (H.k[v] == 0 || H.k[j] == 0) continue;
-        H.Bh[e] = H.arena.get_n<double>((size_t)H.k[v] * H.k[j]);
+        H.Bh[e] = base;
+        base += (size_t)H.k[v] * H.k[j];
         KBlockProblem kp{};
         kp.out = H.Bh[e];
         kp.ia = H.skel_d(v);
@@ -213,11 +219,16 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
         mm = std::max(mm, kp.na);
         mn = std::max(mn, kp.nb);
       }
-    for (int v = T.first_at(1); v < T.first_at(1) + T.count_at(1); ++v)
+    }
+    for (int v = T.first_at(1); v < T.first_at(1) + T.count_at(1); ++v) {
+      size_t row = 0;
+      for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) row += (size_t)T.size(T.near_idx[e]);
+      double* base = H.arena.get_n<double>(std::max<size_t>((size_t)T.size(v) * row, 1));
       for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) {
         const int j = T.near_idx[e];
         const int ni = (int)T.size(v), nj = (int)T.size(j);
-        H.nearA[e] = H.arena.get_n<double>((size_t)std::max(ni * nj, 1));
+        H.nearA[e] = base;
+        base += (size_t)ni * nj;
         KBlockProblem kp{};
         kp.out = H.nearA[e];
         kp.offa = T.start[v];
@@ -230,6 +241,7 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
         mm = std::max(mm, ni);
         mn = std::max(mn, nj);
       }
+    }
     // launch in bounded chunks of descriptors
     const size_t chunk = 1 << 16;
     for (size_t a = 0; a < kb.size(); a += chunk) {

@@ -10,6 +10,12 @@
 
 namespace spd {
 
+// Global-memory pointer (global_load instead of flat_load), and a pointer to
+// memory that no workgroup writes while the kernel runs (the compiler may then
+// read wave-uniform addresses through the scalar cache).
+typedef const double __attribute__((address_space(1))) gdouble;
+typedef const double __attribute__((address_space(4))) rdouble;
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------ reductions --
@@ -127,93 +133,170 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem* __restrict__ pr
       }
 }
 
-// Skinny grouped GEMM for at most 16 right-hand columns: bandwidth-bound
-// streaming of A.  A workgroup owns 64 rows of one problem (lane l owns row
-// i0 + l) and the four waves split every term's inner dimension into four
-// contiguous quarters; the quarters are summed in wave order through LDS, so
-// results are deterministic.  The wave index is made wave-uniform so that the
-// B entries, the same for every lane, come from scalar loads.  Long term
-// lists are split into several problems by the host (see Recorder::gemm).
-template <int NC>
-__global__ __launch_bounds__(256) void k_gemm_skinny(const GemmProblem* __restrict__ probs,
-                                                     const GemmTerm* __restrict__ terms,
-                                                     int tiles_max, int transA, int transB) {
-  constexpr int U = 8;
-  __shared__ double red[3][64][NC];
+// Skinny grouped GEMM for at most 4 right-hand columns: bandwidth-bound
+// streaming of A.  A workgroup of NW waves owns up to 64*RG rows of one
+// problem (lane l of row group g owns row i0 + 64 g + l), so every column of a
+// block is read by one workgroup only: no cache line is fetched by two
+// workgroups, which may sit on different XCDs with separate L2s.  The waves
+// take the columns of each term round-robin (wave w reads columns w, w+NW,
+// ...), U columns per step, all loads of a step issued back to back; in the
+// last step of a term, out-of-range columns load from an in-range address and
+// are zeroed afterwards.  Small launches use 16 waves per workgroup so that
+// each wave's chain of dependent memory round trips stays short.  The NW
+// partial sums are added pairwise in a fixed tree through LDS, so results are
+// deterministic.  The wave index is made wave-uniform so that the B entries,
+// the same for every lane, come from scalar loads.  A is read with
+// non-temporal loads: it is streamed once per launch.  Long term lists are
+// split into several problems by the host (see Recorder::gemm).
+template <int NC, int RG, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gemm_skinny(const GemmProblem* __restrict__ probs,
+                                                          const GemmTerm* __restrict__ terms,
+                                                          int tiles_max, int transA, int transB) {
+  constexpr int U = (RG == 1) ? 8 : (RG == 2 ? 6 : 4);
+  constexpr int TR = 64 * RG;
+  __shared__ double red[NW / 2][TR][NC];
   const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
   const GemmProblem P = probs[p];
-  const int tm = (P.m + 63) / 64;
-  if (tile >= tm) return;
+  const int i0 = tile * TR;
+  if (i0 >= P.m || P.n <= 0) return;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int row = tile * 64 + lane;
-  const bool rowok = row < P.m;
   const int n = P.n;
-  double acc[NC];
+  int jc[NC];  // right-hand columns past n read column 0 and are never stored
 #pragma unroll
-  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  for (int j = 0; j < NC; ++j) jc[j] = j < n ? j : 0;
+  int rowc[RG];  // rows past the problem read row i0 and are never stored
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    const int r = i0 + 64 * g + lane;
+    rowc[g] = r < P.m ? r : i0;
+  }
+  double acc[RG][NC];
+#pragma unroll
+  for (int g = 0; g < RG; ++g)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[g][c] = 0.0;
   for (int t = P.term_begin; t < P.term_end; ++t) {
     const GemmTerm T = terms[t];
-    const int q = (T.k + 3) / 4;
-    const int k0 = w * q, k1 = min(T.k, k0 + q);
-    if (k0 >= k1) continue;
+    const int K = T.k;
+    if (w >= K) continue;
     const int64_t lda = T.lda, ldb = T.ldb;
     const double sc = T.scale;
-    // A walks down a column (no transpose) or along a row (transpose)
-    const int64_t astep = transA ? 1 : lda;
-    const double* __restrict__ ap =
-        T.A + (transA ? (int64_t)k0 + (int64_t)(rowok ? row : 0) * lda : (int64_t)(rowok ? row : 0) + k0 * lda);
-    const int64_t bstep = transB ? ldb : 1;
-    const int64_t bcol = transB ? 1 : ldb;
-    const double* __restrict__ bp = T.B + (transB ? (int64_t)k0 * ldb : (int64_t)k0);
-    int k = k0;
-    for (; k + U <= k1; k += U) {
-      double a[U];
+    // op(A)(r, c) = transA ? A[c + r lda] : A[r + c lda];  op(B)(c, j) likewise
+    const int64_t acs = transA ? 1 : lda, ars = transA ? lda : 1;
+    const int64_t bcs = transB ? ldb : 1, bjs = transB ? 1 : ldb;
+    const int64_t astep = NW * acs, bstep = NW * bcs;
+    gdouble* ap[RG];
 #pragma unroll
-      for (int u = 0; u < U; ++u) a[u] = rowok ? ap[u * astep] : 0.0;
+    for (int g = 0; g < RG; ++g) ap[g] = (gdouble*)T.A + (int64_t)rowc[g] * ars + (int64_t)w * acs;
+    rdouble* bp = (rdouble*)T.B + (int64_t)w * bcs;
+    int c = w;  // this wave's next column; a step reads c, c + NW, ..., c + NW (U - 1)
+    for (; c + NW * (U - 1) < K; c += NW * U) {
+      double a[U][RG], b[U][NC];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const double av = sc * a[u];
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (c < n) acc[c] += av * bp[u * bstep + c * bcol];
+        for (int g = 0; g < RG; ++g) a[u][g] = __builtin_nontemporal_load(&ap[g][u * astep]);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) b[u][j] = bp[u * bstep + jc[j] * bjs];
       }
-      ap += U * astep;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+          const double av = sc * a[u][g];
+#pragma unroll
+          for (int j = 0; j < NC; ++j) acc[g][j] += av * b[u][j];
+        }
+#pragma unroll
+      for (int g = 0; g < RG; ++g) ap[g] += U * astep;
       bp += U * bstep;
     }
-    for (; k < k1; ++k) {
-      const double av = rowok ? sc * ap[0] : 0.0;
+    if (c < K) {  // fewer than U columns left: clamp to column c, zero afterwards
+      double a[U][RG], b[U][NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        if (c < n) acc[c] += av * bp[c * bcol];
-      ap += astep;
-      bp += bstep;
+      for (int u = 0; u < U; ++u) {
+        const int64_t uu = (c + NW * u < K) ? u : 0;
+#pragma unroll
+        for (int g = 0; g < RG; ++g) a[u][g] = __builtin_nontemporal_load(&ap[g][uu * astep]);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) b[u][j] = bp[uu * bstep + jc[j] * bjs];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool cok = c + NW * u < K;
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+          const double av = cok ? sc * a[u][g] : 0.0;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) acc[g][j] += av * (cok ? b[u][j] : 0.0);
+        }
+      }
     }
   }
-  if (w > 0) {
+  // pairwise tree over the waves: at width h, wave w < h adds wave w + h
 #pragma unroll
-    for (int c = 0; c < NC; ++c) red[w - 1][lane][c] = acc[c];
+  for (int h = NW / 2; h >= 1; h /= 2) {
+    if (w >= h && w < 2 * h) {
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) red[w - h][64 * g + lane][j] = acc[g][j];
+    }
+    __syncthreads();
+    if (w < h) {
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[g][j] += red[w][64 * g + lane][j];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (w == 0 && rowok) {
+  if (w == 0) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (c >= n) continue;
-      const double v = ((acc[c] + red[0][lane][c]) + red[1][lane][c]) + red[2][lane][c];
-      double* cp = P.C + row + (int64_t)c * P.ldc;
-      double val = P.alpha * v;
-      if (P.beta != 0.0) val += P.beta * (*cp);
-      *cp = val;
+    for (int g = 0; g < RG; ++g) {
+      const int r = i0 + 64 * g + lane;
+      if (r >= P.m) continue;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        if (j >= n) continue;
+        double* cp = P.C + r + (int64_t)j * P.ldc;
+        double val = P.alpha * acc[g][j];
+        if (P.beta != 0.0) val += P.beta * (*cp);
+        *cp = val;
+      }
     }
   }
 }
 
+template <int NC, int NW>
+static void launch_skinny_nw(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
+                             int max_m, int transA, int transB) {
+  if (max_m <= 64) {
+    hipLaunchKernelGGL((k_gemm_skinny<NC, 1, NW>), dim3((unsigned)nprob), dim3(64 * NW), 0, s, d_p,
+                       d_t, 1, transA, transB);
+  } else if (max_m <= 128) {
+    hipLaunchKernelGGL((k_gemm_skinny<NC, 2, NW>), dim3((unsigned)nprob), dim3(64 * NW), 0, s, d_p,
+                       d_t, 1, transA, transB);
+  } else {
+    const int tiles = ceil_div(max_m, 256);
+    hipLaunchKernelGGL((k_gemm_skinny<NC, 4, NW>), dim3((unsigned)nprob * tiles), dim3(64 * NW), 0,
+                       s, d_p, d_t, tiles, transA, transB);
+  }
+}
+
+// Workgroups below which a launch uses 16 waves per workgroup (two per SIMD
+// of every CU at 4 waves).
+static constexpr int kSkinnyWide = 2048;
+
 template <int NC>
 static void launch_skinny(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
                           int max_m, int transA, int transB) {
-  const int tiles = ceil_div(max_m, 64);
-  hipLaunchKernelGGL((k_gemm_skinny<NC>), dim3((unsigned)nprob * tiles), dim3(256), 0, s, d_p, d_t,
-                     tiles, transA, transB);
+  const int64_t blocks = (int64_t)nprob * ceil_div(max_m, 256);
+  if (blocks < kSkinnyWide)
+    launch_skinny_nw<NC, 16>(s, d_p, d_t, nprob, max_m, transA, transB);
+  else
+    launch_skinny_nw<NC, 4>(s, d_p, d_t, nprob, max_m, transA, transB);
 }
 
 void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,

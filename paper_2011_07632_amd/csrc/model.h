@@ -162,9 +162,12 @@ struct Factors {
   std::vector<double*> S; // leaf Cholesky factors S_v (n_v x n_v)
   std::vector<double*> V; // V_v (leaf, n_v x r_v) or V-bar_v (rho_v x r_v)
   std::vector<double*> F; // factor of I + bold B_v (rho_v x rho_v), nonleaf incl. root
-  std::vector<double*> Sinv, Finv;  // explicit inverses of S_v and F_v (lower)
+  // operators of the solve, formed by ulv_factor:
+  //   Dm: leaf A_vv^{-1} = S_v^{-T} S_v^{-1}; nonleaf and root (I + bold B_vv)^{-1} - I
+  //   Zs: Z_v = S_v^{-T} V_v (leaf) or F_v^{-T} V-bar_v (nonleaf); ZsT: Z_v^T
+  std::vector<double*> Dm, Zs, ZsT;
   bool root_factored = false;
-  bool inverted = false;
+  bool ops_ready = false;  // Dm, Zs, ZsT formed
   // stacked rank-space layout: the children of p share a rho_p-row buffer
   std::vector<int64_t> par_off;
   int64_t stack_rows = 0;
@@ -206,7 +209,9 @@ struct ULVModel {
 
 void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s);
 void ulv_apply_tree(ULVModel& U, const double* b, double* x, int ncols);
-double* ulv_plan_z(ULVModel& U, int m);
+// apply plan buffers: ulv_plan_in is read and ulv_plan_out written in place
+double* ulv_plan_in(ULVModel& U, int m);
+double* ulv_plan_out(ULVModel& U, int m);
 
 // product plan buffers: h2_plan_x is read and h2_plan_y written in place
 double* h2_plan_x(H2Model& H, int m);

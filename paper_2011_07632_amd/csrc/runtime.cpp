@@ -3,8 +3,8 @@
 #include "model.h"
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
-#include <unordered_set>
 #include <cstring>
 
 namespace spd {
@@ -120,8 +120,21 @@ void GemmBatch::add(double* C, int m, int n, int ldc, double beta, double alpha)
   max_n = std::max(max_n, n);
 }
 
+// A term that continues the previous term of the same problem in memory (its
+// first column of op(A) follows that term's last, and likewise its rows of
+// op(B)) is merged into it: a longer unbroken stream for the kernels.
 void GemmBatch::term(const double* A, int lda, const double* B, int ldb, int k, double scale) {
   if (k <= 0) return;
+  GemmProblem& p = probs.back();
+  if (p.term_end > p.term_begin) {
+    GemmTerm& q = terms.back();
+    const int64_t acs = transA ? 1 : q.lda, bcs = transB ? q.ldb : 1;
+    if (q.lda == lda && (q.ldb == ldb || (p.n == 1 && !transB)) && q.scale == scale &&
+        A == q.A + acs * q.k && B == q.B + bcs * q.k) {
+      q.k += k;
+      return;
+    }
+  }
   GemmTerm t{};
   t.A = A;
   t.B = B;
@@ -130,7 +143,7 @@ void GemmBatch::term(const double* A, int lda, const double* B, int ldb, int k, 
   t.lda = lda;
   t.ldb = ldb;
   terms.push_back(t);
-  probs.back().term_end = (int)terms.size();
+  p.term_end = (int)terms.size();
 }
 
 void GemmBatch::run(hipStream_t s, Stage& st) {
@@ -202,23 +215,37 @@ static const void* keep(Arena& a, hipStream_t s, const std::vector<T>& v) {
   return upload(a, s, v);
 }
 
-// Products with at most 16 columns are bandwidth-bound; a problem whose term
-// list streams more than kSplitBytes of A is cut into consecutive groups of
-// terms, each written to its own partial result, and a second launch sums the
-// partials in group order into C (deterministic).  This balances the work over
-// workgroups when per-problem work is uneven (the coupling pass).
-static constexpr double kSplitBytes = 4.0 * (1 << 20);
+// Products with at most 16 columns are bandwidth-bound; a problem that streams
+// more than kSplitBytes of A is cut into parts of about equal width (terms are
+// cut at column boundaries where needed), each written to its own partial
+// result, and a second launch sums the partials in part order into C
+// (deterministic).  This balances the work over workgroups when per-problem
+// work is uneven (the coupling pass).
+static constexpr double kSplitBytes = 1.0 * (1 << 20);
 
+// Algorithmic bytes of a batch: every A operand once, C once (twice with
+// beta), and the union of the B ranges read (B operands of different terms
+// may overlap, e.g. skeleton vectors shared by many coupling rows).
 static double batch_bytes(const GemmBatch& b) {
   double bytes = 0;
-  std::unordered_set<const double*> seen;
+  std::vector<std::pair<const double*, const double*>> rs;
   for (const GemmProblem& p : b.probs) {
     bytes += 8.0 * p.m * p.n * (p.beta != 0.0 ? 2.0 : 1.0);
     for (int q = p.term_begin; q < p.term_end; ++q) {
       const GemmTerm& g = b.terms[q];
-      bytes += 8.0 * p.m * g.k;                                // every A operand once
-      if (seen.insert(g.B).second) bytes += 8.0 * g.k * p.n;   // distinct B operands once
+      bytes += 8.0 * p.m * g.k;
+      if (!b.transB)
+        for (int j = 0; j < p.n; ++j) rs.push_back({g.B + (int64_t)j * g.ldb, g.B + (int64_t)j * g.ldb + g.k});
+      else
+        for (int c = 0; c < g.k; ++c) rs.push_back({g.B + (int64_t)c * g.ldb, g.B + (int64_t)c * g.ldb + p.n});
     }
+  }
+  std::sort(rs.begin(), rs.end());
+  const double* end = nullptr;
+  for (const auto& r : rs) {
+    const double* lo = (end && r.first < end) ? end : r.first;
+    if (r.second > lo) bytes += 8.0 * (double)(r.second - lo);
+    if (!end || r.second > end) end = r.second;
   }
   return bytes;
 }
@@ -226,13 +253,15 @@ static double batch_bytes(const GemmBatch& b) {
 void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
   if (b.probs.empty() || b.max_m == 0 || b.max_n == 0) return;
   const double bytes = batch_bytes(b);
+  auto width = [&](const GemmProblem& p) {
+    int64_t k = 0;
+    for (int q = p.term_begin; q < p.term_end; ++q) k += b.terms[q].k;
+    return k;
+  };
   bool split = false;
   if (b.max_n <= 16)
-    for (const GemmProblem& p : b.probs) {
-      double w = 0;
-      for (int q = p.term_begin; q < p.term_end; ++q) w += 8.0 * p.m * b.terms[q].k;
-      if (w > kSplitBytes && p.term_end - p.term_begin > 1) { split = true; break; }
-    }
+    for (const GemmProblem& p : b.probs)
+      if (8.0 * p.m * width(p) > kSplitBytes && width(p) > 1) { split = true; break; }
   if (!split) {
     std::vector<GemmTerm> t = b.terms;
     if (t.empty()) t.push_back(GemmTerm{});
@@ -244,9 +273,8 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
   BlockBatch red;
   // partial results live in this recorder's arena for its lifetime
   for (const GemmProblem& p : b.probs) {
-    double w = 0;
-    for (int q = p.term_begin; q < p.term_end; ++q) w += 8.0 * p.m * b.terms[q].k;
-    if (w <= kSplitBytes || p.term_end - p.term_begin <= 1) {
+    const int64_t K = width(p);
+    if (8.0 * p.m * K <= kSplitBytes || K <= 1) {
       parts.probs.push_back(p);
       parts.probs.back().term_begin = (int)parts.terms.size();
       for (int q = p.term_begin; q < p.term_end; ++q) parts.terms.push_back(b.terms[q]);
@@ -255,20 +283,32 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
       parts.max_n = std::max(parts.max_n, p.n);
       continue;
     }
+    const int64_t nparts = std::min<int64_t>(K, (int64_t)std::ceil(8.0 * p.m * K / kSplitBytes));
     red.add(p.C, p.m, p.n, p.ldc, p.beta);
     int q = p.term_begin;
-    while (q < p.term_end) {
-      double g = 0;
-      const int q0 = q;
-      while (q < p.term_end && (q == q0 || g + 8.0 * p.m * b.terms[q].k <= kSplitBytes)) {
-        g += 8.0 * p.m * b.terms[q].k;
-        ++q;
+    int64_t off = 0;  // columns of term q already assigned
+    for (int64_t part = 0; part < nparts; ++part) {
+      int64_t want = K * (part + 1) / nparts - K * part / nparts;
+      double* dst = a.get_n<double>((size_t)p.m * p.n);
+      parts.add(dst, p.m, p.n, p.m, 0.0, 1.0);
+      while (want > 0) {
+        const GemmTerm& g = b.terms[q];
+        const int64_t take = std::min<int64_t>(want, g.k - off);
+        GemmTerm t = g;
+        const int64_t acs = b.transA ? 1 : g.lda, bcs = b.transB ? g.ldb : 1;
+        t.A = g.A + acs * off;
+        t.B = g.B + bcs * off;
+        t.k = (int)take;
+        parts.terms.push_back(t);
+        want -= take;
+        off += take;
+        if (off == g.k) {
+          ++q;
+          off = 0;
+        }
       }
-      double* part = a.get_n<double>((size_t)p.m * p.n);
-      parts.add(part, p.m, p.n, p.m, 0.0, 1.0);
-      for (int r = q0; r < q; ++r) parts.terms.push_back(b.terms[r]);
       parts.probs.back().term_end = (int)parts.terms.size();
-      red.term(part, p.m, p.alpha);
+      red.term(dst, p.m, p.alpha);
     }
   }
   recs.push_back({0, keep(a, s, parts.probs), keep(a, s, parts.terms), (int)parts.probs.size(),

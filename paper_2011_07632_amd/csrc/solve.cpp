@@ -11,6 +11,16 @@
 // z += V (w - t), x = S^{-T} z).  The paper calls this step a ULV solve and
 // times it with the construction; the method is not spelled out there.
 //
+// The sweeps are run in an equivalent form with one product per level.  With
+// Z = S^{-T} V (leaf) or F^{-T} V-bar (nonleaf) and d = w - t:
+//   up:    t_v = Z_v^T b_v (leaf),  t_v = Z_v^T [t_c] (nonleaf)
+//   root:  [d_c] = ((I + bold B_root)^{-1} - I) [t_c]
+//   down:  [d_c] = ((I + bold B_v)^{-1} - I) [t_c] + Z_v d_v
+//   leaf:  x_v = A_vv^{-1} b_v + Z_v d_v
+// since F^{-T}(F^{-1} t + V-bar d) - t = (F^{-T} F^{-1} - I) t + Z d and
+// S^{-T}(S^{-1} b + V d) = (S S^T)^{-1} b + Z d.  The matrices are formed once
+// by ulv_factor from explicit inverses of the triangular factors.
+//
 // PCG (Section 6): x0 = 0, one recurrence per right-hand side, a column stops
 // once its recursively updated residual satisfies ||r|| <= rtol ||b||.
 #include "model.h"
@@ -25,40 +35,60 @@ struct ULVModel::ApplyPlan {
   int ncols = 0;
   Arena arena;
   Recorder rec;
-  double* z = nullptr;   // tree-order work vector (input and output)
-  double* ts = nullptr;  // stacked t blocks
-  double* ws = nullptr;  // stacked w blocks
-  std::vector<double*> u;
+  double* in = nullptr;   // tree-order right-hand sides (read)
+  double* out = nullptr;  // tree-order solution (written)
+  double* ts = nullptr;   // stacked t blocks
+  double* ds = nullptr;   // stacked d = w - t blocks
 };
 
 ULVModel::ULVModel() = default;
 ULVModel::~ULVModel() = default;
 
-// Explicit inverses of the triangular factors (S_v at the leaves, F_v above),
-// formed once by triangular solves against the identity, so that every sweep
-// of the solve is a batched product.
-static void invert_factors(Factors& F, Stage& st, hipStream_t s) {
-  if (F.inverted) return;
+// The solve's matrices (see the top of this file): explicit inverses X of the
+// triangular factors (S_v at the leaves, F_v above) by triangular solves
+// against the identity, in scratch memory; then Dm_v = X^T X (leaf) or
+// X^T X - I, and Z_v and Z_v^T copied from the construction, so that every
+// product of the solve reads its matrix down columns.
+static void form_solve_ops(Factors& F, const HSSModel& M, Stage& st, hipStream_t s) {
+  if (F.ops_ready) return;
   const TreeHost& T = F.T;
-  F.Sinv.assign(T.nnodes, nullptr);
-  F.Finv.assign(T.nnodes, nullptr);
-  BlockBatch eye;
+  F.Dm.assign(T.nnodes, nullptr);
+  F.Zs.assign(T.nnodes, nullptr);
+  F.ZsT.assign(T.nnodes, nullptr);
+  Arena tmp;
+  BlockBatch eye, dm_init, cp;
   TrsmBatch tb;
+  GemmBatch g(1, 0);
   for (int v = 0; v < T.nnodes; ++v) {
     const bool leaf = T.is_leaf(v);
     const double* L = leaf ? F.S[v] : F.F[v];
     const int n = F.rho[v];
     if (!L || n <= 0) continue;
-    double* X = F.arena.get_n<double>((size_t)n * n);
-    (leaf ? F.Sinv : F.Finv)[v] = X;
+    double* X = tmp.get_n<double>((size_t)n * n);
     eye.add(X, n, n, n, 0.0, 1);
     tb.add(L, n, X, n, n, n);
+    F.Dm[v] = F.arena.get_n<double>((size_t)n * n);
+    if (!leaf) dm_init.add(F.Dm[v], n, n, n, 0.0, 1);
+    g.add(F.Dm[v], n, n, n, leaf ? 0.0 : -1.0);
+    g.term(X, n, X, n, n);
+    const int r = F.r[v];
+    if (v > 0 && r > 0 && (size_t)v < M.Z.size() && M.Z[v]) {
+      F.Zs[v] = F.arena.get_n<double>((size_t)n * r);
+      F.ZsT[v] = F.arena.get_n<double>((size_t)n * r);
+      cp.add(F.Zs[v], n, r, n);
+      cp.term(M.Z[v], n);
+      cp.add(F.ZsT[v], r, n, r);
+      cp.term(M.Z[v], n, 1.0, 1);
+    }
   }
   eye.run(s, st);
   tb.run(s, st, 0);
+  dm_init.run(s, st);
+  g.run(s, st);
+  cp.run(s, st);
   SPD_HIP(hipStreamSynchronize(s));
   st.reset();
-  F.inverted = true;
+  F.ops_ready = true;
 }
 
 void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
@@ -68,7 +98,7 @@ void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
   const TreeHost& T = F.T;
   if (T.L == 1 || F.root_factored) {
     F.root_factored = true;
-    invert_factors(F, U.stage, s);
+    form_solve_ops(F, M, U.stage, s);
     return;
   }
   const int c1 = 1, c2 = 2, r1 = F.r[c1], r2 = F.r[c2], rv = r1 + r2;
@@ -102,136 +132,113 @@ void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
   }
   SPD_HIP(hipStreamSynchronize(s));
   F.root_factored = true;
-  invert_factors(F, U.stage, s);
+  form_solve_ops(F, M, U.stage, s);
 }
 
+// The sweeps as batched products, one launch per level.
 static void build_apply_plan(ULVModel& U, int m) {
   auto pl = std::make_unique<ULVModel::ApplyPlan>();
   pl->ncols = m;
   Factors& F = *U.f;
   const TreeHost& T = F.T;
-  const int L = T.L, nn = T.nnodes;
+  const int L = T.L;
   const int64_t N = T.N;
   hipStream_t s = U.s;
   Arena& a = pl->arena;
   Recorder& rec = pl->rec;
-  pl->z = a.get_n<double>((size_t)N * m);
-  double* z2 = a.get_n<double>((size_t)N * m);
+  pl->in = a.get_n<double>((size_t)N * m);
+  pl->out = a.get_n<double>((size_t)N * m);
   const int lf = T.first_at(1), lc = T.count_at(1);
   const int Ni = (int)N;
   if (L == 1) {
-    GemmBatch g1(0, 0), g2(1, 0);
-    g1.add(z2, Ni, m, Ni);
-    g1.term(F.Sinv[0], Ni, pl->z, Ni, Ni);
-    g2.add(pl->z, Ni, m, Ni);
-    g2.term(F.Sinv[0], Ni, z2, Ni, Ni);
-    rec.gemm(a, s, g1);
-    rec.gemm(a, s, g2);
+    GemmBatch g;
+    g.add(pl->out, Ni, m, Ni);
+    g.term(F.Dm[0], Ni, pl->in, Ni, Ni);
+    rec.gemm(a, s, g);
     SPD_HIP(hipStreamSynchronize(s));
     U.plan = std::move(pl);
     return;
   }
   const int64_t rows = std::max<int64_t>(F.stack_rows, 1);
   pl->ts = a.get_n<double>((size_t)rows * m);
-  pl->ws = a.get_n<double>((size_t)rows * m);
-  pl->u.assign(nn, nullptr);
-  double* rt = a.get_n<double>((size_t)std::max(F.rho[0], 1) * m);
-  // leaves: z2 = S^{-1} b ; t = V^T z2
+  pl->ds = a.get_n<double>((size_t)rows * m);
+  // leaves: t_v = Z_v^T b_v
   {
-    GemmBatch g1(0, 0), g2(1, 0);
+    GemmBatch g;
     for (int v = lf; v < lf + lc; ++v) {
-      const int nv = F.rho[v];
-      g1.add(z2 + T.start[v], nv, m, Ni);
-      g1.term(F.Sinv[v], nv, pl->z + T.start[v], Ni, nv);
       if (F.r[v] == 0) continue;
-      g2.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
-      g2.term(F.V[v], nv, z2 + T.start[v], Ni, nv);
+      g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
+      g.term(F.ZsT[v], F.r[v], pl->in + T.start[v], Ni, F.rho[v]);
     }
-    rec.gemm(a, s, g1);
-    rec.gemm(a, s, g2);
+    rec.gemm(a, s, g);
   }
-  // upward: u = F^{-1} [t_c] ; t = V-bar^T u
+  // upward: t_v = Z_v^T [t_c]
   for (int lev = 2; lev <= L - 1; ++lev) {
-    GemmBatch g1(0, 0), g2(1, 0);
+    GemmBatch g;
     for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
-      const int rv = F.rho[v];
-      pl->u[v] = a.get_n<double>((size_t)std::max(rv, 1) * m);
-      if (rv == 0) continue;
-      g1.add(pl->u[v], rv, m, rv);
-      g1.term(F.Finv[v], rv, pl->ts + F.par_off[v] * m, rv, rv);
-      if (F.r[v] == 0) continue;
-      g2.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
-      g2.term(F.V[v], rv, pl->u[v], rv, rv);
+      if (F.r[v] == 0 || F.rho[v] == 0) continue;
+      g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
+      g.term(F.ZsT[v], F.r[v], pl->ts + F.par_off[v] * m, F.rho[v], F.rho[v]);
     }
-    rec.gemm(a, s, g1);
-    rec.gemm(a, s, g2);
+    rec.gemm(a, s, g);
   }
-  // root: w = F_root^{-T} F_root^{-1} [t_c]
-  {
+  // root: [d_c] = ((I + bold B_root)^{-1} - I) [t_c]
+  if (F.rho[0] > 0) {
     const int rv = F.rho[0];
-    if (rv > 0) {
-      GemmBatch g1(0, 0), g2(1, 0);
-      g1.add(rt, rv, m, rv);
-      g1.term(F.Finv[0], rv, pl->ts + F.par_off[0] * m, rv, rv);
-      g2.add(pl->ws + F.par_off[0] * m, rv, m, rv);
-      g2.term(F.Finv[0], rv, rt, rv, rv);
-      rec.gemm(a, s, g1);
-      rec.gemm(a, s, g2);
-    }
+    GemmBatch g;
+    g.add(pl->ds + F.par_off[0] * m, rv, m, rv);
+    g.term(F.Dm[0], rv, pl->ts + F.par_off[0] * m, rv, rv);
+    rec.gemm(a, s, g);
   }
-  // downward: u += V-bar (w - t) ; [w_c] = F^{-T} u
+  // downward: [d_c] = ((I + bold B_v)^{-1} - I) [t_c] + Z_v d_v
   for (int lev = L - 1; lev >= 2; --lev) {
-    GemmBatch g1(0, 0), g2(1, 0);
+    GemmBatch g;
     for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
       const int rv = F.rho[v];
       if (rv == 0) continue;
-      if (F.r[v] > 0) {
-        g1.add(pl->u[v], rv, m, rv, 1.0);
-        g1.term(F.V[v], rv, F.blk(pl->ws, v, m), F.blk_ld(v), F.r[v], 1.0);
-        g1.term(F.V[v], rv, F.blk(pl->ts, v, m), F.blk_ld(v), F.r[v], -1.0);
-      }
-      g2.add(pl->ws + F.par_off[v] * m, rv, m, rv);
-      g2.term(F.Finv[v], rv, pl->u[v], rv, rv);
+      g.add(pl->ds + F.par_off[v] * m, rv, m, rv);
+      g.term(F.Dm[v], rv, pl->ts + F.par_off[v] * m, rv, rv);
+      if (F.r[v] > 0) g.term(F.Zs[v], rv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
     }
-    rec.gemm(a, s, g1);
-    rec.gemm(a, s, g2);
+    rec.gemm(a, s, g);
   }
-  // leaves: z2 += V (w - t) ; x = S^{-T} z2
+  // leaves: x_v = A_vv^{-1} b_v + Z_v d_v
   {
-    GemmBatch g1(0, 0), g2(1, 0);
+    GemmBatch g;
     for (int v = lf; v < lf + lc; ++v) {
       const int nv = F.rho[v];
-      if (F.r[v] > 0) {
-        g1.add(z2 + T.start[v], nv, m, Ni, 1.0);
-        g1.term(F.V[v], nv, F.blk(pl->ws, v, m), F.blk_ld(v), F.r[v], 1.0);
-        g1.term(F.V[v], nv, F.blk(pl->ts, v, m), F.blk_ld(v), F.r[v], -1.0);
-      }
-      g2.add(pl->z + T.start[v], nv, m, Ni);
-      g2.term(F.Sinv[v], nv, z2 + T.start[v], Ni, nv);
+      g.add(pl->out + T.start[v], nv, m, Ni);
+      g.term(F.Dm[v], nv, pl->in + T.start[v], Ni, nv);
+      if (F.r[v] > 0) g.term(F.Zs[v], nv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
     }
-    rec.gemm(a, s, g1);
-    rec.gemm(a, s, g2);
+    rec.gemm(a, s, g);
   }
   SPD_HIP(hipStreamSynchronize(s));
   U.plan = std::move(pl);
 }
 
-double* ulv_plan_z(ULVModel& U, int m) {
+double* ulv_plan_in(ULVModel& U, int m) {
   if (!U.plan || U.plan->ncols != m) {
     U.plan.reset();
     build_apply_plan(U, m);
   }
-  return U.plan->z;
+  return U.plan->in;
+}
+
+double* ulv_plan_out(ULVModel& U, int m) {
+  ulv_plan_in(U, m);
+  return U.plan->out;
 }
 
 void ulv_apply_tree(ULVModel& U, const double* b, double* x, int m) {
-  double* z = ulv_plan_z(U, m);
+  double* in = ulv_plan_in(U, m);
+  double* out = U.plan->out;
   const int64_t N = U.f->T.N;
-  if (b != z)
-    SPD_HIP(hipMemcpyAsync(z, b, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, U.s));
+  if (b != in)
+    SPD_HIP(hipMemcpyAsync(in, b, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, U.s));
   U.plan->rec.replay(U.s);
-  if (x != z)
-    SPD_HIP(hipMemcpyAsync(x, z, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, U.s));
+  if (x != out)
+    SPD_HIP(hipMemcpyAsync(x, out, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, U.s));
 }
 
 // ------------------------------------------------------------------ PCG --
@@ -271,11 +278,12 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   const int64_t N = H.T.N;
   const size_t bytes = (size_t)N * m * sizeof(double);
   Arena a;
-  double* r = a.get_n<double>((size_t)N * m);
-  double* z = a.get_n<double>((size_t)N * m);
-  double* p = h2_plan_x(H, m);   // the product reads p in place
-  double* q = h2_plan_y(H, m);   // and writes q in place
-  if (U) ulv_plan_z(*U, m);
+  // the product reads p and writes q in place; the preconditioner reads r and
+  // writes z in place
+  double* r = U ? ulv_plan_in(*U, m) : a.get_n<double>((size_t)N * m);
+  double* z = U ? ulv_plan_out(*U, m) : a.get_n<double>((size_t)N * m);
+  double* p = h2_plan_x(H, m);
+  double* q = h2_plan_y(H, m);
   const int nblk = ceil_div(N, 8192);
   double* partial = a.get_n<double>((size_t)nblk * m);
   double* sc = a.get_n<double>((size_t)8 * m);

@@ -43,6 +43,30 @@ def test_gemm(B, m, n, k, ta, tb):
         np.testing.assert_allclose(out[b].T, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
 
 
+# Products with at most 4 right-hand columns take the streaming kernel: row
+# tiles of 64, 128 and 256 (several tiles past 256), inner dimensions shorter
+# than the number of waves and with ragged last steps, 16-wave workgroups for
+# small batches and 4-wave workgroups for batches of 2048 or more.
+@pytest.mark.parametrize("m,n,k,bt", [(1, 1, 1, 3), (64, 1, 3, 3), (65, 2, 17, 3), (128, 4, 100, 3),
+                                      (129, 1, 257, 3), (256, 3, 64, 3), (300, 1, 95, 3),
+                                      (600, 2, 33, 2), (100, 1, 203, 2100), (200, 4, 41, 2100),
+                                      (40, 2, 7, 2100)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1)])
+def test_gemm_skinny(B, m, n, k, bt, ta, tb):
+    rng = np.random.default_rng(m * 7 + n * 3 + k + bt + ta)
+    As = [rng.standard_normal((k, m) if ta else (m, k)) for _ in range(bt)]
+    Bs = [rng.standard_normal((n, k) if tb else (k, n)) for _ in range(bt)]
+    Cs = [rng.standard_normal((m, n)) for _ in range(bt)]
+    dA, dB, dC = dev(colmajor_batch(As)), dev(colmajor_batch(Bs)), dev(colmajor_batch(Cs))
+    B.test_gemm(dA, dB, dC, ta, tb, alpha=1.5, beta=0.25)
+    out = dC.cpu().numpy()
+    for b in range(bt):
+        a = As[b].T if ta else As[b]
+        bb = Bs[b].T if tb else Bs[b]
+        ref = 1.5 * a @ bb + 0.25 * Cs[b]
+        np.testing.assert_allclose(out[b].T, ref, rtol=0, atol=1e-12 * max(np.abs(ref).max(), 1.0))
+
+
 @pytest.mark.parametrize("n", [1, 31, 63, 245, 300])
 def test_cholesky(B, n):
     rng = np.random.default_rng(n)
