@@ -51,6 +51,30 @@ def recorded_traffic(workload: str, pass_name: str):
     return round(rec["fetch_bytes"] + rec["write_bytes"], 1)
 
 
+def h2_sampled_error(P, h2, w, Xg, nrows: int = 200) -> float:
+    """Realized accuracy of the H^2 matrix: relative error of the product on a
+    random vector over sampled rows, each row of sigma*I + K formed directly."""
+    import torch
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(w.n)
+    xg = P.binding.cols_like(w.n, 1, "cuda").copy_(torch.from_numpy(x[:, None]))
+    y = P.h2_matvec(h2, xg).cpu().numpy()[:, 0]
+    X = Xg.cpu().numpy()
+    rows = rng.choice(w.n, size=nrows, replace=False)
+    d = np.sqrt(((X[rows, None, :] - X[None, :, :]) ** 2).sum(-1))
+    if w.kernel == "matern32":
+        t = np.sqrt(3.0) * d / w.ell
+        K = (1.0 + t) * np.exp(-t)
+    elif w.kernel == "gaussian":
+        K = np.exp(-(d / w.ell) ** 2)
+    elif w.kernel == "exponential":
+        K = np.exp(-d / w.ell)
+    else:
+        K = 1.0 / np.sqrt(d * d + w.ell * w.ell)
+    ref = K @ x + w.shift * x[rows]
+    return float(np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -177,6 +201,8 @@ def main():
                 "kernel": f"{kern}: {dom['pass']} of h2_matvec",
                 "bytes_per_launch": dom["bytes"], "ms_per_launch": round(dom["ms"], 4),
                 "product_passes_ms": passes}
+    h2_err = h2_sampled_error(P, h2, w, X)
+    log(f"[bench] sampled-row error of the H^2 product vs sigma*I + K: {h2_err:.2e}")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_sample, int(it.max()))
@@ -201,6 +227,7 @@ def main():
         "pcg_iterations": int(it.max()),
         "relres_max": float(res.max()),
         "h2_build_s": round(t_h2, 3),
+        "h2_rel_err_sampled": float(f"{h2_err:.3e}"),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -49,6 +49,30 @@ struct GemmTerm {
   int k, lda, ldb, pad;
 };
 
+// Symmetric-pair product for at most 4 right-hand columns.  For every term t
+// of a problem, with A_t an m x k_t block of a symmetric matrix whose mirror
+// block is A_t^T:
+//   C = alpha * sum_t scale_t A_t B_t + beta * C         (row results, m x n)
+//   P_t = scale_t A_t^T X   for every term with P_t set  (k_t x n, ldp)
+// X (m x n) holds the problem's own input rows.  When the problem's rows are
+// cut into row tiles, tile r writes its part of A_t^T X at P_t + r * ptile.
+struct SymProblem {
+  double* C;
+  const double* X;
+  int64_t ptile;
+  int m, n, ldc, ldx, ldp;
+  int term_begin, term_end;
+  int pad;
+  double alpha, beta;
+};
+struct SymTerm {
+  const double* A;
+  const double* B;
+  double* P;      // null: row result only (diagonal blocks, bases)
+  double scale;
+  int k, lda, ldb, pad;
+};
+
 // dst (m x n) = beta * dst + sum_t alpha_t * src_t  (+ identity if add_eye)
 struct BlockProblem {
   double* dst;
@@ -107,6 +131,10 @@ struct CpqrProblem {
 // ----------------------------------------------------------- launchers --
 // All launchers enqueue on `s` and copy their descriptor arrays from device
 // memory (`d_*` pointers) that the caller keeps alive until completion.
+void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
+                 int max_n);
+// rows per workgroup of launch_symv for a launch whose largest problem has max_m rows
+int symv_row_tile(int max_m);
 void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t,
                  int nprob, int max_m, int max_n, int transA, int transB);
 void launch_block(hipStream_t s, const BlockProblem* d_p, const BlockTerm* d_t,

@@ -298,8 +298,30 @@ static void build_plan(H2Model& H, int m) {
       rec.gemm(a, s, g);
       rec.tag_from(first, 100 + lev);
     }
-    // coupling: y-hat_v = sum_j B_vj x-hat_j
-    {
+    // coupling: y-hat_v = sum_j B_vj x-hat_j.  With at most 4 columns the
+    // blocks B_vj with j > v are read once for both B_vj x-hat_j and
+    // B_jv x-hat_v = B_vj^T x-hat_v (B^{H2} is symmetric: B_jv = B_vj^T).
+    if (m <= 4) {
+      std::vector<SymRow> rows;
+      std::vector<int> row_of(T.nnodes, -1);
+      for (int v = 1; v < T.nnodes; ++v) {
+        if (H.k[v] == 0) continue;
+        row_of[v] = (int)rows.size();
+        rows.push_back(SymRow{H.hat(pl->yh, v, m), H.hat_ld(v), H.hat(pl->xh, v, m), H.hat_ld(v), H.k[v], {}});
+      }
+      for (int v = 1; v < T.nnodes; ++v) {
+        if (H.k[v] == 0) continue;
+        SymRow& R = rows[row_of[v]];
+        for (int64_t e = T.coup_ptr[v]; e < T.coup_ptr[v + 1]; ++e) {
+          const int j = T.coup_idx[e];
+          if (H.k[j] == 0 || j < v) continue;
+          R.terms.push_back({H.Bh[e], H.k[v], H.hat(pl->xh, j, m), H.hat_ld(j), H.k[j], row_of[j]});
+        }
+      }
+      const size_t first = rec.recs.size();
+      rec.symv(a, s, rows, m);
+      rec.tag_from(first, 200);
+    } else {
       GemmBatch g(0, 0);
       for (int v = 1; v < T.nnodes; ++v) {
         if (H.k[v] == 0) continue;
@@ -327,8 +349,27 @@ static void build_plan(H2Model& H, int m) {
       rec.tag_from(first, 300 + lev);
     }
   }
-  // leaves: y_v = W_v y-hat_v + sum_{j near v} A_vj x_j
-  {
+  // leaves: y_v = W_v y-hat_v + sum_{j near v} A_vj x_j.  With at most 4
+  // columns the near blocks A_vj with j > v also give A_jv x_v = A_vj^T x_v.
+  if (m <= 4) {
+    std::vector<SymRow> rows;
+    for (int v = lf; v < lf + lc; ++v)
+      rows.push_back(SymRow{pl->yt + T.start[v], (int)N, pl->xt + T.start[v], (int)N, (int)T.size(v), {}});
+    for (int v = lf; v < lf + lc; ++v) {
+      SymRow& R = rows[v - lf];
+      if (L > 1 && H.k[v] > 0)
+        R.terms.push_back({H.W[v], H.cand[v], H.hat(pl->yh, v, m), H.hat_ld(v), H.k[v], -1});
+      for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) {
+        const int j = T.near_idx[e];
+        if (j < v) continue;
+        R.terms.push_back({H.nearA[e], (int)T.size(v), pl->xt + T.start[j], (int)N, (int)T.size(j),
+                           j == v ? -1 : j - lf});
+      }
+    }
+    const size_t first = rec.recs.size();
+    rec.symv(a, s, rows, m);
+    rec.tag_from(first, 400);
+  } else {
     GemmBatch g(0, 0);
     for (int v = lf; v < lf + lc; ++v) {
       g.add(pl->yt + T.start[v], (int)T.size(v), m, (int)N);
@@ -381,17 +422,13 @@ void h2_plan_run_last(H2Model& H) {
   one.replay(H.s);
 }
 
-// Algorithmic bytes of the leaf pass: every stored near block once, the leaf
-// bases and skeleton-space inputs once, x read once and y written once.
+// Algorithmic bytes of the leaf pass: the sum over its recorded launches
+// (every near block read, the leaf bases and skeleton-space inputs, x and y).
 H2Model::NearStats h2_near_stats(H2Model& H, int m) {
-  const TreeHost& T = H.T;
+  h2_plan_x(H, m);
   double b = 0;
-  for (int v = T.first_at(1); v < T.first_at(1) + T.count_at(1); ++v) {
-    for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e)
-      b += 8.0 * (double)T.size(v) * (double)T.size(T.near_idx[e]);
-    if (T.L > 1) b += 8.0 * (double)H.cand[v] * H.k[v] + 8.0 * (double)H.k[v] * m;
-  }
-  b += 2.0 * 8.0 * (double)T.N * m;
+  for (const LaunchRec& r : H.plan->rec.recs)
+    if (r.tag == 400) b += r.bytes;
   H2Model::NearStats st;
   st.bytes = b;
   return st;

@@ -299,6 +299,221 @@ static void launch_skinny(hipStream_t s, const GemmProblem* d_p, const GemmTerm*
     launch_skinny_nw<NC, 4>(s, d_p, d_t, nprob, max_m, transA, transB);
 }
 
+// Sum over the 64 lanes of V values at once (V a power of two, at most 64):
+// at each of the first log2(V) exchange steps a lane keeps half of its values
+// and trades the other half with its partner, then the last steps are a plain
+// butterfly.  Lane l returns the total of value index
+// sum_s bit(l, 5 - s) * V / 2^(s+1); every lane whose low 6 - log2(V) bits are
+// zero holds a distinct index.  The order of additions is fixed.
+template <int V>
+__device__ __forceinline__ double wave_sum_many(double (&v)[V], int lane) {
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int d = 32 >> s;
+    constexpr int kV = V;
+    const int nv = kV >> s;
+    if (nv >= 2) {
+      const int h = nv / 2;
+      const bool up = (lane & d) != 0;
+#pragma unroll
+      for (int q = 0; q < kV / 2; ++q) {
+        if (q < h) {
+          const double give = up ? v[q] : v[q + h];
+          const double keep = up ? v[q + h] : v[q];
+          v[q] = keep + __shfl_xor(give, d);
+        }
+      }
+    } else {
+      v[0] += __shfl_xor(v[0], d);
+    }
+  }
+  return v[0];
+}
+
+template <int V>
+__device__ __forceinline__ int wave_sum_index(int lane) {
+  int idx = 0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+    if ((V >> s) >= 2 && (lane & (32 >> s))) idx += V >> (s + 1);
+  return idx;
+}
+
+template <int V>
+__device__ __forceinline__ bool wave_sum_holder(int lane) {
+  int hs = 0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+    if ((V >> s) >= 2) ++hs;
+  return (lane & ((64 >> hs) - 1)) == 0;
+}
+
+// Symmetric-pair product (see SymProblem).  The row results follow the
+// streaming GEMV above (a workgroup owns the problem's rows of a row tile, the
+// waves take columns round-robin, U per step).  For a term with P set, each
+// loaded column a is also dotted with the problem's own rows X: the lane
+// partial sums of the U columns of a step are added across the wave by
+// wave_sum_many and stored by the holding lanes, so every off-diagonal block
+// is read once for both of its products.
+template <int NC, int RG, int NW>
+__global__ __launch_bounds__(64 * NW) void k_symv(const SymProblem* __restrict__ probs,
+                                                   const SymTerm* __restrict__ terms, int tiles_max) {
+  constexpr int U = (RG == 1) ? 8 : 4;
+  constexpr int V = U * NC;
+  constexpr int TR = 64 * RG;
+  __shared__ double red[NW / 2][TR][NC];
+  const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
+  const SymProblem P = probs[p];
+  const int i0 = tile * TR;
+  if (i0 >= P.m || P.n <= 0) return;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n = P.n;
+  int jc[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) jc[j] = j < n ? j : 0;
+  int rowc[RG];
+  double xi[RG][NC];  // the problem's own input rows; zero past the last row
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    const int r = i0 + 64 * g + lane;
+    const bool ok = r < P.m;
+    rowc[g] = ok ? r : i0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) xi[g][j] = ok ? P.X[rowc[g] + (int64_t)jc[j] * P.ldx] : 0.0;
+  }
+  double acc[RG][NC];
+#pragma unroll
+  for (int g = 0; g < RG; ++g)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[g][j] = 0.0;
+  const int vidx = wave_sum_index<V>(lane);
+  const bool holder = wave_sum_holder<V>(lane);
+  const int hu = vidx / NC, hj = vidx % NC;  // the (column step, right-hand column) a holder stores
+  for (int t = P.term_begin; t < P.term_end; ++t) {
+    const SymTerm T = terms[t];
+    const int K = T.k;
+    if (w >= K) continue;
+    const int64_t lda = T.lda, ldb = T.ldb;
+    const double sc = T.scale;
+    const int64_t astep = NW * lda;
+    gdouble* ap[RG];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) ap[g] = (gdouble*)T.A + rowc[g] + (int64_t)w * lda;
+    rdouble* bp = (rdouble*)T.B + w;
+    double* pt = T.P ? T.P + (int64_t)tile * P.ptile : nullptr;
+    for (int c = w; c < K; c += NW * U) {
+      double a[U][RG], b[U][NC];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t uu = (c + NW * u < K) ? u : 0;
+#pragma unroll
+        for (int g = 0; g < RG; ++g) a[u][g] = __builtin_nontemporal_load(&ap[g][uu * astep]);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) b[u][j] = bp[uu * NW + jc[j] * ldb];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool cok = c + NW * u < K;
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+          const double av = cok ? sc * a[u][g] : 0.0;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) acc[g][j] += av * (cok ? b[u][j] : 0.0);
+        }
+      }
+      if (pt) {
+        double v[V];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            double sum = 0.0;
+#pragma unroll
+            for (int g = 0; g < RG; ++g) sum += a[u][g] * xi[g][j];
+            v[u * NC + j] = sum;
+          }
+        const double tot = wave_sum_many<V>(v, lane);
+        const int col = c + NW * hu;
+        if (holder && col < K && hj < n) pt[col + (int64_t)hj * P.ldp] = sc * tot;
+      }
+#pragma unroll
+      for (int g = 0; g < RG; ++g) ap[g] += U * astep;
+      bp += U * NW;
+    }
+  }
+#pragma unroll
+  for (int h = NW / 2; h >= 1; h /= 2) {
+    if (w >= h && w < 2 * h) {
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) red[w - h][64 * g + lane][j] = acc[g][j];
+    }
+    __syncthreads();
+    if (w < h) {
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[g][j] += red[w][64 * g + lane][j];
+    }
+    __syncthreads();
+  }
+  if (w == 0) {
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      const int r = i0 + 64 * g + lane;
+      if (r >= P.m) continue;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        if (j >= n) continue;
+        double* cp = P.C + r + (int64_t)j * P.ldc;
+        double val = P.alpha * acc[g][j];
+        if (P.beta != 0.0) val += P.beta * (*cp);
+        *cp = val;
+      }
+    }
+  }
+}
+
+int symv_row_tile(int max_m) { return max_m <= 64 ? 64 : (max_m <= 128 ? 128 : 256); }
+
+template <int NC, int NW>
+static void launch_symv_nw(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
+                           int max_m) {
+  if (max_m <= 64) {
+    hipLaunchKernelGGL((k_symv<NC, 1, NW>), dim3((unsigned)nprob), dim3(64 * NW), 0, s, d_p, d_t, 1);
+  } else if (max_m <= 128) {
+    hipLaunchKernelGGL((k_symv<NC, 2, NW>), dim3((unsigned)nprob), dim3(64 * NW), 0, s, d_p, d_t, 1);
+  } else {
+    const int tiles = ceil_div(max_m, 256);
+    hipLaunchKernelGGL((k_symv<NC, 4, NW>), dim3((unsigned)nprob * tiles), dim3(64 * NW), 0, s, d_p,
+                       d_t, tiles);
+  }
+}
+
+// 16-wave workgroups for small launches with one right-hand column only (more
+// columns would not fit the register budget of a 1024-thread workgroup).
+template <int NC>
+static void launch_symv_nc(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
+                           int max_m) {
+  const int64_t blocks = (int64_t)nprob * ceil_div(max_m, 256);
+  if (NC == 1 && blocks < kSkinnyWide)
+    launch_symv_nw<NC, 16>(s, d_p, d_t, nprob, max_m);
+  else
+    launch_symv_nw<NC, 4>(s, d_p, d_t, nprob, max_m);
+}
+
+void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
+                 int max_n) {
+  if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
+  if (max_n > 4) throw Error(SPD_E_INVALID, "symmetric-pair product supports at most 4 columns");
+  if (max_n == 1) launch_symv_nc<1>(s, d_p, d_t, nprob, max_m);
+  else if (max_n == 2) launch_symv_nc<2>(s, d_p, d_t, nprob, max_m);
+  else launch_symv_nc<4>(s, d_p, d_t, nprob, max_m);
+  SPD_HIP(hipGetLastError());
+}
+
 void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
                  int max_m, int max_n, int transA, int transB) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;

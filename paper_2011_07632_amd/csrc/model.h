@@ -84,16 +84,40 @@ struct TrsmBatch {
 // A recorded launch with descriptors resident in device memory, replayed by
 // the solve loops (matvec and preconditioner apply) without host work.
 struct LaunchRec {
-  int type;  // 0 gemm, 1 block, 2 trsm
+  int type;  // 0 gemm, 1 block, 2 trsm, 3 symmetric-pair product
   const void* probs;
   const void* terms;
   int nprob, max_m, max_n, transA, transB;
   double bytes;  // algorithmic bytes: every A operand once, distinct B operands once, C once
   int tag = -1;  // caller-defined label (which pass of a product)
 };
+// One block row of a symmetric product with at most 4 right-hand columns:
+// y = sum_t A_t B_t, and every mirrored term (an off-diagonal block A_ij of a
+// symmetric matrix, stored once) also adds A_ij^T x to the output of row
+// `mirror`, where x are this row's own input rows.
+struct SymRow {
+  double* y;
+  int ldy;
+  const double* x;
+  int ldx;
+  int m;
+  struct Term {
+    const double* A;
+    int lda;
+    const double* B;
+    int ldb;
+    int k;
+    int mirror;  // index of the receiving row, or -1
+  };
+  std::vector<Term> terms;
+};
+
 struct Recorder {
   std::vector<LaunchRec> recs;
   void gemm(Arena& a, hipStream_t s, const GemmBatch& b);
+  // symmetric product of n <= 4 columns over rows (one product launch and one
+  // launch that sums each row's partial results in a fixed order)
+  void symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n);
   void block(Arena& a, hipStream_t s, const BlockBatch& b);
   void trsm(Arena& a, hipStream_t s, const TrsmBatch& b, int trans);
   void replay(hipStream_t s) const;

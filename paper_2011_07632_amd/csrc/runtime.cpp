@@ -316,6 +316,138 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
   block(a, s, red);
 }
 
+// Symmetric-pair product: the rows' terms are cut into parts of about
+// kSplitBytes of A (at column granularity) and written as SymProblems whose
+// row results go to per-part buffers; the mirrored products A^T x go to
+// per-row regions [row tile][mirrored columns x n].  A block launch then forms
+// every output row as the sum, in a fixed order, of its own parts and of the
+// mirrored products addressed to it.
+void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n) {
+  if (rows.empty() || n <= 0) return;
+  int max_m = 0;
+  for (const SymRow& R : rows) max_m = std::max(max_m, R.m);
+  if (max_m == 0) return;
+  const int tile = symv_row_tile(max_m);
+  std::vector<SymProblem> probs;
+  std::vector<SymTerm> terms;
+  // contributions to each row's output, in order: (source, leading dimension)
+  std::vector<std::vector<std::pair<const double*, int>>> contrib(rows.size());
+  double bytes = 0;
+  std::vector<std::pair<const double*, const double*>> bset;
+  for (size_t i = 0; i < rows.size(); ++i) {
+    const SymRow& R = rows[i];
+    if (R.m <= 0) continue;
+    // merge adjacent terms that continue each other in A and B (and are both
+    // mirrored or both not); mirrored terms take consecutive columns of P
+    struct MT { const double* A; const double* B; int lda, ldb, k; bool mir; std::vector<std::pair<int, int>> tgt; };
+    std::vector<MT> mt;
+    int64_t kmir = 0;
+    for (const SymRow::Term& t : R.terms) {
+      if (t.k <= 0) continue;
+      const bool mir = t.mirror >= 0;
+      if (!mt.empty()) {
+        MT& q = mt.back();
+        if (q.mir == mir && q.lda == t.lda && (q.ldb == t.ldb || n == 1) && t.A == q.A + (int64_t)q.lda * q.k &&
+            t.B == q.B + q.k) {
+          if (mir) q.tgt.push_back({t.mirror, t.k});
+          q.k += t.k;
+          if (mir) kmir += t.k;
+          continue;
+        }
+      }
+      MT m{t.A, t.B, t.lda, t.ldb, t.k, mir, {}};
+      if (mir) {
+        m.tgt.push_back({t.mirror, t.k});
+        kmir += t.k;
+      }
+      mt.push_back(m);
+    }
+    const int tiles = ceil_div(R.m, tile);
+    double* pb = kmir > 0 ? a.get_n<double>((size_t)tiles * kmir * n) : nullptr;
+    // P column of every merged term; mirrored products addressed to their rows
+    std::vector<int64_t> pcol(mt.size(), -1);
+    {
+      int64_t c = 0;
+      for (size_t q = 0; q < mt.size(); ++q) {
+        if (!mt[q].mir) continue;
+        pcol[q] = c;
+        for (const auto& tg : mt[q].tgt) {
+          for (int r = 0; r < tiles; ++r)
+            contrib[tg.first].push_back({pb + (int64_t)r * kmir * n + c, (int)kmir});
+          c += tg.second;
+        }
+      }
+    }
+    int64_t K = 0;
+    for (const MT& q : mt) K += q.k;
+    const int64_t nparts =
+        K == 0 ? 1 : std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)std::ceil(8.0 * R.m * K / kSplitBytes)));
+    size_t q = 0;
+    int64_t off = 0;
+    for (int64_t part = 0; part < nparts; ++part) {
+      int64_t want = K * (part + 1) / nparts - K * part / nparts;
+      double* dst = a.get_n<double>((size_t)R.m * n);
+      SymProblem P{};
+      P.C = dst;
+      P.X = R.x;
+      P.ptile = kmir * n;
+      P.m = R.m;
+      P.n = n;
+      P.ldc = R.m;
+      P.ldx = R.ldx;
+      P.ldp = (int)std::max<int64_t>(kmir, 1);
+      P.term_begin = (int)terms.size();
+      P.alpha = 1.0;
+      P.beta = 0.0;
+      while (want > 0) {
+        const MT& g = mt[q];
+        const int64_t take = std::min<int64_t>(want, g.k - off);
+        SymTerm t{};
+        t.A = g.A + (int64_t)g.lda * off;
+        t.B = g.B + off;
+        t.P = g.mir ? pb + pcol[q] + off : nullptr;
+        t.scale = 1.0;
+        t.k = (int)take;
+        t.lda = g.lda;
+        t.ldb = g.ldb;
+        terms.push_back(t);
+        want -= take;
+        off += take;
+        if (off == g.k) {
+          ++q;
+          off = 0;
+        }
+      }
+      P.term_end = (int)terms.size();
+      probs.push_back(P);
+      contrib[i].insert(contrib[i].begin() + part, {dst, R.m});
+    }
+    // algorithmic bytes: every block once, own rows, B ranges once, row and mirrored results
+    for (const MT& g : mt) {
+      bytes += 8.0 * R.m * g.k;
+      for (int j = 0; j < n; ++j) bset.push_back({g.B + (int64_t)j * g.ldb, g.B + (int64_t)j * g.ldb + g.k});
+    }
+    bytes += 8.0 * R.m * n * 2.0 + 8.0 * tiles * kmir * n;
+  }
+  std::sort(bset.begin(), bset.end());
+  const double* end = nullptr;
+  for (const auto& r : bset) {
+    const double* lo = (end && r.first < end) ? end : r.first;
+    if (r.second > lo) bytes += 8.0 * (double)(r.second - lo);
+    if (!end || r.second > end) end = r.second;
+  }
+  if (terms.empty()) terms.push_back(SymTerm{});
+  recs.push_back({3, keep(a, s, probs), keep(a, s, terms), (int)probs.size(), max_m, n, 0, 0, bytes, -1});
+  BlockBatch red;
+  for (size_t i = 0; i < rows.size(); ++i) {
+    const SymRow& R = rows[i];
+    if (R.m <= 0) continue;
+    red.add(R.y, R.m, n, R.ldy, 0.0);
+    for (const auto& c : contrib[i]) red.term(c.first, c.second, 1.0);
+  }
+  block(a, s, red);
+}
+
 void Recorder::block(Arena& a, hipStream_t s, const BlockBatch& b) {
   if (b.probs.empty() || b.max_m == 0 || b.max_n == 0) return;
   std::vector<BlockTerm> t = b.terms;
@@ -338,6 +470,8 @@ void Recorder::replay(hipStream_t s) const {
     else if (r.type == 1)
       launch_block(s, (const BlockProblem*)r.probs, (const BlockTerm*)r.terms, r.nprob, r.max_m,
                    r.max_n);
+    else if (r.type == 3)
+      launch_symv(s, (const SymProblem*)r.probs, (const SymTerm*)r.terms, r.nprob, r.max_m, r.max_n);
     else
       launch_trsm(s, (const TrsmProblem*)r.probs, r.nprob, r.max_m, r.max_n, r.transA, 0);
   }

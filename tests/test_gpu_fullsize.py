@@ -1,0 +1,112 @@
+"""The HIP path at the full size of the benchmarked workload (Matern-3/2,
+l = 0.1, sigma = 1e-4, N = 100,000 points in the unit cube, leaf 200), in the
+launch configuration the benchmark times (GPU).
+
+The oracle cannot build this size in a test's time, so the checks are the ones
+that hold at any size: exact structure of the tree and lists, sampled rows of
+the product against rows of sigma*I + K computed one by one, agreement of the
+two product paths (symmetric-pair streaming for at most 4 columns, MFMA batch
+for more), symmetry and positivity of the preconditioner, and PCG reaching its
+tolerance with the true residual."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import kernels as okern
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+W = workloads.MEDIUM
+
+
+class Full:
+    def __init__(self):
+        from paper_2011_07632_amd import binding as B
+        print(f"\n[fullsize] {W.name}: N={W.n}", flush=True)
+        self.B = B
+        self.X = W.points()
+        self.h2 = B.h2_build(torch.from_numpy(self.X).cuda(), W.kernel, W.ell, W.shift, leaf=W.leaf,
+                             tol=W.h2_tol, eta=W.eta)
+        self.hss = B.spdhss_build(self.h2, W.hss_tol, W.max_rank, W.oversample,
+                                  omega=B.cols_like(W.n, W.s, "cuda").copy_(torch.from_numpy(W.omega())))
+        self.ulv = B.ulv_factor(self.hss)
+        print("[fullsize] built", flush=True)
+
+
+_full = []
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    if not _full:
+        _full.append(Full())
+    return _full[0]
+
+
+def cols(F, a):
+    return F.B.cols_like(W.n, a.shape[1], "cuda").copy_(torch.from_numpy(np.ascontiguousarray(a)))
+
+
+def test_tree_and_lists_structure(F):
+    perm = F.h2.perm()
+    assert np.array_equal(np.sort(perm), np.arange(W.n))
+    start = F.h2.node_start()
+    nn = F.h2.nnodes
+    L = F.h2.levels
+    first_leaf = (1 << (L - 1)) - 1
+    sizes = np.diff(start)[first_leaf:nn]
+    assert sizes.max() - sizes.min() <= 1
+    near, coup = F.h2.lists()
+    for v in range(nn):
+        assert v not in coup[v]
+        for j in coup[v]:
+            assert v in coup[j], (v, j)
+        for j in near[v]:
+            assert v in near[j], (v, j)
+
+
+def test_matvec_rows_against_kernel(F):
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((W.n, 1))
+    y = F.B.h2_matvec(F.h2, cols(F, x)).cpu().numpy()[:, 0]
+    rows = rng.choice(W.n, size=400, replace=False)
+    ref = okern.evaluate(W.kernel, W.ell, F.X[rows], F.X) @ x[:, 0] + W.shift * x[rows, 0]
+    err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
+    print(f"[fullsize] sampled-row error of the H^2 product vs sigma*I + K: {err:.2e}", flush=True)
+    # The tolerance is the per-node truncation threshold of the proxy ID; the
+    # realized error of the default proxy set (8 shells of 128 points) at this
+    # size is 5.3e-5 (denser proxy sets reach 2.6e-6 at 8 x 256).  The bound
+    # guards that value.
+    assert err <= 1e-4
+
+
+def test_symmetric_and_batched_products_agree(F):
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((W.n, 5))
+    y5 = F.B.h2_matvec(F.h2, cols(F, x)).cpu().numpy()
+    for c in (0, 3):
+        y1 = F.B.h2_matvec(F.h2, cols(F, x[:, c:c + 1])).cpu().numpy()[:, 0]
+        d = np.linalg.norm(y1 - y5[:, c]) / np.linalg.norm(y5[:, c])
+        assert d <= 1e-13, (c, d)
+
+
+def test_preconditioner_symmetric_positive(F):
+    rng = np.random.default_rng(13)
+    uv = rng.standard_normal((W.n, 2))
+    Mi = F.B.ulv_apply(F.ulv, cols(F, uv)).cpu().numpy()
+    a = uv[:, 0] @ Mi[:, 1]
+    b = uv[:, 1] @ Mi[:, 0]
+    scale = np.sqrt(abs(uv[:, 0] @ Mi[:, 0]) * abs(uv[:, 1] @ Mi[:, 1]))
+    assert abs(a - b) <= 1e-10 * scale
+    assert uv[:, 0] @ Mi[:, 0] > 0 and uv[:, 1] @ Mi[:, 1] > 0
+
+
+def test_pcg_reaches_tolerance(F):
+    b = cols(F, W.rhs())
+    x, it, res = F.B.pcg_solve(F.h2, F.ulv, b, rtol=W.pcg_tol, maxit=20000)
+    print(f"[fullsize] PCG iterations {it.tolist()} true relative residual {res.tolist()}", flush=True)
+    assert int(it.max()) < 20000
+    assert float(res.max()) <= 2 * W.pcg_tol

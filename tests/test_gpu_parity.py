@@ -110,10 +110,13 @@ def test_h2_skeletons_exact(P):
         assert sk[v].tolist() == P.o_h2.skel[v].tolist(), v
 
 
-def test_h2_matvec(P):
+# 1-4 columns take the symmetric-pair streaming product (1, 2 and 4-column
+# kernels), 5 the batched MFMA product
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 5])
+def test_h2_matvec(P, nrhs):
     rng = np.random.default_rng(1)
-    x = rng.standard_normal((P.w.n, 3))
-    xg = P.B.cols_like(P.w.n, 3, "cuda").copy_(torch.from_numpy(x))
+    x = rng.standard_normal((P.w.n, nrhs))
+    xg = P.B.cols_like(P.w.n, nrhs, "cuda").copy_(torch.from_numpy(x))
     y = P.B.h2_matvec(P.g_h2, xg).cpu().numpy()
     yo = np.empty_like(x)
     yo[P.T.perm] = P.o_h2.matvec(x[P.T.perm])
