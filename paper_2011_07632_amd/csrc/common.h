@@ -36,17 +36,28 @@ void set_last_error(const std::string& msg);
 // ------------------------------------------------------------ descriptors --
 // C = beta * C + alpha * sum_t op(A_t) op(B_t); all terms of a problem share
 // (m, n); each term has its own inner size k.  Column-major storage.
+// C = alpha * sum_t scale_t op(A_t) op(B_t) + beta * C (+ D).  The index and
+// addend fields are for products with at most 4 columns (the streaming kernel)
+// and are null otherwise:
+//   cidx: row r of C is row cidx[r] of the C array (scatter);
+//   D, didx, ldd: D row (didx ? didx[r] : r) is added to C row r;
+//   bidx: row c of B is row bidx[c] of the B array (gather; B not transposed).
 struct GemmProblem {
   double* C;
   int m, n, ldc;
   int term_begin, term_end;
   double alpha, beta;
+  const int* cidx;
+  const double* D;
+  const int* didx;
+  int ldd, pad;
 };
 struct GemmTerm {
   const double* A;
   const double* B;
   double scale;  // multiplies this term's product
   int k, lda, ldb, pad;
+  const int* bidx;
 };
 
 // Symmetric-pair product for at most 4 right-hand columns.  For every term t

@@ -53,6 +53,9 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
   H.cand_h.assign(nn, {});
   H.skel_h.assign(nn, {});
   H.W.assign(nn, nullptr);
+  H.piv_d.assign(nn, nullptr);
+  H.E.assign(nn, nullptr);
+  H.ET.assign(nn, nullptr);
   {
     std::vector<int> pos(n);
     std::iota(pos.begin(), pos.end(), 0);
@@ -141,17 +144,29 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
       }
       tb.run(s, st, 1, 1);
       std::vector<std::vector<int>> pivh(nj);
+      BlockBatch ecp;  // E_v and E_v^T, kept for the streaming product
       for (int q = 0; q < nj; ++q) {
         const int v = jobs[i + q].v, c = H.cand[v], mr = std::min(P, c), k = ranks[q];
         H.k[v] = k;
         if (k > 0) {
           H.W[v] = H.arena.get_n<double>((size_t)c * k);
           launch_scatter_interp(s, H.W[v], c, Rp[q] + (size_t)k * mr, mr, pivp[q], c, k);
+          H.piv_d[v] = H.arena.get_n<int>(c);
+          SPD_HIP(hipMemcpyAsync(H.piv_d[v], pivp[q], c * sizeof(int), hipMemcpyDeviceToDevice, s));
+          if (c > k) {
+            H.E[v] = H.arena.get_n<double>((size_t)k * (c - k));
+            H.ET[v] = H.arena.get_n<double>((size_t)k * (c - k));
+            ecp.add(H.E[v], k, c - k, k);
+            ecp.term(Rp[q] + (size_t)k * mr, mr);
+            ecp.add(H.ET[v], c - k, k, c - k);
+            ecp.term(Rp[q] + (size_t)k * mr, mr, 1.0, 1);
+          }
         }
         pivh[q].resize(k);
         if (k > 0)
           SPD_HIP(hipMemcpyAsync(pivh[q].data(), pivp[q], k * sizeof(int), hipMemcpyDeviceToHost, s));
       }
+      ecp.run(s, st);
       SPD_HIP(hipStreamSynchronize(s));
       st.reset();
       for (int q = 0; q < nj; ++q) {
@@ -282,17 +297,27 @@ static void build_plan(H2Model& H, int m) {
   pl->yh = a.get_n<double>((size_t)std::max<int64_t>(H.stack_rows, 1) * m);
   Recorder& rec = pl->rec;
   const int lf = T.first_at(1), lc = T.count_at(1);
+  // With at most 4 columns the interpolation W_v = Pi_v [I; E_v^T] is applied
+  // in that form: the identity rows are a gather (upward) or scatter
+  // (downward) of the vector, and only E_v is streamed.
+  const bool eform = m <= 4;
   if (L > 1) {
     // upward: x-hat_v = W_v^T x_v (leaf) or W_v^T [x-hat_c1; x-hat_c2]
+    //         = x[Pi_v(0:k)] + E_v x[Pi_v(k:cand)]
     for (int lev = 1; lev < L; ++lev) {
       GemmBatch g(0, 0);
       for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
         if (H.k[v] == 0) continue;
-        g.add(H.hat(pl->xh, v, m), H.k[v], m, H.hat_ld(v));
-        if (lev == 1)
-          g.term(H.WT[v], H.k[v], pl->xt + T.start[v], (int)N, H.cand[v]);
-        else
-          g.term(H.WT[v], H.k[v], pl->xh + H.par_off[v] * m, H.cand[v], H.cand[v]);
+        const double* xin = lev == 1 ? pl->xt + T.start[v] : pl->xh + H.par_off[v] * m;
+        const int ldin = lev == 1 ? (int)N : H.cand[v];
+        if (eform) {
+          const int k = H.k[v], c = H.cand[v];
+          g.add_indexed(H.hat(pl->xh, v, m), k, m, H.hat_ld(v), 0.0, nullptr, xin, H.piv_d[v], ldin);
+          if (c > k) g.term_gathered(H.E[v], k, xin, ldin, H.piv_d[v] + k, c - k);
+        } else {
+          g.add(H.hat(pl->xh, v, m), H.k[v], m, H.hat_ld(v));
+          g.term(H.WT[v], H.k[v], xin, ldin, H.cand[v]);
+        }
       }
       const size_t first = rec.recs.size();
       rec.gemm(a, s, g);
@@ -336,29 +361,53 @@ static void build_plan(H2Model& H, int m) {
       rec.gemm(a, s, g);
       rec.tag_from(first, 200);
     }
-    // downward: [y-hat_c1; y-hat_c2] += W_v y-hat_v
-    for (int lev = L - 1; lev >= 2; --lev) {
+    // downward: [y-hat_c1; y-hat_c2] += W_v y-hat_v; with the E form the
+    // skeleton rows Pi_v(0:k) receive y-hat_v and the others E_v^T y-hat_v.
+    // The E form continues to the leaves (level 1), where W_v y-hat_v is the
+    // far-field part of y_v; the leaf pass then adds the near field.
+    for (int lev = L - 1; lev >= (eform ? 1 : 2); --lev) {
       GemmBatch g(0, 0);
       for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
-        if (H.k[v] == 0 || H.cand[v] == 0) continue;
-        g.add(pl->yh + H.par_off[v] * m, H.cand[v], m, H.cand[v], 1.0);
-        g.term(H.W[v], H.cand[v], H.hat(pl->yh, v, m), H.hat_ld(v), H.k[v]);
+        const bool leaf = lev == 1;
+        double* yout = leaf ? pl->yt + T.start[v] : pl->yh + H.par_off[v] * m;
+        const int ldout = leaf ? (int)N : H.cand[v];
+        const double beta = leaf ? 0.0 : 1.0;
+        const int k = H.k[v], c = H.cand[v];
+        if (eform) {
+          if (k == 0) {
+            if (leaf) g.add((double*)yout, (int)T.size(v), m, ldout);  // no far field: zero rows
+            continue;
+          }
+          g.add_indexed(yout, k, m, ldout, beta, H.piv_d[v], H.hat(pl->yh, v, m), nullptr, H.hat_ld(v));
+          if (c > k) {
+            g.add_indexed(yout, c - k, m, ldout, beta, H.piv_d[v] + k, nullptr, nullptr, 0);
+            g.term(H.ET[v], c - k, H.hat(pl->yh, v, m), H.hat_ld(v), k);
+          }
+        } else {
+          if (k == 0 || c == 0) continue;
+          g.add(yout, c, m, ldout, 1.0);
+          g.term(H.W[v], c, H.hat(pl->yh, v, m), H.hat_ld(v), k);
+        }
       }
       const size_t first = rec.recs.size();
       rec.gemm(a, s, g);
       rec.tag_from(first, 300 + lev);
     }
   }
+  if (eform && L == 1) {  // a single leaf: no far field
+    GemmBatch g(0, 0);
+    g.add(pl->yt, (int)N, m, (int)N);
+    rec.gemm(a, s, g);
+  }
   // leaves: y_v = W_v y-hat_v + sum_{j near v} A_vj x_j.  With at most 4
   // columns the near blocks A_vj with j > v also give A_jv x_v = A_vj^T x_v.
-  if (m <= 4) {
+  if (eform) {
+    // the far-field part of y is already in place (downward pass at level 1)
     std::vector<SymRow> rows;
     for (int v = lf; v < lf + lc; ++v)
       rows.push_back(SymRow{pl->yt + T.start[v], (int)N, pl->xt + T.start[v], (int)N, (int)T.size(v), {}});
     for (int v = lf; v < lf + lc; ++v) {
       SymRow& R = rows[v - lf];
-      if (L > 1 && H.k[v] > 0)
-        R.terms.push_back({H.W[v], H.cand[v], H.hat(pl->yh, v, m), H.hat_ld(v), H.k[v], -1});
       for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) {
         const int j = T.near_idx[e];
         if (j < v) continue;
@@ -367,7 +416,7 @@ static void build_plan(H2Model& H, int m) {
       }
     }
     const size_t first = rec.recs.size();
-    rec.symv(a, s, rows, m);
+    rec.symv(a, s, rows, m, 1.0);
     rec.tag_from(first, 400);
   } else {
     GemmBatch g(0, 0);

@@ -138,8 +138,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem* __restrict__ pr
 // problem (lane l of row group g owns row i0 + 64 g + l), so every column of a
 // block is read by one workgroup only: no cache line is fetched by two
 // workgroups, which may sit on different XCDs with separate L2s.  The waves
-// take the columns of each term round-robin (wave w reads columns w, w+NW,
-// ...), U columns per step, all loads of a step issued back to back; in the
+// take the columns of each term in runs of U adjacent columns (a step of the
+// workgroup covers NW*U adjacent columns, wave w reading run w), so a cache
+// line shared by adjacent columns is read within one wave's step; all loads
+// of a step are issued back to back; in the
 // last step of a term, out-of-range columns load from an in-range address and
 // are zeroed afterwards.  Small launches use 16 waves per workgroup so that
 // each wave's chain of dependent memory round trips stays short.  The NW
@@ -179,26 +181,36 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_skinny(const GemmProblem* __re
   for (int t = P.term_begin; t < P.term_end; ++t) {
     const GemmTerm T = terms[t];
     const int K = T.k;
-    if (w >= K) continue;
+    if (w * U >= K) continue;
     const int64_t lda = T.lda, ldb = T.ldb;
     const double sc = T.scale;
     // op(A)(r, c) = transA ? A[c + r lda] : A[r + c lda];  op(B)(c, j) likewise
     const int64_t acs = transA ? 1 : lda, ars = transA ? lda : 1;
     const int64_t bcs = transB ? ldb : 1, bjs = transB ? 1 : ldb;
-    const int64_t astep = NW * acs, bstep = NW * bcs;
+    const int64_t astep = acs, bstep = bcs;
     gdouble* ap[RG];
 #pragma unroll
-    for (int g = 0; g < RG; ++g) ap[g] = (gdouble*)T.A + (int64_t)rowc[g] * ars + (int64_t)w * acs;
-    rdouble* bp = (rdouble*)T.B + (int64_t)w * bcs;
-    int c = w;  // this wave's next column; a step reads c, c + NW, ..., c + NW (U - 1)
-    for (; c + NW * (U - 1) < K; c += NW * U) {
+    for (int g = 0; g < RG; ++g) ap[g] = (gdouble*)T.A + (int64_t)rowc[g] * ars + (int64_t)w * U * acs;
+    rdouble* bp = (rdouble*)T.B + (int64_t)w * U * bcs;
+    // gathered B: row c of B is row bidx[c] of T.B
+    const int __attribute__((address_space(4)))* bix =
+        T.bidx ? (const int __attribute__((address_space(4)))*)T.bidx + w * U : nullptr;
+    rdouble* B0 = (rdouble*)T.B;
+    int c = w * U;  // this wave's next column; a step reads columns c, ..., c + U - 1
+    for (; c + U - 1 < K; c += NW * U) {
       double a[U][RG], b[U][NC];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
 #pragma unroll
         for (int g = 0; g < RG; ++g) a[u][g] = __builtin_nontemporal_load(&ap[g][u * astep]);
+        if (bix) {
+          const int64_t row = bix[u];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) b[u][j] = bp[u * bstep + jc[j] * bjs];
+          for (int j = 0; j < NC; ++j) b[u][j] = B0[row + jc[j] * bjs];
+        } else {
+#pragma unroll
+          for (int j = 0; j < NC; ++j) b[u][j] = bp[u * bstep + jc[j] * bjs];
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -209,22 +221,29 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_skinny(const GemmProblem* __re
           for (int j = 0; j < NC; ++j) acc[g][j] += av * b[u][j];
         }
 #pragma unroll
-      for (int g = 0; g < RG; ++g) ap[g] += U * astep;
-      bp += U * bstep;
+      for (int g = 0; g < RG; ++g) ap[g] += NW * U * astep;
+      bp += NW * U * bstep;
+      if (bix) bix += U * NW;
     }
     if (c < K) {  // fewer than U columns left: clamp to column c, zero afterwards
       double a[U][RG], b[U][NC];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t uu = (c + NW * u < K) ? u : 0;
+        const int64_t uu = (c + u < K) ? u : 0;
 #pragma unroll
         for (int g = 0; g < RG; ++g) a[u][g] = __builtin_nontemporal_load(&ap[g][uu * astep]);
+        if (bix) {
+          const int64_t row = bix[uu];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) b[u][j] = bp[uu * bstep + jc[j] * bjs];
+          for (int j = 0; j < NC; ++j) b[u][j] = B0[row + jc[j] * bjs];
+        } else {
+#pragma unroll
+          for (int j = 0; j < NC; ++j) b[u][j] = bp[uu * bstep + jc[j] * bjs];
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const bool cok = c + NW * u < K;
+        const bool cok = c + u < K;
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
           const double av = cok ? sc * a[u][g] : 0.0;
@@ -257,12 +276,15 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_skinny(const GemmProblem* __re
     for (int g = 0; g < RG; ++g) {
       const int r = i0 + 64 * g + lane;
       if (r >= P.m) continue;
+      const int64_t rc = P.cidx ? P.cidx[r] : r;
+      const int64_t rd = P.didx ? P.didx[r] : r;
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         if (j >= n) continue;
-        double* cp = P.C + r + (int64_t)j * P.ldc;
+        double* cp = P.C + rc + (int64_t)j * P.ldc;
         double val = P.alpha * acc[g][j];
         if (P.beta != 0.0) val += P.beta * (*cp);
+        if (P.D) val += P.D[rd + (int64_t)j * P.ldd];
         *cp = val;
       }
     }
@@ -350,7 +372,7 @@ __device__ __forceinline__ bool wave_sum_holder(int lane) {
 
 // Symmetric-pair product (see SymProblem).  The row results follow the
 // streaming GEMV above (a workgroup owns the problem's rows of a row tile, the
-// waves take columns round-robin, U per step).  For a term with P set, each
+// waves take runs of U adjacent columns).  For a term with P set, each
 // loaded column a is also dotted with the problem's own rows X: the lane
 // partial sums of the U columns of a step are added across the wave by
 // wave_sum_many and stored by the holding lanes, so every off-diagonal block
@@ -393,28 +415,28 @@ __global__ __launch_bounds__(64 * NW) void k_symv(const SymProblem* __restrict__
   for (int t = P.term_begin; t < P.term_end; ++t) {
     const SymTerm T = terms[t];
     const int K = T.k;
-    if (w >= K) continue;
+    if (w * U >= K) continue;
     const int64_t lda = T.lda, ldb = T.ldb;
     const double sc = T.scale;
-    const int64_t astep = NW * lda;
+    const int64_t astep = lda;
     gdouble* ap[RG];
 #pragma unroll
-    for (int g = 0; g < RG; ++g) ap[g] = (gdouble*)T.A + rowc[g] + (int64_t)w * lda;
-    rdouble* bp = (rdouble*)T.B + w;
+    for (int g = 0; g < RG; ++g) ap[g] = (gdouble*)T.A + rowc[g] + (int64_t)w * U * lda;
+    rdouble* bp = (rdouble*)T.B + w * U;
     double* pt = T.P ? T.P + (int64_t)tile * P.ptile : nullptr;
-    for (int c = w; c < K; c += NW * U) {
+    for (int c = w * U; c < K; c += NW * U) {
       double a[U][RG], b[U][NC];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t uu = (c + NW * u < K) ? u : 0;
+        const int64_t uu = (c + u < K) ? u : 0;
 #pragma unroll
         for (int g = 0; g < RG; ++g) a[u][g] = __builtin_nontemporal_load(&ap[g][uu * astep]);
 #pragma unroll
-        for (int j = 0; j < NC; ++j) b[u][j] = bp[uu * NW + jc[j] * ldb];
+        for (int j = 0; j < NC; ++j) b[u][j] = bp[uu + jc[j] * ldb];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const bool cok = c + NW * u < K;
+        const bool cok = c + u < K;
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
           const double av = cok ? sc * a[u][g] : 0.0;
@@ -434,11 +456,11 @@ __global__ __launch_bounds__(64 * NW) void k_symv(const SymProblem* __restrict__
             v[u * NC + j] = sum;
           }
         const double tot = wave_sum_many<V>(v, lane);
-        const int col = c + NW * hu;
+        const int col = c + hu;
         if (holder && col < K && hj < n) pt[col + (int64_t)hj * P.ldp] = sc * tot;
       }
 #pragma unroll
-      for (int g = 0; g < RG; ++g) ap[g] += U * astep;
+      for (int g = 0; g < RG; ++g) ap[g] += NW * U * lda;
       bp += U * NW;
     }
   }

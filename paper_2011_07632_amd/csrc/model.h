@@ -61,6 +61,12 @@ struct GemmBatch {
   explicit GemmBatch(int ta = 0, int tb = 0) : transA(ta), transB(tb) {}
   void add(double* C, int m, int n, int ldc, double beta = 0.0, double alpha = 1.0);
   void term(const double* A, int lda, const double* B, int ldb, int k, double scale = 1.0);
+  // indexed forms (at most 4 columns): scattered C rows and an addend D with
+  // optional row gather; a term whose B rows are gathered through bidx
+  void add_indexed(double* C, int m, int n, int ldc, double beta, const int* cidx, const double* D,
+                   const int* didx, int ldd);
+  void term_gathered(const double* A, int lda, const double* B, int ldb, const int* bidx, int k);
+  bool indexed = false;
   void run(hipStream_t s, Stage& st);
   bool empty() const { return probs.empty(); }
 };
@@ -116,8 +122,9 @@ struct Recorder {
   std::vector<LaunchRec> recs;
   void gemm(Arena& a, hipStream_t s, const GemmBatch& b);
   // symmetric product of n <= 4 columns over rows (one product launch and one
-  // launch that sums each row's partial results in a fixed order)
-  void symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n);
+  // launch that sums each row's partial results in a fixed order into
+  // y = beta * y + sum)
+  void symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n, double beta = 0.0);
   void block(Arena& a, hipStream_t s, const BlockBatch& b);
   void trsm(Arena& a, hipStream_t s, const TrsmBatch& b, int trans);
   void replay(hipStream_t s) const;
@@ -144,6 +151,10 @@ struct H2Model {
   std::vector<std::vector<int>> skel_h;  // skeleton of every node (tree positions)
   std::vector<double*> W;         // U_v (leaf) or R_v (nonleaf): cand_v x k_v, ld cand_v
   std::vector<double*> WT;        // W_v^T (k_v x cand_v, ld k_v): coalesced upward pass
+  // W_v = Pi_v [I; E_v^T]: the ID's column order Pi_v (cand_v positions, the
+  // skeleton first) and E_v = R11^{-1} R12 (k_v x (cand_v - k_v)) and its transpose
+  std::vector<int*> piv_d;
+  std::vector<double*> E, ET;
   std::vector<double*> Bh;        // per coupling entry: K(skel_i, skel_j), k_i x k_j
   std::vector<double*> nearA;     // per leaf near entry: n_i x n_j, ld n_i
   double times[4] = {0, 0, 0, 0};

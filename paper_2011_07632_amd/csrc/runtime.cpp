@@ -126,7 +126,7 @@ void GemmBatch::add(double* C, int m, int n, int ldc, double beta, double alpha)
 void GemmBatch::term(const double* A, int lda, const double* B, int ldb, int k, double scale) {
   if (k <= 0) return;
   GemmProblem& p = probs.back();
-  if (p.term_end > p.term_begin) {
+  if (p.term_end > p.term_begin && !terms.back().bidx) {
     GemmTerm& q = terms.back();
     const int64_t acs = transA ? 1 : q.lda, bcs = transB ? q.ldb : 1;
     if (q.lda == lda && (q.ldb == ldb || (p.n == 1 && !transB)) && q.scale == scale &&
@@ -146,8 +146,36 @@ void GemmBatch::term(const double* A, int lda, const double* B, int ldb, int k, 
   p.term_end = (int)terms.size();
 }
 
+void GemmBatch::add_indexed(double* C, int m, int n, int ldc, double beta, const int* cidx,
+                            const double* D, const int* didx, int ldd) {
+  add(C, m, n, ldc, beta);
+  GemmProblem& p = probs.back();
+  p.cidx = cidx;
+  p.D = D;
+  p.didx = didx;
+  p.ldd = ldd;
+  indexed = true;
+}
+
+void GemmBatch::term_gathered(const double* A, int lda, const double* B, int ldb, const int* bidx,
+                              int k) {
+  if (k <= 0) return;
+  GemmTerm t{};
+  t.A = A;
+  t.B = B;
+  t.scale = 1.0;
+  t.k = k;
+  t.lda = lda;
+  t.ldb = ldb;
+  t.bidx = bidx;
+  terms.push_back(t);
+  probs.back().term_end = (int)terms.size();
+  indexed = true;
+}
+
 void GemmBatch::run(hipStream_t s, Stage& st) {
   if (probs.empty() || max_m == 0 || max_n == 0) return;
+  if (indexed && max_n > 4) throw Error(SPD_E_INVALID, "indexed products support at most 4 columns");
   const GemmTerm dummy{};
   auto* dp = (const GemmProblem*)st.push(s, probs.data(), probs.size() * sizeof(GemmProblem));
   auto* dt = (const GemmTerm*)st.push(s, terms.empty() ? &dummy : terms.data(),
@@ -231,9 +259,15 @@ static double batch_bytes(const GemmBatch& b) {
   std::vector<std::pair<const double*, const double*>> rs;
   for (const GemmProblem& p : b.probs) {
     bytes += 8.0 * p.m * p.n * (p.beta != 0.0 ? 2.0 : 1.0);
+    if (p.D) bytes += 8.0 * p.m * p.n + (p.didx ? 4.0 * p.m : 0.0);
+    if (p.cidx) bytes += 4.0 * p.m;
     for (int q = p.term_begin; q < p.term_end; ++q) {
       const GemmTerm& g = b.terms[q];
       bytes += 8.0 * p.m * g.k;
+      if (g.bidx) {
+        bytes += 8.0 * g.k * p.n + 4.0 * g.k;  // gathered rows and their indices
+        continue;
+      }
       if (!b.transB)
         for (int j = 0; j < p.n; ++j) rs.push_back({g.B + (int64_t)j * g.ldb, g.B + (int64_t)j * g.ldb + g.k});
       else
@@ -258,8 +292,9 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
     for (int q = p.term_begin; q < p.term_end; ++q) k += b.terms[q].k;
     return k;
   };
+  if (b.indexed && b.max_n > 4) throw Error(SPD_E_INVALID, "indexed products support at most 4 columns");
   bool split = false;
-  if (b.max_n <= 16)
+  if (b.max_n <= 16 && !b.indexed)
     for (const GemmProblem& p : b.probs)
       if (8.0 * p.m * width(p) > kSplitBytes && width(p) > 1) { split = true; break; }
   if (!split) {
@@ -322,7 +357,7 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
 // per-row regions [row tile][mirrored columns x n].  A block launch then forms
 // every output row as the sum, in a fixed order, of its own parts and of the
 // mirrored products addressed to it.
-void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n) {
+void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n, double beta) {
   if (rows.empty() || n <= 0) return;
   int max_m = 0;
   for (const SymRow& R : rows) max_m = std::max(max_m, R.m);
@@ -442,7 +477,7 @@ void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, in
   for (size_t i = 0; i < rows.size(); ++i) {
     const SymRow& R = rows[i];
     if (R.m <= 0) continue;
-    red.add(R.y, R.m, n, R.ldy, 0.0);
+    red.add(R.y, R.m, n, R.ldy, beta);
     for (const auto& c : contrib[i]) red.term(c.first, c.second, 1.0);
   }
   block(a, s, red);
