@@ -142,12 +142,18 @@ struct CpqrProblem {
 // ----------------------------------------------------------- launchers --
 // All launchers enqueue on `s` and copy their descriptor arrays from device
 // memory (`d_*` pointers) that the caller keeps alive until completion.
+// dot-form product (op(A) = A^T stored K x m, at most 4 columns); max_k bounds
+// the terms' K
+void launch_gemv_t(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob, int max_m,
+                   int max_n, int max_k, int transB);
 void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
                  int max_n);
 // rows per workgroup of launch_symv for a launch whose largest problem has max_m rows
 int symv_row_tile(int max_m);
-void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t,
-                 int nprob, int max_m, int max_n, int transA, int transB);
+// max_k bounds the terms' inner dimension (used to pick the dot-form variant
+// when transA is set and there are at most 4 columns)
+void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
+                 int max_m, int max_n, int transA, int transB, int max_k = 1 << 30);
 void launch_block(hipStream_t s, const BlockProblem* d_p, const BlockTerm* d_t,
                   int nprob, int max_m, int max_n);
 void launch_kblock(hipStream_t s, const KBlockProblem* d_p, int nprob, int max_m,

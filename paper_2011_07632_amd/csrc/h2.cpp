@@ -299,13 +299,14 @@ static void build_plan(H2Model& H, int m) {
   const int lf = T.first_at(1), lc = T.count_at(1);
   // With at most 4 columns the interpolation W_v = Pi_v [I; E_v^T] is applied
   // in that form: the identity rows are a gather (upward) or scatter
-  // (downward) of the vector, and only E_v is streamed.
+  // (downward) of the vector, and only E_v is streamed, as dot products down
+  // the columns of E_v^T (upward) or E_v (downward).
   const bool eform = m <= 4;
   if (L > 1) {
     // upward: x-hat_v = W_v^T x_v (leaf) or W_v^T [x-hat_c1; x-hat_c2]
     //         = x[Pi_v(0:k)] + E_v x[Pi_v(k:cand)]
     for (int lev = 1; lev < L; ++lev) {
-      GemmBatch g(0, 0);
+      GemmBatch g(eform ? 1 : 0, 0);  // E form: dot products down the columns of E^T
       for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
         if (H.k[v] == 0) continue;
         const double* xin = lev == 1 ? pl->xt + T.start[v] : pl->xh + H.par_off[v] * m;
@@ -313,7 +314,7 @@ static void build_plan(H2Model& H, int m) {
         if (eform) {
           const int k = H.k[v], c = H.cand[v];
           g.add_indexed(H.hat(pl->xh, v, m), k, m, H.hat_ld(v), 0.0, nullptr, xin, H.piv_d[v], ldin);
-          if (c > k) g.term_gathered(H.E[v], k, xin, ldin, H.piv_d[v] + k, c - k);
+          if (c > k) g.term_gathered(H.ET[v], c - k, xin, ldin, H.piv_d[v] + k, c - k);
         } else {
           g.add(H.hat(pl->xh, v, m), H.k[v], m, H.hat_ld(v));
           g.term(H.WT[v], H.k[v], xin, ldin, H.cand[v]);
@@ -366,7 +367,7 @@ static void build_plan(H2Model& H, int m) {
     // The E form continues to the leaves (level 1), where W_v y-hat_v is the
     // far-field part of y_v; the leaf pass then adds the near field.
     for (int lev = L - 1; lev >= (eform ? 1 : 2); --lev) {
-      GemmBatch g(0, 0);
+      GemmBatch g(eform ? 1 : 0, 0);  // E form: dot products down the columns of E
       for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
         const bool leaf = lev == 1;
         double* yout = leaf ? pl->yt + T.start[v] : pl->yh + H.par_off[v] * m;
@@ -381,7 +382,7 @@ static void build_plan(H2Model& H, int m) {
           g.add_indexed(yout, k, m, ldout, beta, H.piv_d[v], H.hat(pl->yh, v, m), nullptr, H.hat_ld(v));
           if (c > k) {
             g.add_indexed(yout, c - k, m, ldout, beta, H.piv_d[v] + k, nullptr, nullptr, 0);
-            g.term(H.ET[v], c - k, H.hat(pl->yh, v, m), H.hat_ld(v), k);
+            g.term(H.E[v], k, H.hat(pl->yh, v, m), H.hat_ld(v), k);
           }
         } else {
           if (k == 0 || c == 0) continue;

@@ -133,6 +133,55 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem* __restrict__ pr
       }
 }
 
+// Sum over the 64 lanes of V values at once (V a power of two, at most 64):
+// at each of the first log2(V) exchange steps a lane keeps half of its values
+// and trades the other half with its partner, then the last steps are a plain
+// butterfly.  Lane l returns the total of value index
+// sum_s bit(l, 5 - s) * V / 2^(s+1); every lane whose low 6 - log2(V) bits are
+// zero holds a distinct index.  The order of additions is fixed.
+template <int V>
+__device__ __forceinline__ double wave_sum_many(double (&v)[V], int lane) {
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int d = 32 >> s;
+    constexpr int kV = V;
+    const int nv = kV >> s;
+    if (nv >= 2) {
+      const int h = nv / 2;
+      const bool up = (lane & d) != 0;
+#pragma unroll
+      for (int q = 0; q < kV / 2; ++q) {
+        if (q < h) {
+          const double give = up ? v[q] : v[q + h];
+          const double keep = up ? v[q + h] : v[q];
+          v[q] = keep + __shfl_xor(give, d);
+        }
+      }
+    } else {
+      v[0] += __shfl_xor(v[0], d);
+    }
+  }
+  return v[0];
+}
+
+template <int V>
+__device__ __forceinline__ int wave_sum_index(int lane) {
+  int idx = 0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+    if ((V >> s) >= 2 && (lane & (32 >> s))) idx += V >> (s + 1);
+  return idx;
+}
+
+template <int V>
+__device__ __forceinline__ bool wave_sum_holder(int lane) {
+  int hs = 0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+    if ((V >> s) >= 2) ++hs;
+  return (lane & ((64 >> hs) - 1)) == 0;
+}
+
 // Skinny grouped GEMM for at most 4 right-hand columns: bandwidth-bound
 // streaming of A.  A workgroup of NW waves owns up to 64*RG rows of one
 // problem (lane l of row group g owns row i0 + 64 g + l), so every column of a
@@ -307,6 +356,108 @@ static void launch_skinny_nw(hipStream_t s, const GemmProblem* d_p, const GemmTe
   }
 }
 
+// Dot-form product for at most 4 right-hand columns with A stored transposed
+// (op(A) = A^T, A stored K x m): output row r is column r of A dotted with B,
+// so lanes run along the contiguous K dimension.  Each wave owns U output rows
+// and keeps U x KU loads in flight (KU chunks of 64 along K), which covers
+// K <= 64 KU in one round trip; the U x NC lane sums are added across the wave
+// with wave_sum_many and stored by the holding lanes.  Waves are independent
+// (no LDS, no barrier).  This is the kernel for the small per-level products
+// of the solve sweeps and of the H^2 interpolation, whose cost is the chain of
+// dependent memory round trips rather than bandwidth.
+template <int NC, int U, int KU>
+__global__ __launch_bounds__(256) void k_gemv_t(const GemmProblem* __restrict__ probs,
+                                               const GemmTerm* __restrict__ terms, int tiles_max,
+                                               int transB) {
+  constexpr int V = U * NC;
+  const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
+  const GemmProblem P = probs[p];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r0 = (tile * 4 + w) * U;  // this wave's first output row
+  if (r0 >= P.m || P.n <= 0) return;
+  const int n = P.n;
+  int jc[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) jc[j] = j < n ? j : 0;
+  int rc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) rc[u] = min(r0 + u, P.m - 1);
+  double acc[U][NC];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[u][j] = 0.0;
+  for (int t = P.term_begin; t < P.term_end; ++t) {
+    const GemmTerm T = terms[t];
+    const int K = T.k;
+    const int64_t lda = T.lda, ldb = T.ldb;
+    const double sc = T.scale;
+    gdouble* A = (gdouble*)T.A;
+    gdouble* B = (gdouble*)T.B;
+    const int* __restrict__ bidx = T.bidx;
+    // op(B)(k, j) = transB ? B[j + k ldb] : B[k + j ldb]
+    const int64_t bks = transB ? ldb : 1, bjs = transB ? 1 : ldb;
+    for (int k0 = 0; k0 < K; k0 += 64 * KU) {
+      double a[U][KU], b[KU][NC];
+#pragma unroll
+      for (int q = 0; q < KU; ++q) {
+        const int k = k0 + 64 * q + lane;
+        const int kc = k < K ? k : K - 1;
+        const int64_t brow = bidx ? bidx[kc] : kc;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) b[q][j] = k < K ? B[brow * bks + jc[j] * bjs] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u][q] = __builtin_nontemporal_load(&A[kc + (int64_t)rc[u] * lda]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < KU; ++q)
+#pragma unroll
+          for (int j = 0; j < NC; ++j) acc[u][j] += sc * a[u][q] * b[q][j];
+    }
+  }
+  double v[V];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) v[u * NC + j] = acc[u][j];
+  const double tot = wave_sum_many<V>(v, lane);
+  const int idx = wave_sum_index<V>(lane);
+  const int r = r0 + idx / NC, j = idx % NC;
+  if (wave_sum_holder<V>(lane) && r < P.m && j < n) {
+    const int64_t row = P.cidx ? P.cidx[r] : r;
+    double* cp = P.C + row + (int64_t)j * P.ldc;
+    double val = P.alpha * tot;
+    if (P.beta != 0.0) val += P.beta * (*cp);
+    if (P.D) val += P.D[(P.didx ? P.didx[r] : r) + (int64_t)j * P.ldd];
+    *cp = val;
+  }
+}
+
+// rows per workgroup of the dot-form kernel: 4 waves of U rows
+template <int NC, int U>
+static void launch_gemv_t_u(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
+                            int max_m, int max_k, int transB) {
+  const int tiles = ceil_div(max_m, 4 * U);
+  const dim3 grid((unsigned)nprob * tiles);
+  if (max_k <= 256)
+    hipLaunchKernelGGL((k_gemv_t<NC, U, 4>), grid, dim3(256), 0, s, d_p, d_t, tiles, transB);
+  else
+    hipLaunchKernelGGL((k_gemv_t<NC, U, 8>), grid, dim3(256), 0, s, d_p, d_t, tiles, transB);
+}
+
+void launch_gemv_t(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob, int max_m,
+                   int max_n, int max_k, int transB) {
+  if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
+  if (max_n > 4) throw Error(SPD_E_INVALID, "dot-form product supports at most 4 columns");
+  if (max_n == 1) launch_gemv_t_u<1, 4>(s, d_p, d_t, nprob, max_m, max_k, transB);
+  else if (max_n == 2) launch_gemv_t_u<2, 2>(s, d_p, d_t, nprob, max_m, max_k, transB);
+  else launch_gemv_t_u<4, 1>(s, d_p, d_t, nprob, max_m, max_k, transB);
+  SPD_HIP(hipGetLastError());
+}
+
 // Workgroups below which a launch uses 16 waves per workgroup (two per SIMD
 // of every CU at 4 waves).
 static constexpr int kSkinnyWide = 2048;
@@ -319,55 +470,6 @@ static void launch_skinny(hipStream_t s, const GemmProblem* d_p, const GemmTerm*
     launch_skinny_nw<NC, 16>(s, d_p, d_t, nprob, max_m, transA, transB);
   else
     launch_skinny_nw<NC, 4>(s, d_p, d_t, nprob, max_m, transA, transB);
-}
-
-// Sum over the 64 lanes of V values at once (V a power of two, at most 64):
-// at each of the first log2(V) exchange steps a lane keeps half of its values
-// and trades the other half with its partner, then the last steps are a plain
-// butterfly.  Lane l returns the total of value index
-// sum_s bit(l, 5 - s) * V / 2^(s+1); every lane whose low 6 - log2(V) bits are
-// zero holds a distinct index.  The order of additions is fixed.
-template <int V>
-__device__ __forceinline__ double wave_sum_many(double (&v)[V], int lane) {
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int d = 32 >> s;
-    constexpr int kV = V;
-    const int nv = kV >> s;
-    if (nv >= 2) {
-      const int h = nv / 2;
-      const bool up = (lane & d) != 0;
-#pragma unroll
-      for (int q = 0; q < kV / 2; ++q) {
-        if (q < h) {
-          const double give = up ? v[q] : v[q + h];
-          const double keep = up ? v[q + h] : v[q];
-          v[q] = keep + __shfl_xor(give, d);
-        }
-      }
-    } else {
-      v[0] += __shfl_xor(v[0], d);
-    }
-  }
-  return v[0];
-}
-
-template <int V>
-__device__ __forceinline__ int wave_sum_index(int lane) {
-  int idx = 0;
-#pragma unroll
-  for (int s = 0; s < 6; ++s)
-    if ((V >> s) >= 2 && (lane & (32 >> s))) idx += V >> (s + 1);
-  return idx;
-}
-
-template <int V>
-__device__ __forceinline__ bool wave_sum_holder(int lane) {
-  int hs = 0;
-#pragma unroll
-  for (int s = 0; s < 6; ++s)
-    if ((V >> s) >= 2) ++hs;
-  return (lane & ((64 >> hs) - 1)) == 0;
 }
 
 // Symmetric-pair product (see SymProblem).  The row results follow the
@@ -537,8 +639,12 @@ void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int n
 }
 
 void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
-                 int max_m, int max_n, int transA, int transB) {
+                 int max_m, int max_n, int transA, int transB, int max_k) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
+  if (transA && max_n <= 4) {
+    launch_gemv_t(s, d_p, d_t, nprob, max_m, max_n, max_k, transB);
+    return;
+  }
   if (max_n <= 4) {
     if (max_n == 1) launch_skinny<1>(s, d_p, d_t, nprob, max_m, transA, transB);
     else if (max_n <= 2) launch_skinny<2>(s, d_p, d_t, nprob, max_m, transA, transB);

@@ -57,7 +57,7 @@ class Stage {
 struct GemmBatch {
   std::vector<GemmProblem> probs;
   std::vector<GemmTerm> terms;
-  int max_m = 0, max_n = 0, transA = 0, transB = 0;
+  int max_m = 0, max_n = 0, transA = 0, transB = 0, max_k = 0;
   explicit GemmBatch(int ta = 0, int tb = 0) : transA(ta), transB(tb) {}
   void add(double* C, int m, int n, int ldc, double beta = 0.0, double alpha = 1.0);
   void term(const double* A, int lda, const double* B, int ldb, int k, double scale = 1.0);
@@ -96,6 +96,7 @@ struct LaunchRec {
   int nprob, max_m, max_n, transA, transB;
   double bytes;  // algorithmic bytes: every A operand once, distinct B operands once, C once
   int tag = -1;  // caller-defined label (which pass of a product)
+  int max_k = 1 << 30;  // bound on the terms' inner dimension (gemm records)
 };
 // One block row of a symmetric product with at most 4 right-hand columns:
 // y = sum_t A_t B_t, and every mirrored term (an off-diagonal block A_ij of a

@@ -132,6 +132,7 @@ void GemmBatch::term(const double* A, int lda, const double* B, int ldb, int k, 
     if (q.lda == lda && (q.ldb == ldb || (p.n == 1 && !transB)) && q.scale == scale &&
         A == q.A + acs * q.k && B == q.B + bcs * q.k) {
       q.k += k;
+      max_k = std::max(max_k, q.k);
       return;
     }
   }
@@ -144,6 +145,7 @@ void GemmBatch::term(const double* A, int lda, const double* B, int ldb, int k, 
   t.ldb = ldb;
   terms.push_back(t);
   p.term_end = (int)terms.size();
+  max_k = std::max(max_k, k);
 }
 
 void GemmBatch::add_indexed(double* C, int m, int n, int ldc, double beta, const int* cidx,
@@ -171,6 +173,7 @@ void GemmBatch::term_gathered(const double* A, int lda, const double* B, int ldb
   terms.push_back(t);
   probs.back().term_end = (int)terms.size();
   indexed = true;
+  max_k = std::max(max_k, k);
 }
 
 void GemmBatch::run(hipStream_t s, Stage& st) {
@@ -180,7 +183,7 @@ void GemmBatch::run(hipStream_t s, Stage& st) {
   auto* dp = (const GemmProblem*)st.push(s, probs.data(), probs.size() * sizeof(GemmProblem));
   auto* dt = (const GemmTerm*)st.push(s, terms.empty() ? &dummy : terms.data(),
                                       std::max<size_t>(1, terms.size()) * sizeof(GemmTerm));
-  launch_gemm(s, dp, dt, (int)probs.size(), max_m, max_n, transA, transB);
+  launch_gemm(s, dp, dt, (int)probs.size(), max_m, max_n, transA, transB, std::max(max_k, 1));
 }
 
 void BlockBatch::add(double* dst, int m, int n, int ldd, double beta, int add_eye) {
@@ -302,6 +305,7 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
     if (t.empty()) t.push_back(GemmTerm{});
     recs.push_back({0, keep(a, s, b.probs), keep(a, s, t), (int)b.probs.size(), b.max_m, b.max_n,
                     b.transA, b.transB, bytes, -1});
+    recs.back().max_k = std::max(b.max_k, 1);
     return;
   }
   GemmBatch parts(b.transA, b.transB);
@@ -348,6 +352,7 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
   }
   recs.push_back({0, keep(a, s, parts.probs), keep(a, s, parts.terms), (int)parts.probs.size(),
                   parts.max_m, parts.max_n, parts.transA, parts.transB, bytes, -1});
+  recs.back().max_k = std::max(b.max_k, 1);
   block(a, s, red);
 }
 
@@ -501,7 +506,7 @@ void Recorder::replay(hipStream_t s) const {
   for (const LaunchRec& r : recs) {
     if (r.type == 0)
       launch_gemm(s, (const GemmProblem*)r.probs, (const GemmTerm*)r.terms, r.nprob, r.max_m,
-                  r.max_n, r.transA, r.transB);
+                  r.max_n, r.transA, r.transB, r.max_k);
     else if (r.type == 1)
       launch_block(s, (const BlockProblem*)r.probs, (const BlockTerm*)r.terms, r.nprob, r.max_m,
                    r.max_n);

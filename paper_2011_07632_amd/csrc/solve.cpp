@@ -135,7 +135,10 @@ void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
   form_solve_ops(F, M, U.stage, s);
 }
 
-// The sweeps as batched products, one launch per level.
+// The sweeps as batched products, one launch per level.  With at most 4
+// columns every product is a dot-form product (transposed storage: Z_v for
+// Z_v^T, Z_v^T for Z_v, and the symmetric Dm_v for itself), whose lanes run
+// down stored columns; with more columns the same products run on MFMA.
 static void build_apply_plan(ULVModel& U, int m) {
   auto pl = std::make_unique<ULVModel::ApplyPlan>();
   pl->ncols = m;
@@ -150,8 +153,9 @@ static void build_apply_plan(ULVModel& U, int m) {
   pl->out = a.get_n<double>((size_t)N * m);
   const int lf = T.first_at(1), lc = T.count_at(1);
   const int Ni = (int)N;
+  const int tA = m <= 4 ? 1 : 0;
   if (L == 1) {
-    GemmBatch g;
+    GemmBatch g(tA, 0);
     g.add(pl->out, Ni, m, Ni);
     g.term(F.Dm[0], Ni, pl->in, Ni, Ni);
     rec.gemm(a, s, g);
@@ -164,52 +168,60 @@ static void build_apply_plan(ULVModel& U, int m) {
   pl->ds = a.get_n<double>((size_t)rows * m);
   // leaves: t_v = Z_v^T b_v
   {
-    GemmBatch g;
+    GemmBatch g(tA, 0);
     for (int v = lf; v < lf + lc; ++v) {
       if (F.r[v] == 0) continue;
       g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
-      g.term(F.ZsT[v], F.r[v], pl->in + T.start[v], Ni, F.rho[v]);
+      if (tA) g.term(F.Zs[v], F.rho[v], pl->in + T.start[v], Ni, F.rho[v]);
+      else g.term(F.ZsT[v], F.r[v], pl->in + T.start[v], Ni, F.rho[v]);
     }
     rec.gemm(a, s, g);
   }
   // upward: t_v = Z_v^T [t_c]
   for (int lev = 2; lev <= L - 1; ++lev) {
-    GemmBatch g;
+    GemmBatch g(tA, 0);
     for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
       if (F.r[v] == 0 || F.rho[v] == 0) continue;
       g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
-      g.term(F.ZsT[v], F.r[v], pl->ts + F.par_off[v] * m, F.rho[v], F.rho[v]);
+      if (tA) g.term(F.Zs[v], F.rho[v], pl->ts + F.par_off[v] * m, F.rho[v], F.rho[v]);
+      else g.term(F.ZsT[v], F.r[v], pl->ts + F.par_off[v] * m, F.rho[v], F.rho[v]);
     }
     rec.gemm(a, s, g);
   }
   // root: [d_c] = ((I + bold B_root)^{-1} - I) [t_c]
   if (F.rho[0] > 0) {
     const int rv = F.rho[0];
-    GemmBatch g;
+    GemmBatch g(tA, 0);
     g.add(pl->ds + F.par_off[0] * m, rv, m, rv);
     g.term(F.Dm[0], rv, pl->ts + F.par_off[0] * m, rv, rv);
     rec.gemm(a, s, g);
   }
   // downward: [d_c] = ((I + bold B_v)^{-1} - I) [t_c] + Z_v d_v
   for (int lev = L - 1; lev >= 2; --lev) {
-    GemmBatch g;
+    GemmBatch g(tA, 0);
     for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
       const int rv = F.rho[v];
       if (rv == 0) continue;
       g.add(pl->ds + F.par_off[v] * m, rv, m, rv);
       g.term(F.Dm[v], rv, pl->ts + F.par_off[v] * m, rv, rv);
-      if (F.r[v] > 0) g.term(F.Zs[v], rv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
+      if (F.r[v] > 0) {
+        if (tA) g.term(F.ZsT[v], F.r[v], F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
+        else g.term(F.Zs[v], rv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
+      }
     }
     rec.gemm(a, s, g);
   }
   // leaves: x_v = A_vv^{-1} b_v + Z_v d_v
   {
-    GemmBatch g;
+    GemmBatch g(tA, 0);
     for (int v = lf; v < lf + lc; ++v) {
       const int nv = F.rho[v];
       g.add(pl->out + T.start[v], nv, m, Ni);
       g.term(F.Dm[v], nv, pl->in + T.start[v], Ni, nv);
-      if (F.r[v] > 0) g.term(F.Zs[v], nv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
+      if (F.r[v] > 0) {
+        if (tA) g.term(F.ZsT[v], F.r[v], F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
+        else g.term(F.Zs[v], nv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
+      }
     }
     rec.gemm(a, s, g);
   }
