@@ -1442,6 +1442,115 @@ void launch_coldot(hipStream_t s, const double* x, const double* y, int64_t n, i
   SPD_HIP(hipGetLastError());
 }
 
+// Fused PCG updates.  Column dot products are kept as per-chunk partial sums
+// (DOT_CHUNK entries per workgroup of k_coldot_partial); every consumer adds
+// the partials of its column in chunk order, so all blocks agree bit for bit
+// and no separate finishing launch is needed.
+__device__ __forceinline__ double chunk_sum(const double* __restrict__ partial, int nblk, int c) {
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[b + (int64_t)c * nblk];
+  return s;
+}
+
+// x += alpha p, r -= alpha q with alpha = (r.z) / (p.q), then the partial sums
+// of the updated r.r; block (0, c) counts the iteration and records r.z for
+// the next beta.
+__global__ __launch_bounds__(256) void k_pcg_xr_dot(double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p,
+                                                    const double* __restrict__ q,
+                                                    const double* __restrict__ rzp,
+                                                    const double* __restrict__ pqp, int nblk,
+                                                    const int* __restrict__ active, int64_t n,
+                                                    int64_t ld, int* __restrict__ iters,
+                                                    double* __restrict__ rzv,
+                                                    double* __restrict__ rrp) {
+  __shared__ double red[4];
+  const int b = blockIdx.x, c = blockIdx.y;
+  if (!active[c]) return;
+  const double rz = chunk_sum(rzp, nblk, c);
+  const double alpha = rz / chunk_sum(pqp, nblk, c);
+  if (b == 0 && threadIdx.x == 0) {
+    if (iters) iters[c] += 1;
+    rzv[c] = rz;
+  }
+  const int64_t lo = (int64_t)b * DOT_CHUNK, hi = min(n, lo + DOT_CHUNK);
+  double sacc = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    x[i + c * ld] += alpha * p[i + c * ld];
+    const double rn = r[i + c * ld] - alpha * q[i + c * ld];
+    r[i + c * ld] = rn;
+    sacc += rn * rn;
+  }
+  sacc = wave_sum(sacc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sacc;
+  __syncthreads();
+  if (threadIdx.x == 0) rrp[b + (int64_t)c * nblk] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// active[c] stays set while ||r_c|| > rtol ||b_c||, with r.r from its partials
+__global__ void k_pcg_active_partial(const double* __restrict__ rrp, int nblk,
+                                     const double* __restrict__ bb, double rtol,
+                                     int* __restrict__ active, int ncols, int* any_active) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+    if (active[c]) {
+      const bool a = sqrt(chunk_sum(rrp, nblk, c)) > rtol * sqrt(bb[c]);
+      active[c] = a ? 1 : 0;
+      if (a) atomicOr(&any, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *any_active = any;
+}
+
+// p = z + beta p with beta = (r.z)_new / (r.z)_old, (r.z)_new from its partials
+__global__ void k_pcg_update_p_partial(double* __restrict__ p, const double* __restrict__ z,
+                                       const double* __restrict__ rzp, int nblk,
+                                       const double* __restrict__ rzv,
+                                       const int* __restrict__ active, int64_t n, int64_t ld) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (!active[c] || i >= n) return;
+  const double beta = chunk_sum(rzp, nblk, c) / rzv[c];
+  p[i + c * ld] = z[i + c * ld] + beta * p[i + c * ld];
+}
+
+void launch_coldot_partial(hipStream_t s, const double* x, const double* y, int64_t n, int ncols,
+                           int64_t ld, double* partial) {
+  if (ncols <= 0) return;
+  const int nblk = ceil_div(n, DOT_CHUNK);
+  hipLaunchKernelGGL(k_coldot_partial, dim3(nblk, ncols), dim3(256), 0, s, x, y, n, ld, partial, nblk);
+  SPD_HIP(hipGetLastError());
+}
+
+int coldot_chunks(int64_t n) { return ceil_div(n, DOT_CHUNK); }
+
+void launch_pcg_xr_dot(hipStream_t s, double* x, double* r, const double* p, const double* q,
+                       const double* rzp, const double* pqp, const int* active, int64_t n, int ncols,
+                       int64_t ld, int* iters, double* rzv, double* rrp) {
+  const int nblk = ceil_div(n, DOT_CHUNK);
+  hipLaunchKernelGGL(k_pcg_xr_dot, dim3(nblk, ncols), dim3(256), 0, s, x, r, p, q, rzp, pqp, nblk,
+                     active, n, ld, iters, rzv, rrp);
+  SPD_HIP(hipGetLastError());
+}
+
+void launch_pcg_active_partial(hipStream_t s, const double* rrp, int64_t n, const double* bb,
+                               double rtol, int* active, int ncols, int* any_active) {
+  hipLaunchKernelGGL(k_pcg_active_partial, dim3(1), dim3(64), 0, s, rrp, ceil_div(n, DOT_CHUNK), bb,
+                     rtol, active, ncols, any_active);
+  SPD_HIP(hipGetLastError());
+}
+
+void launch_pcg_update_p_partial(hipStream_t s, double* p, const double* z, const double* rzp,
+                                 const double* rzv, const int* active, int64_t n, int ncols,
+                                 int64_t ld) {
+  hipLaunchKernelGGL(k_pcg_update_p_partial, dim3(ceil_div(n, 256), ncols), dim3(256), 0, s, p, z, rzp,
+                     ceil_div(n, DOT_CHUNK), rzv, active, n, ld);
+  SPD_HIP(hipGetLastError());
+}
+
 __global__ void k_pcg_update_xr(double* __restrict__ x, double* __restrict__ r,
                                 const double* __restrict__ p, const double* __restrict__ q,
                                 const double* __restrict__ rz, const double* __restrict__ pq,

@@ -296,10 +296,14 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   double* z = U ? ulv_plan_out(*U, m) : a.get_n<double>((size_t)N * m);
   double* p = h2_plan_x(H, m);
   double* q = h2_plan_y(H, m);
-  const int nblk = ceil_div(N, 8192);
+  const int nblk = coldot_chunks(N);
   double* partial = a.get_n<double>((size_t)nblk * m);
+  // per-chunk partial dot products of the iteration (see k_pcg_xr_dot)
+  double* pqp = a.get_n<double>((size_t)nblk * m);
+  double* rrp = a.get_n<double>((size_t)nblk * m);
+  double* rzp = a.get_n<double>((size_t)nblk * m);
   double* sc = a.get_n<double>((size_t)8 * m);
-  double* rz = sc, *rzn = sc + m, *pq = sc + 2 * m, *rr = sc + 3 * m, *bb = sc + 4 * m;
+  double* rz = sc, *rzv = sc + m, *rr = sc + 3 * m, *bb = sc + 4 * m;
   int* active = a.get_n<int>(2 * m + 1);
   int* any = active + m;
   int* iters = active + m + 1;
@@ -312,6 +316,7 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   precond(r, z);
   SPD_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, s));
   launch_coldot(s, r, z, N, m, N, partial, rz);
+  launch_coldot_partial(s, r, z, N, m, N, rzp);
   launch_coldot(s, bt, bt, N, m, N, partial, bb);
   launch_coldot(s, r, r, N, m, N, partial, rr);
   {
@@ -321,15 +326,17 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
     SPD_HIP(hipStreamSynchronize(s));
   }
   launch_pcg_active(s, rr, bb, rtol, active, m, any);
+  // one iteration: q = A p; alpha = (r.z)/(p.q); x, r update; stop test;
+  // z = M r; beta = (r.z)_new/(r.z)_old; p update.  The dot products stay as
+  // per-chunk partials read by the next kernel.
   auto body = [&]() {
-    h2_plan_run(H);  // q = A p
-    launch_coldot(s, p, q, N, m, N, partial, pq);
-    launch_pcg_update_xr(s, xt, r, p, q, rz, pq, active, N, m, N, iters);
-    launch_coldot(s, r, r, N, m, N, partial, rr);
-    launch_pcg_active(s, rr, bb, rtol, active, m, any);
+    h2_plan_run(H);
+    launch_coldot_partial(s, p, q, N, m, N, pqp);
+    launch_pcg_xr_dot(s, xt, r, p, q, rzp, pqp, active, N, m, N, iters, rzv, rrp);
+    launch_pcg_active_partial(s, rrp, N, bb, rtol, active, m, any);
     precond(r, z);
-    launch_coldot(s, r, z, N, m, N, partial, rzn);
-    launch_pcg_update_p(s, p, z, rzn, rz, active, N, m, N);
+    launch_coldot_partial(s, r, z, N, m, N, rzp);
+    launch_pcg_update_p_partial(s, p, z, rzp, rzv, active, N, m, N);
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
