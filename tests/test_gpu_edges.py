@@ -1,0 +1,113 @@
+"""Degenerate and edge cases of the HIP path against the oracle and closed
+forms (GPU): a single leaf (the HSS matrix is the dense block), the
+block-Jacobi limit r_max = 0, more than 4 right-hand sides (the MFMA product
+and apply), and argument errors reported through the C ABI."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import kernels as okern
+from oracle.h2 import H2 as OH2
+from oracle.pcg import pcg as opcg
+from oracle.spdhss import SPDHSS as OHSS
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2011_07632_amd import binding
+    return binding
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+def cols(B, a):
+    return B.cols_like(a.shape[0], a.shape[1], "cuda").copy_(torch.from_numpy(np.ascontiguousarray(a)))
+
+
+def test_single_leaf_is_dense(B):
+    w = workloads.SMALL.with_(name="gaussian-l0.5-N50", n=50)
+    X = w.points()
+    A = okern.evaluate(w.kernel, w.ell, X, X) + w.shift * np.eye(w.n)
+    h2 = B.h2_build(torch.from_numpy(X).cuda(), w.kernel, w.ell, w.shift, leaf=64, tol=w.h2_tol)
+    assert h2.levels == 1
+    x = workloads.gaussian_matrix(w.n, 2, 5)
+    assert rel(B.h2_matvec(h2, cols(B, x)).cpu().numpy(), A @ x) <= 1e-13
+    ulv = B.ulv_factor(B.spdhss_build(h2, w.hss_tol, w.max_rank, w.oversample,
+                                      omega=cols(B, w.omega())))
+    assert rel(B.ulv_apply(ulv, cols(B, x)).cpu().numpy(), np.linalg.solve(A, x)) <= 1e-10
+    _, it, res = B.pcg_solve(h2, ulv, cols(B, x), rtol=1e-10, maxit=10)
+    assert it.tolist() == [1, 1]
+    assert float(res.max()) <= 1e-10
+
+
+def test_block_jacobi_limit(B):
+    """r_max = 0: the HSS matrix is blockdiag(A_ii); its solve is per-leaf."""
+    w = workloads.SMALL.with_(name="gaussian-l0.5-N1500-bj", n=1500, max_rank=0, seed_base=3)
+    X = w.points()
+    h2 = B.h2_build(torch.from_numpy(X).cuda(), w.kernel, w.ell, w.shift, leaf=w.leaf, tol=w.h2_tol)
+    hss = B.spdhss_build(h2, w.hss_tol, 0, w.oversample, omega=cols(B, w.omega()))
+    assert (hss.ranks() == 0).all()
+    ulv = B.ulv_factor(hss)
+    b = workloads.gaussian_matrix(w.n, 1, 9)
+    x = B.ulv_apply(ulv, cols(B, b)).cpu().numpy()
+    perm, start = h2.perm(), h2.node_start()
+    L = h2.levels
+    xo = np.empty_like(b)
+    for v in range((1 << (L - 1)) - 1, (1 << L) - 1):
+        idx = perm[start[v]:start[v + 1]]
+        Aii = okern.evaluate(w.kernel, w.ell, X[idx], X[idx]) + w.shift * np.eye(len(idx))
+        xo[idx] = np.linalg.solve(Aii, b[idx])
+    assert rel(x, xo) <= 1e-10
+    o_h2 = OH2(X, w.kernel, w.ell, w.shift, w.leaf, w.h2_tol, eta=w.eta)
+    o_hss = OHSS(o_h2, w.omega()[o_h2.tree.perm], w.hss_tol, 0, "chol")
+    _, it, _ = B.pcg_solve(h2, ulv, cols(B, b), rtol=w.pcg_tol, maxit=500, raise_on_nonconvergence=False)
+    _, ito, _ = opcg(o_h2.matvec, o_hss.solve, b[o_h2.tree.perm], w.pcg_tol, 500)
+    assert abs(int(it[0]) - int(ito[0])) <= 1
+
+
+def test_more_than_four_columns(B):
+    """6 right-hand sides: the product and the apply take the MFMA kernels."""
+    w = workloads.SMALL
+    X = w.points()
+    h2 = B.h2_build(torch.from_numpy(X).cuda(), w.kernel, w.ell, w.shift, leaf=w.leaf, tol=w.h2_tol)
+    ulv = B.ulv_factor(B.spdhss_build(h2, w.hss_tol, w.max_rank, w.oversample, omega=cols(B, w.omega())))
+    o_h2 = OH2(X, w.kernel, w.ell, w.shift, w.leaf, w.h2_tol, eta=w.eta)
+    perm = o_h2.tree.perm
+    o_hss = OHSS(o_h2, w.omega()[perm], w.hss_tol, w.max_rank, "chol")
+    b = workloads.gaussian_matrix(w.n, 6, 21)
+    xo = np.empty_like(b)
+    xo[perm] = o_hss.solve(b[perm])
+    assert rel(B.ulv_apply(ulv, cols(B, b)).cpu().numpy(), xo) <= 1e-10
+    x, it, _ = B.pcg_solve(h2, ulv, cols(B, b), rtol=0.0, maxit=3, raise_on_nonconvergence=False)
+    xo_t, ito, _ = opcg(o_h2.matvec, o_hss.solve, b[perm], 0.0, 3)
+    xo = np.empty_like(b)
+    xo[perm] = xo_t
+    assert it.tolist() == ito.tolist()
+    assert rel(x.cpu().numpy(), xo) <= 1e-10
+
+
+def test_argument_errors(B):
+    X = torch.from_numpy(workloads.SMALL.with_(n=200).points()).cuda()
+    with pytest.raises(B.SpdError):
+        B.h2_build(X[:0], "gaussian", 0.5, 1e-2)
+    with pytest.raises(B.SpdError):
+        B.h2_build(X, "gaussian", 0.5, 1e-2, leaf=0)
+    with pytest.raises(B.SpdError):
+        B.h2_build(X, "gaussian", 0.5, 1e-2, tol=1.5)
+    with pytest.raises(B.SpdError):
+        B.h2_build(X, "gaussian", -0.5, 1e-2)
+    h2 = B.h2_build(X, "gaussian", 0.5, 1e-2, leaf=32)
+    with pytest.raises(B.SpdError):
+        B.spdhss_build(h2, 1e-2, max_rank=120, oversample=10)
+    hss = B.spdhss_build(h2, 1e-2, max_rank=20, oversample=10)
+    ulv = B.ulv_factor(hss)
+    b = B.cols_like(200, 1, "cuda").fill_(1.0)
+    with pytest.raises(B.SpdError):
+        B.pcg_solve(h2, ulv, b, rtol=-1.0, maxit=10)
