@@ -194,7 +194,7 @@ def main():
         ms_, by_ = acc.get(d["pass"], (0.0, 0.0))
         acc[d["pass"]] = (ms_ + d["ms"], by_ + d["bytes"])
     passes = {k: {"ms": round(v[0], 4), "gbs": round(v[1] / v[0] / 1e6, 1)} for k, v in acc.items()}
-    kern = "k_gemm_skinny" if w.nrhs <= 16 else "k_gemm (MFMA)"
+    kern = "k_symv (symmetric-pair streaming product)" if w.nrhs <= 4 else "k_gemm (MFMA)"
     roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
                 "traffic": recorded_traffic(w.name, dom["pass"]),
