@@ -146,8 +146,10 @@ struct CpqrProblem {
 // the terms' K
 void launch_gemv_t(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob, int max_m,
                    int max_n, int max_k, int transB);
+// cap > 0 bounds the number of workgroups (they then walk the problems with a
+// stride), so that the launch can run beside latency-bound work
 void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
-                 int max_n);
+                 int max_n, int cap = 0);
 // rows per workgroup of launch_symv for a launch whose largest problem has max_m rows
 int symv_row_tile(int max_m);
 // max_k bounds the terms' inner dimension (used to pick the dot-form variant

@@ -19,10 +19,15 @@
 
 namespace spd {
 
+// The recorded product.  With at most 4 columns the near-field pass reads only
+// x, so its product launch (`side`) runs on the side stream beside the
+// far-field chain (`rec`: upward, coupling, downward down to the leaves, which
+// writes the far-field part of y); `tail` then adds the near-field parts into
+// y once both are done.  Otherwise everything is in `rec`.
 struct H2Model::MatvecPlan {
   int ncols = 0;
   Arena arena;
-  Recorder rec;
+  Recorder rec, side, tail;
   double* xh = nullptr;
   double* yh = nullptr;
   double* xt = nullptr;  // tree-order input
@@ -30,7 +35,29 @@ struct H2Model::MatvecPlan {
 };
 
 H2Model::H2Model() = default;
-H2Model::~H2Model() = default;
+H2Model::~H2Model() {
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (side_s) (void)hipStreamDestroy(side_s);
+}
+
+// Run the recorded product on H.s (the side part forked onto H.side_s and
+// joined before the tail); stream-ordered and capturable into a graph.
+static void replay_plan(H2Model& H) {
+  auto& pl = *H.plan;
+  if (pl.side.recs.empty()) {
+    pl.rec.replay(H.s);
+    pl.tail.replay(H.s);
+    return;
+  }
+  SPD_HIP(hipEventRecord(H.ev_fork, H.s));
+  SPD_HIP(hipStreamWaitEvent(H.side_s, H.ev_fork, 0));
+  pl.side.replay(H.side_s);
+  SPD_HIP(hipEventRecord(H.ev_join, H.side_s));
+  pl.rec.replay(H.s);
+  SPD_HIP(hipStreamWaitEvent(H.s, H.ev_join, 0));
+  pl.tail.replay(H.s);
+}
 
 void h2_build_impl(H2Model& H, const double* points, int64_t n) {
   hipStream_t s = H.s;
@@ -283,6 +310,13 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
 }
 
 // ------------------------------------------------------------- product --
+// Workgroups of the near-field product when it runs beside the far-field
+// chain (two per CU): few enough to leave the latency-bound level passes
+// room.  Measured on the N = 100k Matern workload: 64 -> 2.67, 128 -> 2.01,
+// 256 -> 1.979, 512 -> 1.975, 1024 -> 1.994 ms per PCG iteration, against
+// 1.997 uncapped.
+static constexpr int kNearCap = 512;
+
 static void build_plan(H2Model& H, int m) {
   auto pl = std::make_unique<H2Model::MatvecPlan>();
   pl->ncols = m;
@@ -416,9 +450,18 @@ static void build_plan(H2Model& H, int m) {
                            j == v ? -1 : j - lf});
       }
     }
-    const size_t first = rec.recs.size();
-    rec.symv(a, s, rows, m, 1.0);
-    rec.tag_from(first, 400);
+    Recorder near;
+    near.symv(a, s, rows, m, 1.0);
+    near.tag_from(0, 400);
+    // the product launch goes to the side stream, the block sum into y after the join
+    pl->side.recs.push_back(near.recs[0]);
+    pl->side.recs[0].cap = kNearCap;
+    pl->tail.recs.assign(near.recs.begin() + 1, near.recs.end());
+    if (!H.side_s) {
+      SPD_HIP(hipStreamCreateWithFlags(&H.side_s, hipStreamNonBlocking));
+      SPD_HIP(hipEventCreateWithFlags(&H.ev_fork, hipEventDisableTiming));
+      SPD_HIP(hipEventCreateWithFlags(&H.ev_join, hipEventDisableTiming));
+    }
   } else {
     GemmBatch g(0, 0);
     for (int v = lf; v < lf + lc; ++v) {
@@ -446,7 +489,7 @@ void h2_matvec_tree(H2Model& H, const double* x, double* y, int m) {
   auto& pl = *H.plan;
   if (x != pl.xt)
     SPD_HIP(hipMemcpyAsync(pl.xt, x, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, H.s));
-  pl.rec.replay(H.s);
+  replay_plan(H);
   if (y != pl.yt)
     SPD_HIP(hipMemcpyAsync(y, pl.yt, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, H.s));
 }
@@ -462,12 +505,20 @@ double* h2_plan_y(H2Model& H, int m) {
   h2_plan_x(H, m);
   return H.plan->yt;
 }
-void h2_plan_run(H2Model& H) { H.plan->rec.replay(H.s); }
+void h2_plan_run(H2Model& H) { replay_plan(H); }
 
-// the last recorded launch of the product is the leaf pass: y = U y-hat + near
+// every recorded launch of the product, in stream order
+static std::vector<LaunchRec> all_launches(const H2Model::MatvecPlan& pl) {
+  std::vector<LaunchRec> v(pl.rec.recs);
+  v.insert(v.end(), pl.side.recs.begin(), pl.side.recs.end());
+  v.insert(v.end(), pl.tail.recs.begin(), pl.tail.recs.end());
+  return v;
+}
+
+// the launches of the near-field (leaf) pass, on H.s
 void h2_plan_run_last(H2Model& H) {
   Recorder one;
-  for (const LaunchRec& r : H.plan->rec.recs)
+  for (const LaunchRec& r : all_launches(*H.plan))
     if (r.tag == 400) one.recs.push_back(r);
   one.replay(H.s);
 }
@@ -477,7 +528,7 @@ void h2_plan_run_last(H2Model& H) {
 H2Model::NearStats h2_near_stats(H2Model& H, int m) {
   h2_plan_x(H, m);
   double b = 0;
-  for (const LaunchRec& r : H.plan->rec.recs)
+  for (const LaunchRec& r : all_launches(*H.plan))
     if (r.tag == 400) b += r.bytes;
   H2Model::NearStats st;
   st.bytes = b;
@@ -488,7 +539,7 @@ H2Model::NearStats h2_near_stats(H2Model& H, int m) {
 // stream); returns the number of launches written.
 int h2_time_launches(H2Model& H, int m, int reps, double* ms, double* bytes, int* tags, int cap) {
   h2_plan_x(H, m);
-  const auto& recs = H.plan->rec.recs;
+  const std::vector<LaunchRec> recs = all_launches(*H.plan);
   hipEvent_t e0, e1;
   SPD_HIP(hipEventCreate(&e0));
   SPD_HIP(hipEventCreate(&e1));

@@ -6,6 +6,8 @@
 // independently, Section 1).
 #include "common.h"
 
+#include <algorithm>
+
 #include <cmath>
 
 namespace spd {
@@ -481,17 +483,20 @@ static void launch_skinny(hipStream_t s, const GemmProblem* d_p, const GemmTerm*
 // is read once for both of its products.
 template <int NC, int RG, int NW>
 __global__ __launch_bounds__(64 * NW) void k_symv(const SymProblem* __restrict__ probs,
-                                                   const SymTerm* __restrict__ terms, int tiles_max) {
+                                                   const SymTerm* __restrict__ terms, int tiles_max,
+                                                   int nwork) {
   constexpr int U = (RG == 1) ? 8 : 4;
   constexpr int V = U * NC;
   constexpr int TR = 64 * RG;
   __shared__ double red[NW / 2][TR][NC];
-  const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
-  const SymProblem P = probs[p];
-  const int i0 = tile * TR;
-  if (i0 >= P.m || P.n <= 0) return;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // a capped grid walks the (problem, row tile) items with a stride
+  for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
+  const int p = item / tiles_max, tile = item % tiles_max;
+  const SymProblem P = probs[p];
+  const int i0 = tile * TR;
+  if (i0 >= P.m || P.n <= 0) continue;
   const int n = P.n;
   int jc[NC];
 #pragma unroll
@@ -598,43 +603,44 @@ __global__ __launch_bounds__(64 * NW) void k_symv(const SymProblem* __restrict__
       }
     }
   }
+  }
 }
 
 int symv_row_tile(int max_m) { return max_m <= 64 ? 64 : (max_m <= 128 ? 128 : 256); }
 
 template <int NC, int NW>
 static void launch_symv_nw(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
-                           int max_m) {
-  if (max_m <= 64) {
-    hipLaunchKernelGGL((k_symv<NC, 1, NW>), dim3((unsigned)nprob), dim3(64 * NW), 0, s, d_p, d_t, 1);
-  } else if (max_m <= 128) {
-    hipLaunchKernelGGL((k_symv<NC, 2, NW>), dim3((unsigned)nprob), dim3(64 * NW), 0, s, d_p, d_t, 1);
-  } else {
-    const int tiles = ceil_div(max_m, 256);
-    hipLaunchKernelGGL((k_symv<NC, 4, NW>), dim3((unsigned)nprob * tiles), dim3(64 * NW), 0, s, d_p,
-                       d_t, tiles);
-  }
+                           int max_m, int cap) {
+  const int tiles = max_m <= 128 ? 1 : ceil_div(max_m, 256);
+  const int nwork = nprob * tiles;
+  const dim3 grid((unsigned)(cap > 0 ? std::min(cap, nwork) : nwork));
+  if (max_m <= 64)
+    hipLaunchKernelGGL((k_symv<NC, 1, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, 1, nwork);
+  else if (max_m <= 128)
+    hipLaunchKernelGGL((k_symv<NC, 2, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, 1, nwork);
+  else
+    hipLaunchKernelGGL((k_symv<NC, 4, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, tiles, nwork);
 }
 
 // 16-wave workgroups for small launches with one right-hand column only (more
 // columns would not fit the register budget of a 1024-thread workgroup).
 template <int NC>
 static void launch_symv_nc(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
-                           int max_m) {
+                           int max_m, int cap) {
   const int64_t blocks = (int64_t)nprob * ceil_div(max_m, 256);
-  if (NC == 1 && blocks < kSkinnyWide)
-    launch_symv_nw<NC, 16>(s, d_p, d_t, nprob, max_m);
+  if (NC == 1 && blocks < kSkinnyWide && cap <= 0)
+    launch_symv_nw<NC, 16>(s, d_p, d_t, nprob, max_m, cap);
   else
-    launch_symv_nw<NC, 4>(s, d_p, d_t, nprob, max_m);
+    launch_symv_nw<NC, 4>(s, d_p, d_t, nprob, max_m, cap);
 }
 
 void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
-                 int max_n) {
+                 int max_n, int cap) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
   if (max_n > 4) throw Error(SPD_E_INVALID, "symmetric-pair product supports at most 4 columns");
-  if (max_n == 1) launch_symv_nc<1>(s, d_p, d_t, nprob, max_m);
-  else if (max_n == 2) launch_symv_nc<2>(s, d_p, d_t, nprob, max_m);
-  else launch_symv_nc<4>(s, d_p, d_t, nprob, max_m);
+  if (max_n == 1) launch_symv_nc<1>(s, d_p, d_t, nprob, max_m, cap);
+  else if (max_n == 2) launch_symv_nc<2>(s, d_p, d_t, nprob, max_m, cap);
+  else launch_symv_nc<4>(s, d_p, d_t, nprob, max_m, cap);
   SPD_HIP(hipGetLastError());
 }
 
@@ -679,7 +685,20 @@ __global__ __launch_bounds__(256) void k_block(const BlockProblem* __restrict__ 
     if (i >= P.m || j >= P.n) continue;
     double* d = P.dst + i + (int64_t)j * P.ldd;
     double v = (P.beta != 0.0) ? P.beta * (*d) : 0.0;
-    for (int t = P.term_begin; t < P.term_end; ++t) {
+    // terms in groups of 8: the loads of a group are issued together, the sum
+    // keeps term order
+    int t = P.term_begin;
+    for (; t + 8 <= P.term_end; t += 8) {
+      double x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const BlockTerm T = terms[t + q];
+        x[q] = T.alpha * (T.trans ? T.src[j + (int64_t)i * T.lds] : T.src[i + (int64_t)j * T.lds]);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v += x[q];
+    }
+    for (; t < P.term_end; ++t) {
       const BlockTerm T = terms[t];
       v += T.alpha * (T.trans ? T.src[j + (int64_t)i * T.lds] : T.src[i + (int64_t)j * T.lds]);
     }

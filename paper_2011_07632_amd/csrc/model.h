@@ -97,6 +97,7 @@ struct LaunchRec {
   double bytes;  // algorithmic bytes: every A operand once, distinct B operands once, C once
   int tag = -1;  // caller-defined label (which pass of a product)
   int max_k = 1 << 30;  // bound on the terms' inner dimension (gemm records)
+  int cap = 0;          // workgroup cap (symmetric-pair records), 0 = none
 };
 // One block row of a symmetric product with at most 4 right-hand columns:
 // y = sum_t A_t B_t, and every mirrored term (an off-diagonal block A_ij of a
@@ -142,6 +143,10 @@ struct H2Model {
   Arena arena;
   Stage stage;
   hipStream_t s = nullptr;
+  // side stream of the product (the near-field pass runs beside the far-field
+  // chain) and its fork/join events; created with the first product plan
+  hipStream_t side_s = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double* pts = nullptr;        // SoA, tree order: x[N] y[N] z[N]
   int64_t* perm_d = nullptr;    // tree position -> original index
   // per node (heap order)
