@@ -122,6 +122,7 @@ def main():
     ap.add_argument("--maxit", type=int, default=20000)
     ap.add_argument("--cpu-sample", type=int, default=6000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision step")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection mode: build the H^2 matrix, run a 2 GiB copy (counter "
                          "calibration) and one product, then exit; run under rocprofv3 --pmc")
@@ -158,15 +159,16 @@ def main():
         log(f"[bench] counters mode done (source {source_hash()})")
         return
 
-    def step():
+    def step(precision="f64"):
         t0 = time.perf_counter()
         hss = P.spdhss_build(h2, w.hss_tol, w.max_rank, w.oversample, omega=om)
-        ulv = P.ulv_factor(hss)
+        ulv = P.ulv_factor(hss, precision=precision)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, it, res = P.pcg_solve(h2, ulv, b, rtol=w.pcg_tol, maxit=args.maxit, out=x)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        step.ulv = ulv
         return t1 - t0, t2 - t1, it, res
 
     for i in range(args.warmup):
@@ -184,6 +186,23 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = 1e3 * wall / args.steps
+    ulv64 = step.ulv
+
+    # mixed-precision form (solve operators in FP32, everything else FP64), one
+    # untimed-for-`value` step beside the plain form, with its apply error
+    mixed = None
+    if not args.no_mixed:
+        tb, ts, it32, res32 = step("f32")
+        v = cols_like(w.n, 1, dev).copy_(torch.from_numpy(workloads.gaussian_matrix(w.n, 1, 4242)))
+        a64 = P.ulv_apply(ulv64, v)
+        a32 = P.ulv_apply(step.ulv, v)
+        diff = float(torch.linalg.norm(a32 - a64) / torch.linalg.norm(a64))
+        mixed = {"value": round(tb + ts, 4), "unit": "s", "build_s": round(tb, 4), "solve_s": round(ts, 4),
+                 "pcg_iterations": int(it32.max()), "relres_max": float(res32.max()),
+                 "precision": "FP32 solve operators; FP64 H^2 product, vectors, residuals and dots",
+                 "apply_rel_diff_vs_f64": float(f"{diff:.3e}")}
+        log(f"[bench] mixed: build {tb:.3f} s solve {ts:.3f} s iterations {int(it32.max())} "
+            f"relres {float(res32.max()):.2e} apply diff {diff:.2e}")
 
     # dominant kernel of the timed region: the slowest launch of the H^2 product
     # that PCG calls every iteration, timed with HIP events on its stream
@@ -230,6 +249,7 @@ def main():
         "h2_rel_err_sampled": float(f"{h2_err:.3e}"),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "mixed": mixed,
     }
     print(json.dumps(out), flush=True)
 

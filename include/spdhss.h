@@ -115,6 +115,26 @@ spd_status spdhss_build(spd_h2_t A, const spd_hss_opts* opts, void* stream,
  * and factors the root block I + bold B_root (eqs. Aii0, Si0, Si). */
 spd_status ulv_factor(spd_hss_t M, void* stream, spd_ulv_t* out);
 
+/* Precision of the solve operators of a factorization. */
+typedef enum {
+  SPD_SOLVE_F64 = 0, /* every operator and sum in FP64 */
+  SPD_SOLVE_F32 = 1  /* the per-level solve operators stored in FP32 and read
+                        as FP32; vectors and sums stay FP64 */
+} spd_solve_precision;
+
+/* ulv_factor with a choice of precision for the solve operators (the
+ * preconditioner side of PCG, Section 6: the preconditioner only has to be
+ * SPD and close to A, so its operators can be rounded to FP32; the H^2
+ * operator, the residuals and the dot products of PCG stay FP64, so the
+ * attainable residual is unchanged).  SPD_SOLVE_F32 halves the bytes of each
+ * apply with at most 4 right-hand sides (more columns use the FP64
+ * operators); ulv_apply then differs from the FP64 apply by about the FP32
+ * rounding of the operators, and pcg_solve switches to the flexible
+ * (Polak-Ribiere) beta, which tolerates that inexactness.
+ * precision: spd_solve_precision; other values give SPD_E_INVALID.  The
+ * FP32 copies are kept with the nested factors (shared with the HSS handle). */
+spd_status ulv_factor_ex(spd_hss_t M, int32_t precision, void* stream, spd_ulv_t* out);
+
 /* x = M^{-1} b for the factored HSS matrix; b, x: DEVICE N x nrhs, ld >= N,
  * original order.  b and x may alias. */
 spd_status ulv_apply(spd_ulv_t F, const double* b, double* x, int32_t nrhs,

@@ -60,6 +60,7 @@ def _load():
         "h2_build": [vp, i64, _Kernel, C.POINTER(_H2Opts), vp, C.POINTER(vp)],
         "spdhss_build": [vp, C.POINTER(_HSSOpts), vp, C.POINTER(vp)],
         "ulv_factor": [vp, vp, C.POINTER(vp)],
+        "ulv_factor_ex": [vp, C.c_int32, vp, C.POINTER(vp)],
         "ulv_apply": [vp, vp, vp, i32, i64, vp],
         "h2_matvec": [vp, vp, vp, i32, i64, vp],
         "pcg_solve": [vp, vp, vp, vp, i32, i64, dbl, i32, vp, vp, vp],
@@ -293,9 +294,14 @@ def spdhss_build(A: H2Matrix, tol: float, max_rank: int = 100, oversample: int =
     return HSSMatrix(out.value, A, s)
 
 
-def ulv_factor(M: HSSMatrix, stream=None) -> ULVFactor:
+SOLVE_PRECISION = {"f64": 0, "f32": 1}
+
+
+def ulv_factor(M: HSSMatrix, stream=None, precision: str = "f64") -> ULVFactor:
+    """precision "f32": solve operators stored and read in FP32 (FP64 vectors
+    and sums); PCG then uses the flexible beta."""
     out = C.c_void_p()
-    _check(lib.ulv_factor(M._h, _stream(stream), C.byref(out)))
+    _check(lib.ulv_factor_ex(M._h, SOLVE_PRECISION[precision], _stream(stream), C.byref(out)))
     return ULVFactor(out.value, M.n, M.device)
 
 

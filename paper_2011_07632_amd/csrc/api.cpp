@@ -94,14 +94,21 @@ spd_status spdhss_build(spd_h2_t A, const spd_hss_opts* opts, void* stream, spd_
   SPD_API_END
 }
 
-spd_status ulv_factor(spd_hss_t M, void* stream, spd_ulv_t* out) {
+spd_status ulv_factor_ex(spd_hss_t M, int32_t precision, void* stream, spd_ulv_t* out) {
   if (out) *out = nullptr;
   SPD_API_BEGIN
   SPD_REQUIRE(M && out, SPD_E_INVALID, "null argument");
+  SPD_REQUIRE(precision == SPD_SOLVE_F64 || precision == SPD_SOLVE_F32, SPD_E_INVALID,
+              "unknown solve precision");
   std::unique_ptr<spd_ulv> u(new spd_ulv());
+  u->m.precision = precision;
   ulv_factor_impl(M->m, u->m, as_stream(stream));
   *out = u.release();
   SPD_API_END
+}
+
+spd_status ulv_factor(spd_hss_t M, void* stream, spd_ulv_t* out) {
+  return ulv_factor_ex(M, SPD_SOLVE_F64, stream, out);
 }
 
 spd_status ulv_apply(spd_ulv_t F, const double* b, double* x, int32_t nrhs, int64_t ld,

@@ -145,7 +145,14 @@ struct CpqrProblem {
 // dot-form product (op(A) = A^T stored K x m, at most 4 columns); max_k bounds
 // the terms' K
 void launch_gemv_t(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob, int max_m,
-                   int max_n, int max_k, int transB);
+                   int max_n, int max_k, int transB, int a_f32 = 0);
+// FP32 copy of an FP64 array
+struct CvtProblem {
+  const double* src;
+  float* dst;
+  int64_t n;
+};
+void launch_to_f32(hipStream_t s, const CvtProblem* d_p, int nprob);
 // cap > 0 bounds the number of workgroups (they then walk the problems with a
 // stride), so that the launch can run beside latency-bound work
 void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
@@ -154,8 +161,9 @@ void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int n
 int symv_row_tile(int max_m);
 // max_k bounds the terms' inner dimension (used to pick the dot-form variant
 // when transA is set and there are at most 4 columns)
+// a_f32: the A operands are FP32 (dot-form product only)
 void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
-                 int max_m, int max_n, int transA, int transB, int max_k = 1 << 30);
+                 int max_m, int max_n, int transA, int transB, int max_k = 1 << 30, int a_f32 = 0);
 void launch_block(hipStream_t s, const BlockProblem* d_p, const BlockTerm* d_t,
                   int nprob, int max_m, int max_n);
 void launch_kblock(hipStream_t s, const KBlockProblem* d_p, int nprob, int max_m,
@@ -189,12 +197,13 @@ void launch_coldot_partial(hipStream_t s, const double* x, const double* y, int6
                            int64_t ld, double* partial);
 void launch_pcg_xr_dot(hipStream_t s, double* x, double* r, const double* p, const double* q,
                        const double* rzp, const double* pqp, const int* active, int64_t n, int ncols,
-                       int64_t ld, int* iters, double* rzv, double* rrp);
+                       int64_t ld, int* iters, double* rzv, double* rrp, const double* zold = nullptr,
+                       double* rzop = nullptr);
 void launch_pcg_active_partial(hipStream_t s, const double* rrp, int64_t n, const double* bb,
                                double rtol, int* active, int ncols, int* any_active);
 void launch_pcg_update_p_partial(hipStream_t s, double* p, const double* z, const double* rzp,
                                  const double* rzv, const int* active, int64_t n, int ncols,
-                                 int64_t ld);
+                                 int64_t ld, const double* rzop = nullptr);
 void launch_coldot(hipStream_t s, const double* x, const double* y, int64_t n,
                    int ncols, int64_t ld, double* partial, double* out);
 void launch_pcg_update_xr(hipStream_t s, double* x, double* r, const double* p,

@@ -367,7 +367,7 @@ static void launch_skinny_nw(hipStream_t s, const GemmProblem* d_p, const GemmTe
 // (no LDS, no barrier).  This is the kernel for the small per-level products
 // of the solve sweeps and of the H^2 interpolation, whose cost is the chain of
 // dependent memory round trips rather than bandwidth.
-template <int NC, int U, int KU>
+template <int NC, int U, int KU, typename TA>
 __global__ __launch_bounds__(256) void k_gemv_t(const GemmProblem* __restrict__ probs,
                                                const GemmTerm* __restrict__ terms, int tiles_max,
                                                int transB) {
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemmProblem* __restrict__ 
     const int K = T.k;
     const int64_t lda = T.lda, ldb = T.ldb;
     const double sc = T.scale;
-    gdouble* A = (gdouble*)T.A;
+    const TA __attribute__((address_space(1)))* A = (const TA __attribute__((address_space(1)))*)T.A;
     gdouble* B = (gdouble*)T.B;
     const int* __restrict__ bidx = T.bidx;
     // op(B)(k, j) = transB ? B[j + k ldb] : B[k + j ldb]
@@ -410,7 +410,8 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemmProblem* __restrict__ 
 #pragma unroll
         for (int j = 0; j < NC; ++j) b[q][j] = k < K ? B[brow * bks + jc[j] * bjs] : 0.0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) a[u][q] = __builtin_nontemporal_load(&A[kc + (int64_t)rc[u] * lda]);
+        for (int u = 0; u < U; ++u)
+          a[u][q] = (double)__builtin_nontemporal_load(&A[kc + (int64_t)rc[u] * lda]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -439,24 +440,45 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemmProblem* __restrict__ 
 }
 
 // rows per workgroup of the dot-form kernel: 4 waves of U rows
-template <int NC, int U>
+template <int NC, int U, typename TA>
 static void launch_gemv_t_u(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
                             int max_m, int max_k, int transB) {
   const int tiles = ceil_div(max_m, 4 * U);
   const dim3 grid((unsigned)nprob * tiles);
   if (max_k <= 256)
-    hipLaunchKernelGGL((k_gemv_t<NC, U, 4>), grid, dim3(256), 0, s, d_p, d_t, tiles, transB);
+    hipLaunchKernelGGL((k_gemv_t<NC, U, 4, TA>), grid, dim3(256), 0, s, d_p, d_t, tiles, transB);
   else
-    hipLaunchKernelGGL((k_gemv_t<NC, U, 8>), grid, dim3(256), 0, s, d_p, d_t, tiles, transB);
+    hipLaunchKernelGGL((k_gemv_t<NC, U, 8, TA>), grid, dim3(256), 0, s, d_p, d_t, tiles, transB);
+}
+
+template <typename TA>
+static void launch_gemv_t_ta(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
+                             int max_m, int max_n, int max_k, int transB) {
+  if (max_n == 1) launch_gemv_t_u<1, 4, TA>(s, d_p, d_t, nprob, max_m, max_k, transB);
+  else if (max_n == 2) launch_gemv_t_u<2, 2, TA>(s, d_p, d_t, nprob, max_m, max_k, transB);
+  else launch_gemv_t_u<4, 1, TA>(s, d_p, d_t, nprob, max_m, max_k, transB);
 }
 
 void launch_gemv_t(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob, int max_m,
-                   int max_n, int max_k, int transB) {
+                   int max_n, int max_k, int transB, int a_f32) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
   if (max_n > 4) throw Error(SPD_E_INVALID, "dot-form product supports at most 4 columns");
-  if (max_n == 1) launch_gemv_t_u<1, 4>(s, d_p, d_t, nprob, max_m, max_k, transB);
-  else if (max_n == 2) launch_gemv_t_u<2, 2>(s, d_p, d_t, nprob, max_m, max_k, transB);
-  else launch_gemv_t_u<4, 1>(s, d_p, d_t, nprob, max_m, max_k, transB);
+  if (a_f32) launch_gemv_t_ta<float>(s, d_p, d_t, nprob, max_m, max_n, max_k, transB);
+  else launch_gemv_t_ta<double>(s, d_p, d_t, nprob, max_m, max_n, max_k, transB);
+  SPD_HIP(hipGetLastError());
+}
+
+// FP32 copies of FP64 arrays: one descriptor per array, grid over (array, chunk)
+__global__ __launch_bounds__(256) void k_to_f32(const CvtProblem* __restrict__ probs, int chunks) {
+  const CvtProblem P = probs[blockIdx.x / chunks];
+  const int64_t chunk = (P.n + chunks - 1) / chunks;
+  const int64_t lo = (blockIdx.x % chunks) * chunk, hi = min(P.n, lo + chunk);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) P.dst[i] = (float)P.src[i];
+}
+void launch_to_f32(hipStream_t s, const CvtProblem* d_p, int nprob) {
+  if (nprob <= 0) return;
+  constexpr int chunks = 16;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)nprob * chunks), dim3(256), 0, s, d_p, chunks);
   SPD_HIP(hipGetLastError());
 }
 
@@ -645,12 +667,13 @@ void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int n
 }
 
 void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
-                 int max_m, int max_n, int transA, int transB, int max_k) {
+                 int max_m, int max_n, int transA, int transB, int max_k, int a_f32) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
   if (transA && max_n <= 4) {
-    launch_gemv_t(s, d_p, d_t, nprob, max_m, max_n, max_k, transB);
+    launch_gemv_t(s, d_p, d_t, nprob, max_m, max_n, max_k, transB, a_f32);
     return;
   }
+  if (a_f32) throw Error(SPD_E_INVALID, "FP32 A only in the dot-form product (transposed, <= 4 columns)");
   if (max_n <= 4) {
     if (max_n == 1) launch_skinny<1>(s, d_p, d_t, nprob, max_m, transA, transB);
     else if (max_n <= 2) launch_skinny<2>(s, d_p, d_t, nprob, max_m, transA, transB);
@@ -1474,6 +1497,7 @@ __device__ __forceinline__ double chunk_sum(const double* __restrict__ partial, 
 // x += alpha p, r -= alpha q with alpha = (r.z) / (p.q), then the partial sums
 // of the updated r.r; block (0, c) counts the iteration and records r.z for
 // the next beta.
+// With zold set (flexible form), the partial sums of r_new . z_old go to rzop.
 __global__ __launch_bounds__(256) void k_pcg_xr_dot(double* __restrict__ x, double* __restrict__ r,
                                                     const double* __restrict__ p,
                                                     const double* __restrict__ q,
@@ -1482,8 +1506,10 @@ __global__ __launch_bounds__(256) void k_pcg_xr_dot(double* __restrict__ x, doub
                                                     const int* __restrict__ active, int64_t n,
                                                     int64_t ld, int* __restrict__ iters,
                                                     double* __restrict__ rzv,
-                                                    double* __restrict__ rrp) {
-  __shared__ double red[4];
+                                                    double* __restrict__ rrp,
+                                                    const double* __restrict__ zold,
+                                                    double* __restrict__ rzop) {
+  __shared__ double red[4], red2[4];
   const int b = blockIdx.x, c = blockIdx.y;
   if (!active[c]) return;
   const double rz = chunk_sum(rzp, nblk, c);
@@ -1493,17 +1519,25 @@ __global__ __launch_bounds__(256) void k_pcg_xr_dot(double* __restrict__ x, doub
     rzv[c] = rz;
   }
   const int64_t lo = (int64_t)b * DOT_CHUNK, hi = min(n, lo + DOT_CHUNK);
-  double sacc = 0.0;
+  double sacc = 0.0, sz = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
     x[i + c * ld] += alpha * p[i + c * ld];
     const double rn = r[i + c * ld] - alpha * q[i + c * ld];
     r[i + c * ld] = rn;
     sacc += rn * rn;
+    if (zold) sz += rn * zold[i + c * ld];
   }
   sacc = wave_sum(sacc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sacc;
+  if (zold) {
+    sz = wave_sum(sz);
+    if ((threadIdx.x & 63) == 0) red2[threadIdx.x >> 6] = sz;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) rrp[b + (int64_t)c * nblk] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) {
+    rrp[b + (int64_t)c * nblk] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (zold) rzop[b + (int64_t)c * nblk] = (red2[0] + red2[1]) + (red2[2] + red2[3]);
+  }
 }
 
 // active[c] stays set while ||r_c|| > rtol ||b_c||, with r.r from its partials
@@ -1524,15 +1558,20 @@ __global__ void k_pcg_active_partial(const double* __restrict__ rrp, int nblk,
   if (threadIdx.x == 0) *any_active = any;
 }
 
-// p = z + beta p with beta = (r.z)_new / (r.z)_old, (r.z)_new from its partials
+// p = z + beta p with beta = (r.z)_new / (r.z)_old, (r.z)_new from its
+// partials; with rzop set (flexible form, for an inexact preconditioner)
+// beta = (r_new . (z_new - z_old)) / (r.z)_old.
 __global__ void k_pcg_update_p_partial(double* __restrict__ p, const double* __restrict__ z,
                                        const double* __restrict__ rzp, int nblk,
                                        const double* __restrict__ rzv,
-                                       const int* __restrict__ active, int64_t n, int64_t ld) {
+                                       const int* __restrict__ active, int64_t n, int64_t ld,
+                                       const double* __restrict__ rzop) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (!active[c] || i >= n) return;
-  const double beta = chunk_sum(rzp, nblk, c) / rzv[c];
+  double num = chunk_sum(rzp, nblk, c);
+  if (rzop) num -= chunk_sum(rzop, nblk, c);
+  const double beta = num / rzv[c];
   p[i + c * ld] = z[i + c * ld] + beta * p[i + c * ld];
 }
 
@@ -1548,10 +1587,11 @@ int coldot_chunks(int64_t n) { return ceil_div(n, DOT_CHUNK); }
 
 void launch_pcg_xr_dot(hipStream_t s, double* x, double* r, const double* p, const double* q,
                        const double* rzp, const double* pqp, const int* active, int64_t n, int ncols,
-                       int64_t ld, int* iters, double* rzv, double* rrp) {
+                       int64_t ld, int* iters, double* rzv, double* rrp, const double* zold,
+                       double* rzop) {
   const int nblk = ceil_div(n, DOT_CHUNK);
   hipLaunchKernelGGL(k_pcg_xr_dot, dim3(nblk, ncols), dim3(256), 0, s, x, r, p, q, rzp, pqp, nblk,
-                     active, n, ld, iters, rzv, rrp);
+                     active, n, ld, iters, rzv, rrp, zold, rzop);
   SPD_HIP(hipGetLastError());
 }
 
@@ -1564,9 +1604,9 @@ void launch_pcg_active_partial(hipStream_t s, const double* rrp, int64_t n, cons
 
 void launch_pcg_update_p_partial(hipStream_t s, double* p, const double* z, const double* rzp,
                                  const double* rzv, const int* active, int64_t n, int ncols,
-                                 int64_t ld) {
+                                 int64_t ld, const double* rzop) {
   hipLaunchKernelGGL(k_pcg_update_p_partial, dim3(ceil_div(n, 256), ncols), dim3(256), 0, s, p, z, rzp,
-                     ceil_div(n, DOT_CHUNK), rzv, active, n, ld);
+                     ceil_div(n, DOT_CHUNK), rzv, active, n, ld, rzop);
   SPD_HIP(hipGetLastError());
 }
 

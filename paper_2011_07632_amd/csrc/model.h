@@ -58,6 +58,7 @@ struct GemmBatch {
   std::vector<GemmProblem> probs;
   std::vector<GemmTerm> terms;
   int max_m = 0, max_n = 0, transA = 0, transB = 0, max_k = 0;
+  int a_f32 = 0;  // A operands are FP32 (set before adding terms)
   explicit GemmBatch(int ta = 0, int tb = 0) : transA(ta), transB(tb) {}
   void add(double* C, int m, int n, int ldc, double beta = 0.0, double alpha = 1.0);
   void term(const double* A, int lda, const double* B, int ldb, int k, double scale = 1.0);
@@ -98,6 +99,7 @@ struct LaunchRec {
   int tag = -1;  // caller-defined label (which pass of a product)
   int max_k = 1 << 30;  // bound on the terms' inner dimension (gemm records)
   int cap = 0;          // workgroup cap (symmetric-pair records), 0 = none
+  int a_f32 = 0;        // FP32 A operands (gemm records)
 };
 // One block row of a symmetric product with at most 4 right-hand columns:
 // y = sum_t A_t B_t, and every mirrored term (an off-diagonal block A_ij of a
@@ -207,6 +209,9 @@ struct Factors {
   //   Dm: leaf A_vv^{-1} = S_v^{-T} S_v^{-1}; nonleaf and root (I + bold B_vv)^{-1} - I
   //   Zs: Z_v = S_v^{-T} V_v (leaf) or F_v^{-T} V-bar_v (nonleaf); ZsT: Z_v^T
   std::vector<double*> Dm, Zs, ZsT;
+  // FP32 copies of Dm, Zs, ZsT for the mixed-precision apply
+  std::vector<float*> Dm32, Zs32, ZsT32;
+  bool ops32_ready = false;
   bool root_factored = false;
   bool ops_ready = false;  // Dm, Zs, ZsT formed
   // stacked rank-space layout: the children of p share a rho_p-row buffer
@@ -240,6 +245,7 @@ void spdhss_build_impl(H2Model& H, const spd_hss_opts& o, HSSModel& M, hipStream
 
 struct ULVModel {
   std::shared_ptr<Factors> f;
+  int precision = 0;  // 0: FP64 apply; 1: FP32 operators, FP64 vectors and sums
   Stage stage;
   hipStream_t s = nullptr;
   struct ApplyPlan;

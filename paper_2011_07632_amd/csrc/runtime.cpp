@@ -126,7 +126,7 @@ void GemmBatch::add(double* C, int m, int n, int ldc, double beta, double alpha)
 void GemmBatch::term(const double* A, int lda, const double* B, int ldb, int k, double scale) {
   if (k <= 0) return;
   GemmProblem& p = probs.back();
-  if (p.term_end > p.term_begin && !terms.back().bidx) {
+  if (p.term_end > p.term_begin && !terms.back().bidx && !a_f32) {
     GemmTerm& q = terms.back();
     const int64_t acs = transA ? 1 : q.lda, bcs = transB ? q.ldb : 1;
     if (q.lda == lda && (q.ldb == ldb || (p.n == 1 && !transB)) && q.scale == scale &&
@@ -183,7 +183,7 @@ void GemmBatch::run(hipStream_t s, Stage& st) {
   auto* dp = (const GemmProblem*)st.push(s, probs.data(), probs.size() * sizeof(GemmProblem));
   auto* dt = (const GemmTerm*)st.push(s, terms.empty() ? &dummy : terms.data(),
                                       std::max<size_t>(1, terms.size()) * sizeof(GemmTerm));
-  launch_gemm(s, dp, dt, (int)probs.size(), max_m, max_n, transA, transB, std::max(max_k, 1));
+  launch_gemm(s, dp, dt, (int)probs.size(), max_m, max_n, transA, transB, std::max(max_k, 1), a_f32);
 }
 
 void BlockBatch::add(double* dst, int m, int n, int ldd, double beta, int add_eye) {
@@ -266,7 +266,7 @@ static double batch_bytes(const GemmBatch& b) {
     if (p.cidx) bytes += 4.0 * p.m;
     for (int q = p.term_begin; q < p.term_end; ++q) {
       const GemmTerm& g = b.terms[q];
-      bytes += 8.0 * p.m * g.k;
+      bytes += (b.a_f32 ? 4.0 : 8.0) * p.m * g.k;
       if (g.bidx) {
         bytes += 8.0 * g.k * p.n + 4.0 * g.k;  // gathered rows and their indices
         continue;
@@ -297,7 +297,7 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
   };
   if (b.indexed && b.max_n > 4) throw Error(SPD_E_INVALID, "indexed products support at most 4 columns");
   bool split = false;
-  if (b.max_n <= 16 && !b.indexed)
+  if (b.max_n <= 16 && !b.indexed && !b.a_f32)
     for (const GemmProblem& p : b.probs)
       if (8.0 * p.m * width(p) > kSplitBytes && width(p) > 1) { split = true; break; }
   if (!split) {
@@ -306,6 +306,7 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
     recs.push_back({0, keep(a, s, b.probs), keep(a, s, t), (int)b.probs.size(), b.max_m, b.max_n,
                     b.transA, b.transB, bytes, -1});
     recs.back().max_k = std::max(b.max_k, 1);
+    recs.back().a_f32 = b.a_f32;
     return;
   }
   GemmBatch parts(b.transA, b.transB);
@@ -506,7 +507,7 @@ void Recorder::replay(hipStream_t s) const {
   for (const LaunchRec& r : recs) {
     if (r.type == 0)
       launch_gemm(s, (const GemmProblem*)r.probs, (const GemmTerm*)r.terms, r.nprob, r.max_m,
-                  r.max_n, r.transA, r.transB, r.max_k);
+                  r.max_n, r.transA, r.transB, r.max_k, r.a_f32);
     else if (r.type == 1)
       launch_block(s, (const BlockProblem*)r.probs, (const BlockTerm*)r.terms, r.nprob, r.max_m,
                    r.max_n);

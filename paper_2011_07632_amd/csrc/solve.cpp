@@ -91,6 +91,36 @@ static void form_solve_ops(Factors& F, const HSSModel& M, Stage& st, hipStream_t
   F.ops_ready = true;
 }
 
+// FP32 copies of the solve operators for the mixed-precision apply.
+static void form_solve_ops_f32(Factors& F, Stage& st, hipStream_t s) {
+  if (F.ops32_ready) return;
+  const int nn = F.T.nnodes;
+  F.Dm32.assign(nn, nullptr);
+  F.Zs32.assign(nn, nullptr);
+  F.ZsT32.assign(nn, nullptr);
+  std::vector<CvtProblem> cv;
+  auto copy = [&](const double* src, float*& dst, int64_t n) {
+    if (!src || n <= 0) return;
+    dst = F.arena.get_n<float>((size_t)n);
+    cv.push_back({src, dst, n});
+  };
+  for (int v = 0; v < nn; ++v) {
+    const int64_t n = F.rho[v], r = F.r[v];
+    copy(F.Dm[v], F.Dm32[v], n * n);
+    if (F.Zs[v]) {
+      copy(F.Zs[v], F.Zs32[v], n * r);
+      copy(F.ZsT[v], F.ZsT32[v], n * r);
+    }
+  }
+  if (!cv.empty()) {
+    auto* d = (const CvtProblem*)st.push(s, cv.data(), cv.size() * sizeof(CvtProblem));
+    launch_to_f32(s, d, (int)cv.size());
+  }
+  SPD_HIP(hipStreamSynchronize(s));
+  st.reset();
+  F.ops32_ready = true;
+}
+
 void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
   U.f = M.f;
   U.s = s;
@@ -99,6 +129,7 @@ void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
   if (T.L == 1 || F.root_factored) {
     F.root_factored = true;
     form_solve_ops(F, M, U.stage, s);
+    if (U.precision == 1) form_solve_ops_f32(F, U.stage, s);
     return;
   }
   const int c1 = 1, c2 = 2, r1 = F.r[c1], r2 = F.r[c2], rv = r1 + r2;
@@ -133,6 +164,7 @@ void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
   SPD_HIP(hipStreamSynchronize(s));
   F.root_factored = true;
   form_solve_ops(F, M, U.stage, s);
+  if (U.precision == 1) form_solve_ops_f32(F, U.stage, s);
 }
 
 // The sweeps as batched products, one launch per level.  With at most 4
@@ -154,10 +186,20 @@ static void build_apply_plan(ULVModel& U, int m) {
   const int lf = T.first_at(1), lc = T.count_at(1);
   const int Ni = (int)N;
   const int tA = m <= 4 ? 1 : 0;
-  if (L == 1) {
+  // mixed precision: FP32 operators in the dot-form products (<= 4 columns)
+  const bool f32 = tA && U.precision == 1;
+  auto op = [&](const std::vector<double*>& d, const std::vector<float*>& f, int v) -> const double* {
+    return f32 ? (const double*)f[v] : d[v];
+  };
+  auto batch = [&]() {
     GemmBatch g(tA, 0);
+    g.a_f32 = f32 ? 1 : 0;
+    return g;
+  };
+  if (L == 1) {
+    GemmBatch g = batch();
     g.add(pl->out, Ni, m, Ni);
-    g.term(F.Dm[0], Ni, pl->in, Ni, Ni);
+    g.term(op(F.Dm, F.Dm32, 0), Ni, pl->in, Ni, Ni);
     rec.gemm(a, s, g);
     SPD_HIP(hipStreamSynchronize(s));
     U.plan = std::move(pl);
@@ -168,22 +210,22 @@ static void build_apply_plan(ULVModel& U, int m) {
   pl->ds = a.get_n<double>((size_t)rows * m);
   // leaves: t_v = Z_v^T b_v
   {
-    GemmBatch g(tA, 0);
+    GemmBatch g = batch();
     for (int v = lf; v < lf + lc; ++v) {
       if (F.r[v] == 0) continue;
       g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
-      if (tA) g.term(F.Zs[v], F.rho[v], pl->in + T.start[v], Ni, F.rho[v]);
+      if (tA) g.term(op(F.Zs, F.Zs32, v), F.rho[v], pl->in + T.start[v], Ni, F.rho[v]);
       else g.term(F.ZsT[v], F.r[v], pl->in + T.start[v], Ni, F.rho[v]);
     }
     rec.gemm(a, s, g);
   }
   // upward: t_v = Z_v^T [t_c]
   for (int lev = 2; lev <= L - 1; ++lev) {
-    GemmBatch g(tA, 0);
+    GemmBatch g = batch();
     for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
       if (F.r[v] == 0 || F.rho[v] == 0) continue;
       g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
-      if (tA) g.term(F.Zs[v], F.rho[v], pl->ts + F.par_off[v] * m, F.rho[v], F.rho[v]);
+      if (tA) g.term(op(F.Zs, F.Zs32, v), F.rho[v], pl->ts + F.par_off[v] * m, F.rho[v], F.rho[v]);
       else g.term(F.ZsT[v], F.r[v], pl->ts + F.par_off[v] * m, F.rho[v], F.rho[v]);
     }
     rec.gemm(a, s, g);
@@ -191,21 +233,21 @@ static void build_apply_plan(ULVModel& U, int m) {
   // root: [d_c] = ((I + bold B_root)^{-1} - I) [t_c]
   if (F.rho[0] > 0) {
     const int rv = F.rho[0];
-    GemmBatch g(tA, 0);
+    GemmBatch g = batch();
     g.add(pl->ds + F.par_off[0] * m, rv, m, rv);
-    g.term(F.Dm[0], rv, pl->ts + F.par_off[0] * m, rv, rv);
+    g.term(op(F.Dm, F.Dm32, 0), rv, pl->ts + F.par_off[0] * m, rv, rv);
     rec.gemm(a, s, g);
   }
   // downward: [d_c] = ((I + bold B_v)^{-1} - I) [t_c] + Z_v d_v
   for (int lev = L - 1; lev >= 2; --lev) {
-    GemmBatch g(tA, 0);
+    GemmBatch g = batch();
     for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
       const int rv = F.rho[v];
       if (rv == 0) continue;
       g.add(pl->ds + F.par_off[v] * m, rv, m, rv);
-      g.term(F.Dm[v], rv, pl->ts + F.par_off[v] * m, rv, rv);
+      g.term(op(F.Dm, F.Dm32, v), rv, pl->ts + F.par_off[v] * m, rv, rv);
       if (F.r[v] > 0) {
-        if (tA) g.term(F.ZsT[v], F.r[v], F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
+        if (tA) g.term(op(F.ZsT, F.ZsT32, v), F.r[v], F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
         else g.term(F.Zs[v], rv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
       }
     }
@@ -213,13 +255,13 @@ static void build_apply_plan(ULVModel& U, int m) {
   }
   // leaves: x_v = A_vv^{-1} b_v + Z_v d_v
   {
-    GemmBatch g(tA, 0);
+    GemmBatch g = batch();
     for (int v = lf; v < lf + lc; ++v) {
       const int nv = F.rho[v];
       g.add(pl->out + T.start[v], nv, m, Ni);
-      g.term(F.Dm[v], nv, pl->in + T.start[v], Ni, nv);
+      g.term(op(F.Dm, F.Dm32, v), nv, pl->in + T.start[v], Ni, nv);
       if (F.r[v] > 0) {
-        if (tA) g.term(F.ZsT[v], F.r[v], F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
+        if (tA) g.term(op(F.ZsT, F.ZsT32, v), F.r[v], F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
         else g.term(F.Zs[v], nv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
       }
     }
@@ -302,6 +344,10 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   double* pqp = a.get_n<double>((size_t)nblk * m);
   double* rrp = a.get_n<double>((size_t)nblk * m);
   double* rzp = a.get_n<double>((size_t)nblk * m);
+  // flexible (Polak-Ribiere) beta when the preconditioner is applied in FP32:
+  // partials of r_new . z_old, taken before z is overwritten
+  const bool flexible = U && U->precision == 1;
+  double* rzop = flexible ? a.get_n<double>((size_t)nblk * m) : nullptr;
   double* sc = a.get_n<double>((size_t)8 * m);
   double* rz = sc, *rzv = sc + m, *rr = sc + 3 * m, *bb = sc + 4 * m;
   int* active = a.get_n<int>(2 * m + 1);
@@ -332,11 +378,12 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   auto body = [&]() {
     h2_plan_run(H);
     launch_coldot_partial(s, p, q, N, m, N, pqp);
-    launch_pcg_xr_dot(s, xt, r, p, q, rzp, pqp, active, N, m, N, iters, rzv, rrp);
+    launch_pcg_xr_dot(s, xt, r, p, q, rzp, pqp, active, N, m, N, iters, rzv, rrp,
+                      flexible ? z : nullptr, rzop);
     launch_pcg_active_partial(s, rrp, N, bb, rtol, active, m, any);
     precond(r, z);
     launch_coldot_partial(s, r, z, N, m, N, rzp);
-    launch_pcg_update_p_partial(s, p, z, rzp, rzv, active, N, m, N);
+    launch_pcg_update_p_partial(s, p, z, rzp, rzv, active, N, m, N, rzop);
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

@@ -110,3 +110,12 @@ def test_pcg_reaches_tolerance(F):
     print(f"[fullsize] PCG iterations {it.tolist()} true relative residual {res.tolist()}", flush=True)
     assert int(it.max()) < 20000
     assert float(res.max()) <= 2 * W.pcg_tol
+
+
+def test_pcg_mixed_precision_reaches_tolerance(F):
+    u32 = F.B.ulv_factor(F.hss, precision="f32")
+    b = cols(F, W.rhs())
+    _, it, res = F.B.pcg_solve(F.h2, u32, b, rtol=W.pcg_tol, maxit=20000)
+    print(f"[fullsize] mixed-precision PCG iterations {it.tolist()} true relative residual {res.tolist()}",
+          flush=True)
+    assert float(res.max()) <= 2 * W.pcg_tol
