@@ -113,6 +113,55 @@ def cpu_baseline(w, n_sample: int, iters_gpu: int, maxit_sample: int = 40) -> di
                        f"N={w.n} (build x N log N, iteration x N) and {iters_gpu} iterations")}
 
 
+def run_batch(args, torch, P):
+    """Independent instances (N log-uniform in [5k, 50k], three kernels, cube and
+    sphere, 4 right-hand sides, FP64 build and FP32 solve operators): all of
+    them one at a time (one worker), then concurrently; the results of the two
+    runs must agree bit for bit."""
+    from paper_2011_07632_amd.binding import cols_like
+    dev = "cuda"
+    ws = workloads.batch_instances(args.batch)
+    reqs = []
+    for w in ws:
+        reqs.append(dict(points=torch.from_numpy(w.points()).to(dev), kernel=w.kernel, ell=w.ell, shift=w.shift,
+                         leaf=w.leaf, h2_tol=w.h2_tol, hss_tol=w.hss_tol, max_rank=w.max_rank,
+                         oversample=w.oversample, b=cols_like(w.n, w.nrhs, dev).copy_(torch.from_numpy(w.rhs())),
+                         omega=cols_like(w.n, w.s, dev).copy_(torch.from_numpy(w.omega())),
+                         rtol=w.pcg_tol, maxit=5000, precision="f32"))
+    P.binding.solve_batch(reqs[:2], workers=2)  # warm-up
+    torch.cuda.synchronize()
+    runs = {}
+    for workers in (1, args.workers):
+        t0 = time.perf_counter()
+        out = P.binding.solve_batch(reqs, workers=workers)
+        torch.cuda.synchronize()
+        runs[workers] = (time.perf_counter() - t0, out)
+        log(f"[bench] batch of {len(ws)} with {workers} worker(s): {runs[workers][0]:.3f} s")
+    t1, o1 = runs[1]
+    tw, ow = runs[args.workers]
+    same = all(np.array_equal(a["x"].cpu().numpy(), b["x"].cpu().numpy()) and
+               a["iters"].tolist() == b["iters"].tolist() for a, b in zip(o1, ow))
+    status = {}
+    for o in ow:
+        status[o["status"]] = status.get(o["status"], 0) + 1
+    line = {"metric": "batched SPD-HSS build + PCG solves per second", "value": round(len(ws) / tw, 3),
+            "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64 build, f32 solve operators",
+            "data": "synthetic",
+            "config": {"workload": f"batch-{len(ws)}-N5k-50k-mixed-kernels", "instances": len(ws),
+                       "points_total": int(sum(w.n for w in ws)), "nrhs_each": 4, "leaf": 128,
+                       "hss_tol": 1e-2, "pcg_tol": 1e-8, "workers": args.workers},
+            "seconds_concurrent": round(tw, 3), "seconds_one_at_a_time": round(t1, 3),
+            "speedup": round(t1 / tw, 3), "results_identical": bool(same), "status_counts": status,
+            "iterations_max": int(max(int(o["iters"].max()) for o in ow)),
+            "relres_max": float(max(float(o["relres"].max()) for o in ow)),
+            "seconds_h2_sum": round(sum(o["seconds_h2"] for o in o1), 3),
+            "seconds_build_sum": round(sum(o["seconds_build"] for o in o1), 3),
+            "seconds_solve_sum": round(sum(o["seconds_solve"] for o in o1), 3),
+            "seconds_longest_instance": round(max(o["seconds_h2"] + o["seconds_build"] + o["seconds_solve"]
+                                                  for o in o1), 3)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +172,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision step")
+    ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
+                    help="batched mode: COUNT independent instances of uneven sizes, run one at a time "
+                         "and then concurrently (spd_solve_batch); prints its own JSON line")
+    ap.add_argument("--workers", type=int, default=8, help="worker threads of the batched mode")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection mode: build the H^2 matrix, run a 2 GiB copy (counter "
                          "calibration) and one product, then exit; run under rocprofv3 --pmc")
@@ -136,6 +189,9 @@ def main():
     import paper_2011_07632_amd as P
     from paper_2011_07632_amd.binding import cols_like
 
+    if args.batch:
+        run_batch(args, torch, P)
+        return
     w = workloads.BY_NAME[args.workload]
     dev = "cuda"
     X = torch.from_numpy(w.points()).to(dev)

@@ -156,6 +156,49 @@ spd_status pcg_solve(spd_h2_t A, spd_ulv_t M, const double* b, double* x,
                      int32_t nrhs, int64_t ld, double rtol, int32_t maxit,
                      void* stream, int32_t* iters, double* relres);
 
+/* ---- many independent instances ---------------------------------------
+ * One solve request: points, kernel and options as for h2_build and
+ * spdhss_build, then pcg_solve of b (nrhs columns) preconditioned by the
+ * factored HSS matrix with the given solve precision.  All arrays are DEVICE
+ * except iters/relres (HOST, nrhs entries each, may be NULL).  b and x are
+ * N x nrhs with ld = N, original point order. */
+typedef struct {
+  const double* points;     /* DEVICE n x 3 row-major */
+  int64_t n;
+  spd_kernel kernel;
+  spd_h2_opts h2;
+  spd_hss_opts hss;         /* hss.omega may be NULL (internal generator) */
+  int32_t solve_precision;  /* spd_solve_precision */
+  const double* b;
+  double* x;
+  int32_t nrhs;
+  double rtol;
+  int32_t maxit;
+  int32_t* iters;           /* HOST, may be NULL */
+  double* relres;           /* HOST, may be NULL */
+} spd_instance;
+
+typedef struct {
+  int32_t status;           /* spd_status of this instance */
+  int32_t iters_max;        /* largest iteration count over its columns */
+  double relres_max;        /* largest true relative residual over its columns */
+  double seconds_h2;        /* wall time of h2_build on its worker */
+  double seconds_build;     /* spdhss_build + ulv_factor */
+  double seconds_solve;     /* pcg_solve */
+} spd_instance_result;
+
+/* Run count independent instances end to end (h2_build, spdhss_build,
+ * ulv_factor_ex, pcg_solve, destroy) on `workers` host threads, each with its
+ * own HIP stream on the calling thread's device, so that the GPU works on
+ * several instances at once (the level-by-level rank read-backs of one
+ * instance block only its worker).  Every instance gives the same result as
+ * the same calls made alone.  Returns SPD_E_INVALID for bad arguments
+ * (count < 0, workers < 1, null pointers); otherwise SPD_OK, with each
+ * instance's own status in results[i] (its message is not kept).  The
+ * instances' device buffers must not overlap where they are written. */
+spd_status spd_solve_batch(const spd_instance* instances, int32_t count, int32_t workers,
+                           spd_instance_result* results);
+
 void h2_destroy(spd_h2_t A);
 void spdhss_destroy(spd_hss_t M);
 void ulv_destroy(spd_ulv_t F);

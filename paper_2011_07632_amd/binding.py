@@ -51,6 +51,18 @@ class _HSSOpts(C.Structure):
                 ("seed", C.c_uint64), ("omega", C.c_void_p)]
 
 
+class _Instance(C.Structure):
+    _fields_ = [("points", C.c_void_p), ("n", C.c_int64), ("kernel", _Kernel), ("h2", _H2Opts),
+                ("hss", _HSSOpts), ("solve_precision", C.c_int32), ("b", C.c_void_p), ("x", C.c_void_p),
+                ("nrhs", C.c_int32), ("rtol", C.c_double), ("maxit", C.c_int32),
+                ("iters", C.c_void_p), ("relres", C.c_void_p)]
+
+
+class _InstanceResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters_max", C.c_int32), ("relres_max", C.c_double),
+                ("seconds_h2", C.c_double), ("seconds_build", C.c_double), ("seconds_solve", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2011_07632_amd.build`")
@@ -72,6 +84,7 @@ def _load():
         "spd_test_chol": [vp, i32, i32, vp, vp],
         "spd_test_trsm": [vp, vp, i32, i32, i32, i32, i32, vp],
         "spd_test_cpqr": [vp, vp, vp, vp, vp, i32, i32, i32, i32, dbl, i32, vp],
+        "spd_solve_batch": [C.POINTER(_Instance), i32, i32, C.POINTER(_InstanceResult)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -396,3 +409,49 @@ def test_cpqr(A, Q, piv, rank, diag, maxrank, tol, which):
     batch, n, m = A.shape
     _check(lib.spd_test_cpqr(A.data_ptr(), _ptr(Q), piv.data_ptr(), rank.data_ptr(), _ptr(diag),
                              batch, m, n, maxrank, tol, which, _stream()))
+
+
+def solve_batch(instances: list[dict], workers: int = 8) -> list[dict]:
+    """Run independent solve requests concurrently (spd_solve_batch).
+
+    Each instance is a dict with points ((N, 3) FP64 device tensor), kernel,
+    ell, shift, leaf, h2_tol, hss_tol, max_rank, oversample, b ((N, nrhs)
+    column-major, ld = N), rtol, maxit and optionally omega ((N, max_rank +
+    oversample), ld = N), seed, eta, proxy_shells, proxy_per_shell and
+    precision ("f64" or "f32").  Returns per instance: x, iters and relres
+    per column, status and wall times."""
+    n = len(instances)
+    arr = (_Instance * max(n, 1))()
+    res = (_InstanceResult * max(n, 1))()
+    keep = []
+    for i, d in enumerate(instances):
+        P = d["points"].contiguous()
+        b, nc, ld = _as_cols(d["b"], P.shape[0])
+        if ld != P.shape[0]:
+            raise ValueError("b must have ld = N")
+        x = cols_like(P.shape[0], nc, P.device)
+        om = d.get("omega")
+        it = np.zeros(nc, dtype=np.int32)
+        rr = np.zeros(nc, dtype=np.float64)
+        keep.append((P, b, x, om, it, rr))
+        I = arr[i]
+        I.points, I.n = P.data_ptr(), P.shape[0]
+        I.kernel = _Kernel(KERNELS[d["kernel"]], float(d["ell"]), float(d["shift"]))
+        I.h2 = _H2Opts(int(d["leaf"]), float(d.get("eta", 1.0)), float(d["h2_tol"]),
+                       int(d.get("proxy_shells", 8)), int(d.get("proxy_per_shell", 128)))
+        I.hss = _HSSOpts(float(d["hss_tol"]), int(d["max_rank"]), int(d["oversample"]), int(d.get("seed", 0)),
+                         _ptr(om))
+        I.solve_precision = SOLVE_PRECISION[d.get("precision", "f64")]
+        I.b, I.x, I.nrhs = b.data_ptr(), x.data_ptr(), nc
+        I.rtol, I.maxit = float(d["rtol"]), int(d["maxit"])
+        I.iters, I.relres = it.ctypes.data, rr.ctypes.data
+    torch.cuda.synchronize()
+    _check(lib.spd_solve_batch(arr, n, int(workers), res))
+    out = []
+    for i in range(n):
+        P, b, x, om, it, rr = keep[i]
+        r = res[i]
+        out.append({"x": x, "iters": it.copy(), "relres": rr.copy(), "status": STATUS_NAMES.get(r.status, r.status),
+                    "seconds_h2": r.seconds_h2, "seconds_build": r.seconds_build,
+                    "seconds_solve": r.seconds_solve})
+    return out

@@ -97,3 +97,26 @@ LARGE = Workload(name="gaussian-l0.2-N1M-cube", n=1_000_000, point_set="cube",
                  pcg_tol=1e-8, seed_base=3)
 
 BY_NAME = {w.name: w for w in (SMALL, MEDIUM, LARGE)}
+
+
+# Batched case: independent instances of uneven sizes.  N is log-uniform in
+# [5,000, 50,000]; instances alternate between the unit cube and the unit
+# sphere; the kernel is drawn uniformly from Gaussian l = 0.3, exponential
+# l = 0.2 and inverse multiquadric c = 0.1, each + 1e-3 I; leaf 128, HSS
+# tolerance 1e-2, 4 right-hand sides.  Instance j draws its points, right-hand
+# sides and Omega with seeds offset by BATCH_SEED + j.
+BATCH_KERNELS = (("gaussian", 0.3), ("exponential", 0.2), ("imq", 0.1))
+BATCH_SEED = 100 * 1002
+
+
+def batch_instances(count: int = 64, seed: int = 4002, n_lo: int = 5000, n_hi: int = 50000) -> list:
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        kern, ell = BATCH_KERNELS[int(rng.integers(len(BATCH_KERNELS)))]
+        ps = "cube" if j % 2 == 0 else "sphere"
+        out.append(Workload(name=f"batch{j}-{kern}-N{n}-{ps}", n=n, point_set=ps, kernel=kern, ell=ell,
+                            shift=1e-3, leaf=128, h2_tol=1e-8, hss_tol=1e-2, max_rank=100, oversample=10,
+                            nrhs=4, pcg_tol=1e-8, seed_base=BATCH_SEED + j))
+    return out
