@@ -158,7 +158,11 @@ def run_batch(args, torch, P):
             "seconds_build_sum": round(sum(o["seconds_build"] for o in o1), 3),
             "seconds_solve_sum": round(sum(o["seconds_solve"] for o in o1), 3),
             "seconds_longest_instance": round(max(o["seconds_h2"] + o["seconds_build"] + o["seconds_solve"]
-                                                  for o in o1), 3)}
+                                                  for o in o1), 3),
+            "instances": [{"name": w.name, "n": w.n, "iters": int(o["iters"].max()),
+                           "relres": float(f"{float(o['relres'].max()):.3e}"), "status": o["status"],
+                           "seconds": round(o["seconds_h2"] + o["seconds_build"] + o["seconds_solve"], 3)}
+                          for w, o in zip(ws, o1)]}
     print(json.dumps(line), flush=True)
 
 

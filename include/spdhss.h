@@ -199,6 +199,12 @@ typedef struct {
 spd_status spd_solve_batch(const spd_instance* instances, int32_t count, int32_t workers,
                            spd_instance_result* results);
 
+/* Device memory released by destroyed handles is kept in a process-wide cache
+ * and reused by later handles (freeing device memory waits for the whole
+ * device, which would stall concurrent instances).  This frees the cache;
+ * memory held by live handles is not affected. */
+void spd_release_cached_memory(void);
+
 void h2_destroy(spd_h2_t A);
 void spdhss_destroy(spd_hss_t M);
 void ulv_destroy(spd_ulv_t F);

@@ -385,3 +385,5 @@ spd_status spd_test_cpqr(double* A, double* Q, int32_t* piv, int32_t* rank, doub
 }
 
 }  // extern "C"
+
+extern "C" void spd_release_cached_memory(void) { spd::release_cached_chunks(); }

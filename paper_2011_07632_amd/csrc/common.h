@@ -19,6 +19,8 @@ struct Error : std::runtime_error {
 };
 
 void set_last_error(const std::string& msg);
+// frees the cached arena chunks of every device (none of them is in use)
+void release_cached_chunks();
 
 #define SPD_HIP(call)                                                          \
   do {                                                                         \
@@ -225,6 +227,13 @@ void launch_gather_skel(hipStream_t s, const int* cand, const int* piv, int k, i
 // --------------------------------------------------------------- arena --
 // Device memory handed out by bumping through large hipMalloc'd chunks; all of
 // it is released together when the owning handle is destroyed.
+// Device memory in 256 MiB chunks (larger requests get a dedicated
+// allocation).  Released chunks go to a process-wide cache per device and are
+// handed to the next arena instead of being freed: hipFree waits for the whole
+// device, which would stall every other stream (concurrent instances).  An
+// arena is released only after the work that used it has completed (every
+// entry point synchronizes its stream before returning); dedicated allocations
+// are freed.  release_cached_chunks() frees the cache.
 class Arena {
  public:
   ~Arena();
@@ -235,7 +244,7 @@ class Arena {
   size_t bytes_used() const { return used_; }
 
  private:
-  std::vector<void*> chunks_;
+  std::vector<std::pair<void*, size_t>> chunks_;
   char* cur_ = nullptr;
   size_t left_ = 0;
   size_t used_ = 0;

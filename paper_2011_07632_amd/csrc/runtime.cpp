@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <chrono>
 #include <cstring>
 
@@ -21,10 +22,55 @@ double now_seconds() {
 // ---------------------------------------------------------------- arena --
 static constexpr size_t kChunk = size_t(256) << 20;
 
+namespace {
+std::mutex g_chunk_mu;
+std::vector<std::pair<int, void*>> g_chunk_cache;  // (device, chunk)
+
+void* take_chunk() {
+  int dev = 0;
+  SPD_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_chunk_mu);
+    for (size_t i = g_chunk_cache.size(); i-- > 0;)
+      if (g_chunk_cache[i].first == dev) {
+        void* p = g_chunk_cache[i].second;
+        g_chunk_cache.erase(g_chunk_cache.begin() + i);
+        return p;
+      }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, kChunk) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void give_chunk(void* p) {
+  int dev = 0;
+  if (hipPointerAttribute_t a{}; hipPointerGetAttributes(&a, p) == hipSuccess) dev = a.device;
+  else (void)hipGetLastError();
+  std::lock_guard<std::mutex> lk(g_chunk_mu);
+  g_chunk_cache.push_back({dev, p});
+}
+}  // namespace
+
+void release_cached_chunks() {
+  std::vector<std::pair<int, void*>> all;
+  {
+    std::lock_guard<std::mutex> lk(g_chunk_mu);
+    all.swap(g_chunk_cache);
+  }
+  for (auto& c : all) (void)hipFree(c.second);
+}
+
 Arena::~Arena() { release(); }
 
 void Arena::release() {
-  for (void* p : chunks_) (void)hipFree(p);
+  for (auto& c : chunks_) {
+    if (c.second == kChunk) give_chunk(c.first);
+    else (void)hipFree(c.first);
+  }
   chunks_.clear();
   cur_ = nullptr;
   left_ = 0;
@@ -37,12 +83,14 @@ void* Arena::get(size_t bytes) {
   if (bytes > left_) {
     const size_t sz = bytes > kChunk / 4 ? bytes : kChunk;
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sz);
-    if (e != hipSuccess) {
+    if (sz == kChunk) {
+      p = take_chunk();
+    } else if (hipMalloc(&p, sz) != hipSuccess) {
       (void)hipGetLastError();
-      throw Error(SPD_E_NOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
+      p = nullptr;
     }
-    chunks_.push_back(p);
+    if (!p) throw Error(SPD_E_NOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
+    chunks_.push_back({p, sz});
     used_ += sz;
     if (sz != kChunk) return p;  // dedicated allocation; keep the current chunk
     cur_ = static_cast<char*>(p);
