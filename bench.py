@@ -166,6 +166,62 @@ def run_batch(args, torch, P):
     print(json.dumps(line), flush=True)
 
 
+def run_serve(args, torch, P):
+    """Requests of uneven size, kernel and width arrive with Poisson gaps and
+    are submitted to the request loop at their arrival times; latency is
+    completion minus arrival."""
+    from paper_2011_07632_amd.binding import cols_like
+    dev = "cuda"
+    trace = workloads.serve_requests(args.serve)
+    reqs = []
+    for _, w in trace:
+        reqs.append(dict(points=torch.from_numpy(w.points()).to(dev), kernel=w.kernel, ell=w.ell,
+                         shift=w.shift, leaf=w.leaf, h2_tol=w.h2_tol, hss_tol=w.hss_tol, max_rank=w.max_rank,
+                         oversample=w.oversample, b=cols_like(w.n, w.nrhs, dev).copy_(torch.from_numpy(w.rhs())),
+                         rtol=w.pcg_tol, maxit=3000, seed=w.seed_base))
+    torch.cuda.synchronize()
+    S = P.binding.Server(workers=args.workers, hbm_budget_bytes=200 << 30)
+    t0 = time.perf_counter()
+    tickets = []
+    for (arr, w), r in zip(trace, reqs):
+        dt = arr - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(S.submit(r))
+    done = {}
+    while len(done) < len(tickets):
+        for k, t in enumerate(tickets):
+            if k in done:
+                continue
+            r = S.wait(t, block=False)
+            if r is not None:
+                done[k] = r
+                log(f"[bench] served {len(done)}/{len(tickets)}: {trace[k][1].name} {r['status']} "
+                    f"latency {r['seconds_total']:.2f} s")
+        time.sleep(0.05)
+    res = [done[k] for k in range(len(tickets))]
+    span = time.perf_counter() - t0
+    S.close()
+    lat = np.array([r["seconds_total"] for r in res])
+    status = {}
+    for r in res:
+        status[r["status"]] = status.get(r["status"], 0) + 1
+    ok = [r for r in res if r["status"] == "SPD_OK"]
+    line = {"metric": "served p50 latency, s (request loop)", "value": round(float(np.percentile(lat, 50)), 3),
+            "unit": "s", "p99_s": round(float(np.percentile(lat, 99)), 3), "higher_is_better": False,
+            "solves_per_s": round(len(res) / span, 3), "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"serve-{len(res)}-poisson20-N10k-100k", "requests": len(res),
+                       "arrival_rate_per_s": 20.0, "n_range": [10000, 100000], "leaf": 400,
+                       "workers": args.workers, "hbm_budget_bytes": 200 << 30},
+            "seconds_makespan": round(span, 3), "status_counts": status,
+            "queued_p50_s": round(float(np.percentile([r["seconds_queued"] for r in res], 50)), 3),
+            "relres_max_converged": float(max([float(r["relres"].max()) for r in ok], default=0.0)),
+            "requests": [{"name": w.name, "arrival_s": round(a, 3), "latency_s": round(r["seconds_total"], 3),
+                          "queued_s": round(r["seconds_queued"], 3), "iters": int(r["iters"].max()),
+                          "status": r["status"]} for (a, w), r in zip(trace, res)]}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,7 +235,10 @@ def main():
     ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
                     help="batched mode: COUNT independent instances of uneven sizes, run one at a time "
                          "and then concurrently (spd_solve_batch); prints its own JSON line")
-    ap.add_argument("--workers", type=int, default=8, help="worker threads of the batched mode")
+    ap.add_argument("--workers", type=int, default=8, help="worker threads of the batched and served modes")
+    ap.add_argument("--serve", type=int, default=0, metavar="COUNT",
+                    help="served mode: a seeded trace of COUNT requests with Poisson arrivals (20/s) "
+                         "through the request loop; prints p50/p99 latency and solves/s")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection mode: build the H^2 matrix, run a 2 GiB copy (counter "
                          "calibration) and one product, then exit; run under rocprofv3 --pmc")
@@ -195,6 +254,9 @@ def main():
 
     if args.batch:
         run_batch(args, torch, P)
+        return
+    if args.serve:
+        run_serve(args, torch, P)
         return
     w = workloads.BY_NAME[args.workload]
     dev = "cuda"

@@ -44,6 +44,7 @@ extern "C" {
 #endif
 
 typedef enum {
+  SPD_PENDING = 1,          /* spd_server_wait without blocking: not finished yet */
   SPD_OK = 0,
   SPD_E_INVALID = -1,       /* bad argument (null pointer, size, option) */
   SPD_E_NOMEM = -2,         /* device allocation failed */
@@ -198,6 +199,40 @@ typedef struct {
  * instances' device buffers must not overlap where they are written. */
 spd_status spd_solve_batch(const spd_instance* instances, int32_t count, int32_t workers,
                            spd_instance_result* results);
+
+/* ---- serving ------------------------------------------------------------
+ * A request loop over a pool of workers (each with its own stream on the
+ * creating thread's device).  Requests (spd_instance, as for spd_solve_batch)
+ * are admitted first-come-first-served while the sum of the estimated device
+ * footprints of the admitted requests stays within hbm_budget_bytes (a
+ * request larger than the budget is admitted alone); requests that arrive
+ * while others run are admitted as workers and memory free up, and their work
+ * overlaps on the device.  A request's H^2, HSS and factor state stays on the
+ * device from its build to the end of its solve.  Each result equals the same
+ * request run alone.  The caller keeps the request's buffers (points, b, x,
+ * omega, iters, relres) valid until spd_server_wait reports it finished. */
+typedef struct spd_server* spd_server_t;
+
+/* workers >= 1; hbm_budget_bytes > 0. */
+spd_status spd_server_create(int32_t workers, int64_t hbm_budget_bytes, spd_server_t* out);
+
+/* Queue a request; *ticket identifies it for spd_server_wait. */
+spd_status spd_server_submit(spd_server_t S, const spd_instance* request, int64_t* ticket);
+
+/* block != 0: wait until the request has finished.  Returns SPD_PENDING
+ * (block == 0, not finished) or SPD_OK with *result filled and, if not NULL,
+ * the seconds from submission to admission (*seconds_queued) and to
+ * completion (*seconds_total); the ticket is then retired.  Unknown or
+ * retired tickets give SPD_E_INVALID. */
+spd_status spd_server_wait(spd_server_t S, int64_t ticket, int32_t block,
+                           spd_instance_result* result, double* seconds_queued,
+                           double* seconds_total);
+
+/* Estimated device bytes of a request (the admission estimate). */
+int64_t spd_request_footprint(const spd_instance* request);
+
+/* Finishes every submitted request, then stops the workers. */
+void spd_server_destroy(spd_server_t S);
 
 /* Device memory released by destroyed handles is kept in a process-wide cache
  * and reused by later handles (freeing device memory waits for the whole

@@ -21,7 +21,7 @@ LIB_PATH = os.environ.get("SPDHSS_LIB", os.path.join(HERE, "libspdhss.so"))
 KERNELS = {"gaussian": 0, "matern32": 1, "exponential": 2, "imq": 3}
 
 SPD_OK, SPD_E_INVALID, SPD_E_NOMEM, SPD_E_NOT_SPD, SPD_E_NOT_CONVERGED, SPD_E_DEVICE = 0, -1, -2, -3, -4, -5
-STATUS_NAMES = {0: "SPD_OK", -1: "SPD_E_INVALID", -2: "SPD_E_NOMEM", -3: "SPD_E_NOT_SPD",
+STATUS_NAMES = {1: "SPD_PENDING", 0: "SPD_OK", -1: "SPD_E_INVALID", -2: "SPD_E_NOMEM", -3: "SPD_E_NOT_SPD",
                 -4: "SPD_E_NOT_CONVERGED", -5: "SPD_E_DEVICE"}
 
 # query ids (include/spdhss.h)
@@ -85,6 +85,9 @@ def _load():
         "spd_test_trsm": [vp, vp, i32, i32, i32, i32, i32, vp],
         "spd_test_cpqr": [vp, vp, vp, vp, vp, i32, i32, i32, i32, dbl, i32, vp],
         "spd_solve_batch": [C.POINTER(_Instance), i32, i32, C.POINTER(_InstanceResult)],
+        "spd_server_create": [i32, i64, C.POINTER(vp)],
+        "spd_server_submit": [vp, C.POINTER(_Instance), C.POINTER(i64)],
+        "spd_server_wait": [vp, i64, i32, C.POINTER(_InstanceResult), C.POINTER(dbl), C.POINTER(dbl)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -94,6 +97,10 @@ def _load():
         f = getattr(L, name)
         f.argtypes = [vp]
         f.restype = None
+    L.spd_server_destroy.argtypes = [vp]
+    L.spd_server_destroy.restype = None
+    L.spd_request_footprint.argtypes = [C.POINTER(_Instance)]
+    L.spd_request_footprint.restype = C.c_int64
     L.spd_last_error.argtypes = []
     L.spd_last_error.restype = C.c_char_p
     return L
@@ -411,6 +418,79 @@ def test_cpqr(A, Q, piv, rank, diag, maxrank, tol, which):
                              batch, m, n, maxrank, tol, which, _stream()))
 
 
+def _fill_instance(I: _Instance, d: dict):
+    """Fill a request descriptor from a dict; returns the objects it points to."""
+    P = d["points"].contiguous()
+    b, nc, ld = _as_cols(d["b"], P.shape[0])
+    if ld != P.shape[0]:
+        raise ValueError("b must have ld = N")
+    x = cols_like(P.shape[0], nc, P.device)
+    om = d.get("omega")
+    it = np.zeros(nc, dtype=np.int32)
+    rr = np.zeros(nc, dtype=np.float64)
+    I.points, I.n = P.data_ptr(), P.shape[0]
+    I.kernel = _Kernel(KERNELS[d["kernel"]], float(d["ell"]), float(d["shift"]))
+    I.h2 = _H2Opts(int(d["leaf"]), float(d.get("eta", 1.0)), float(d["h2_tol"]),
+                   int(d.get("proxy_shells", 8)), int(d.get("proxy_per_shell", 128)))
+    I.hss = _HSSOpts(float(d["hss_tol"]), int(d["max_rank"]), int(d["oversample"]), int(d.get("seed", 0)),
+                     _ptr(om))
+    I.solve_precision = SOLVE_PRECISION[d.get("precision", "f64")]
+    I.b, I.x, I.nrhs = b.data_ptr(), x.data_ptr(), nc
+    I.rtol, I.maxit = float(d["rtol"]), int(d["maxit"])
+    I.iters, I.relres = it.ctypes.data, rr.ctypes.data
+    return (P, b, x, om, it, rr)
+
+
+class Server:
+    """Request loop (spd_server_*): submit() queues a request dict (as for
+    solve_batch) and returns a ticket; wait(ticket) returns its result with
+    the queueing and total latency in seconds."""
+
+    def __init__(self, workers: int = 8, hbm_budget_bytes: int = 200 << 30):
+        h = C.c_void_p()
+        _check(lib.spd_server_create(int(workers), int(hbm_budget_bytes), C.byref(h)))
+        self._h = h
+        self._pending = {}
+
+    def footprint(self, d: dict) -> int:
+        I = _Instance()
+        keep = _fill_instance(I, d)  # noqa: F841
+        return int(lib.spd_request_footprint(C.byref(I)))
+
+    def submit(self, d: dict) -> int:
+        I = _Instance()
+        keep = _fill_instance(I, d)
+        torch.cuda.current_stream().synchronize()
+        t = C.c_int64()
+        _check(lib.spd_server_submit(self._h, C.byref(I), C.byref(t)))
+        self._pending[t.value] = (I, keep)
+        return t.value
+
+    def wait(self, ticket: int, block: bool = True):
+        r = _InstanceResult()
+        q, tot = C.c_double(), C.c_double()
+        code = lib.spd_server_wait(self._h, int(ticket), 1 if block else 0, C.byref(r), C.byref(q), C.byref(tot))
+        if code == 1:
+            return None
+        _check(code)
+        I, (P, b, x, om, it, rr) = self._pending.pop(ticket)
+        return {"x": x, "iters": it.copy(), "relres": rr.copy(), "status": STATUS_NAMES.get(r.status, r.status),
+                "seconds_queued": q.value, "seconds_total": tot.value, "seconds_h2": r.seconds_h2,
+                "seconds_build": r.seconds_build, "seconds_solve": r.seconds_solve}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            lib.spd_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def solve_batch(instances: list[dict], workers: int = 8) -> list[dict]:
     """Run independent solve requests concurrently (spd_solve_batch).
 
@@ -423,28 +503,7 @@ def solve_batch(instances: list[dict], workers: int = 8) -> list[dict]:
     n = len(instances)
     arr = (_Instance * max(n, 1))()
     res = (_InstanceResult * max(n, 1))()
-    keep = []
-    for i, d in enumerate(instances):
-        P = d["points"].contiguous()
-        b, nc, ld = _as_cols(d["b"], P.shape[0])
-        if ld != P.shape[0]:
-            raise ValueError("b must have ld = N")
-        x = cols_like(P.shape[0], nc, P.device)
-        om = d.get("omega")
-        it = np.zeros(nc, dtype=np.int32)
-        rr = np.zeros(nc, dtype=np.float64)
-        keep.append((P, b, x, om, it, rr))
-        I = arr[i]
-        I.points, I.n = P.data_ptr(), P.shape[0]
-        I.kernel = _Kernel(KERNELS[d["kernel"]], float(d["ell"]), float(d["shift"]))
-        I.h2 = _H2Opts(int(d["leaf"]), float(d.get("eta", 1.0)), float(d["h2_tol"]),
-                       int(d.get("proxy_shells", 8)), int(d.get("proxy_per_shell", 128)))
-        I.hss = _HSSOpts(float(d["hss_tol"]), int(d["max_rank"]), int(d["oversample"]), int(d.get("seed", 0)),
-                         _ptr(om))
-        I.solve_precision = SOLVE_PRECISION[d.get("precision", "f64")]
-        I.b, I.x, I.nrhs = b.data_ptr(), x.data_ptr(), nc
-        I.rtol, I.maxit = float(d["rtol"]), int(d["maxit"])
-        I.iters, I.relres = it.ctypes.data, rr.ctypes.data
+    keep = [_fill_instance(arr[i], d) for i, d in enumerate(instances)]
     torch.cuda.synchronize()
     _check(lib.spd_solve_batch(arr, n, int(workers), res))
     out = []

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libspdhss.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["kernels.hip", "runtime.cpp", "tree.cpp", "h2.cpp", "hss.cpp", "solve.cpp", "api.cpp",
-           "batch.cpp"]
+           "batch.cpp", "serve.cpp"]
 ARCH = os.environ.get("SPDHSS_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

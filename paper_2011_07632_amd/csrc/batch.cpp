@@ -20,6 +20,9 @@ double seconds_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+}  // namespace
+
+namespace spd {
 void run_instance(const spd_instance& I, hipStream_t s, spd_instance_result& R) {
   R = spd_instance_result{};
   auto t0 = std::chrono::steady_clock::now();
@@ -54,8 +57,7 @@ void run_instance(const spd_instance& I, hipStream_t s, spd_instance_result& R) 
   if (M) spdhss_destroy(M);
   if (A) h2_destroy(A);
 }
-
-}  // namespace
+}  // namespace spd
 
 extern "C" spd_status spd_solve_batch(const spd_instance* instances, int32_t count, int32_t workers,
                                       spd_instance_result* results) {
@@ -81,7 +83,7 @@ extern "C" spd_status spd_solve_batch(const spd_instance* instances, int32_t cou
       setup_fail = 1;
       return;
     }
-    for (int i = next++; i < count; i = next++) run_instance(instances[i], s, results[i]);
+    for (int i = next++; i < count; i = next++) spd::run_instance(instances[i], s, results[i]);
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
   };
@@ -96,7 +98,7 @@ extern "C" spd_status spd_solve_batch(const spd_instance* instances, int32_t cou
       spd::set_last_error("stream creation failed");
       return SPD_E_DEVICE;
     }
-    for (int i = next++; i < count; i = next++) run_instance(instances[i], s, results[i]);
+    for (int i = next++; i < count; i = next++) spd::run_instance(instances[i], s, results[i]);
     (void)hipStreamDestroy(s);
   }
   return SPD_OK;

@@ -1,0 +1,76 @@
+"""Request loop (GPU): requests submitted while others run are admitted and
+overlap; each result equals the same request run alone; the HBM budget
+serializes admission; non-blocking waits report pending requests."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2011_07632_amd import binding
+    return binding
+
+
+def request(B, w, precision="f64"):
+    dev = "cuda"
+    return dict(points=torch.from_numpy(w.points()).to(dev), kernel=w.kernel, ell=w.ell, shift=w.shift,
+                leaf=w.leaf, h2_tol=w.h2_tol, hss_tol=w.hss_tol, max_rank=w.max_rank, oversample=w.oversample,
+                omega=B.cols_like(w.n, w.s, dev).copy_(torch.from_numpy(w.omega())),
+                b=B.cols_like(w.n, w.nrhs, dev).copy_(torch.from_numpy(w.rhs())),
+                rtol=w.pcg_tol, maxit=3000, precision=precision)
+
+
+def alone(B, r):
+    out = B.solve_batch([r], workers=1)[0]
+    return out["x"].cpu().numpy(), out["iters"]
+
+
+def test_results_in_the_mix_equal_alone(B):
+    ws = workloads.batch_instances(count=5, seed=77, n_lo=1500, n_hi=5000)
+    reqs = [request(B, w, "f32" if j == 2 else "f64") for j, w in enumerate(ws)]
+    ref = [alone(B, r) for r in reqs]
+    S = B.Server(workers=3)
+    tickets = []
+    for r in reqs:
+        tickets.append(S.submit(r))
+        time.sleep(0.02)
+    got = [S.wait(t) for t in tickets]
+    S.close()
+    for w, (x, it), g in zip(ws, ref, got):
+        print(f"[serve] {w.name}: queued {g['seconds_queued']:.3f} s total {g['seconds_total']:.3f} s "
+              f"iterations {g['iters'].tolist()} {g['status']}", flush=True)
+        assert g["status"] in ("SPD_OK", "SPD_E_NOT_CONVERGED")
+        assert g["iters"].tolist() == it.tolist(), w.name
+        assert np.array_equal(g["x"].cpu().numpy(), x), w.name
+
+
+def test_budget_serializes_admission(B):
+    ws = workloads.batch_instances(count=3, seed=78, n_lo=1500, n_hi=3000)
+    reqs = [request(B, w) for w in ws]
+    S = B.Server(workers=3, hbm_budget_bytes=1)
+    assert all(S.footprint(r) > 1 for r in reqs)
+    tickets = [S.submit(r) for r in reqs]
+    pending = S.wait(tickets[-1], block=False)
+    got = [S.wait(t) for t in tickets]
+    S.close()
+    assert pending is None or pending["status"] in ("SPD_OK", "SPD_E_NOT_CONVERGED")
+    # with a budget below every footprint the requests run one at a time, in order
+    assert got[1]["seconds_queued"] >= got[0]["seconds_total"] - got[0]["seconds_queued"] - 0.05
+    assert got[2]["seconds_queued"] > got[1]["seconds_queued"]
+
+
+def test_footprint_grows_with_n(B):
+    S = B.Server(workers=1)
+    small, big = workloads.batch_instances(count=2, seed=79, n_lo=2000, n_hi=2001)[0], None
+    big = small.with_(n=8000)
+    assert S.footprint(request(B, big)) > S.footprint(request(B, small))
+    S.close()

@@ -120,3 +120,31 @@ def batch_instances(count: int = 64, seed: int = 4002, n_lo: int = 5000, n_hi: i
                             shift=1e-3, leaf=128, h2_tol=1e-8, hss_tol=1e-2, max_rank=100, oversample=10,
                             nrhs=4, pcg_tol=1e-8, seed_base=BATCH_SEED + j))
     return out
+
+
+# Served case: a seeded trace of solve requests with Poisson arrivals (rate
+# per second), N log-uniform in [n_lo, n_hi], cube points, a kernel drawn from
+# Gaussian / Matern-3/2 / exponential with l uniform in [0.05, 0.5], + 1e-3 I,
+# leaf 400, 1 to 32 right-hand sides.  Request j draws its data with seeds
+# offset by SERVE_SEED + j.
+SERVE_KERNELS = ("gaussian", "matern32", "exponential")
+SERVE_SEED = 100 * 1004
+
+
+def serve_requests(count: int = 64, rate: float = 20.0, seed: int = 4004, n_lo: int = 10_000,
+                   n_hi: int = 100_000) -> list:
+    """[(arrival seconds, Workload)] sorted by arrival."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for j in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        kern = SERVE_KERNELS[int(rng.integers(len(SERVE_KERNELS)))]
+        ell = float(rng.uniform(0.05, 0.5))
+        nrhs = int(rng.integers(1, 33))
+        out.append((t, Workload(name=f"req{j}-{kern}-l{ell:.3f}-N{n}-r{nrhs}", n=n, point_set="cube",
+                                kernel=kern, ell=ell, shift=1e-3, leaf=400, h2_tol=1e-8, hss_tol=1e-2,
+                                max_rank=100, oversample=10, nrhs=nrhs, pcg_tol=1e-8,
+                                seed_base=SERVE_SEED + j)))
+    return out
