@@ -351,3 +351,23 @@ def test_matvec_error_on_order_of_tau():
         errs[tau] = matvec_error(h.matvec, lambda X: A @ X, 1000)
     assert 1e-3 < errs[1e-1] < 0.3
     assert 1e-5 < errs[1e-2] < errs[1e-1]
+
+
+def test_golden_fixture():
+    """The oracle reproduces its recorded results (tests/golden/oracle_n300.json,
+    written by tests/golden/make_golden.py): integers exactly, norms to 1e-12.
+    A change here means the oracle's arithmetic changed."""
+    import importlib.util
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(here, "make_golden.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(os.path.join(here, "oracle_n300.json")) as f:
+        want = json.load(f)
+    got = json.loads(json.dumps(mod.compute()))
+    for key in ("perm", "h2_skeletons", "hss_ranks", "hss_pivots", "pcg_iterations"):
+        assert got[key] == want[key], key
+    for key in ("matvec_ones_norm", "solution_norm"):
+        assert abs(got[key] - want[key]) <= 1e-12 * abs(want[key]), key
