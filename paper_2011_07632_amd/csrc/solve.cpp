@@ -404,38 +404,70 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   }
   int h_any = 1;
   int done = 0;
-  while (done < maxit) {
-    SPD_HIP(hipMemcpyAsync(&h_any, any, sizeof(int), hipMemcpyDeviceToHost, s));
-    SPD_HIP(hipStreamSynchronize(s));
-    if (!h_any) break;
-    const int chunk = std::min(kCheckEvery, maxit - done);
-    for (int c = 0; c < chunk; ++c) {
-      if (use_graph) SPD_HIP(hipGraphLaunch(exec, s));
-      else body();
+  auto iterate = [&]() {
+    while (done < maxit) {
+      SPD_HIP(hipMemcpyAsync(&h_any, any, sizeof(int), hipMemcpyDeviceToHost, s));
+      SPD_HIP(hipStreamSynchronize(s));
+      if (!h_any) break;
+      const int chunk = std::min(kCheckEvery, maxit - done);
+      for (int c = 0; c < chunk; ++c) {
+        if (use_graph) SPD_HIP(hipGraphLaunch(exec, s));
+        else body();
+      }
+      done += chunk;
     }
-    done += chunk;
+  };
+  // r = b - A x (true residual) and its relative norms per column
+  std::vector<double> hrr(m), hbb(m), rel(m);
+  auto true_residual = [&]() {
+    SPD_HIP(hipMemcpyAsync(p, xt, bytes, hipMemcpyDeviceToDevice, s));
+    h2_plan_run(H);
+    SPD_HIP(hipMemcpyAsync(r, bt, bytes, hipMemcpyDeviceToDevice, s));
+    launch_axpby(s, r, q, -1.0, 1.0, N, m, N);
+    launch_coldot(s, r, r, N, m, N, partial, rr);
+    SPD_HIP(hipMemcpyAsync(hrr.data(), rr, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    SPD_HIP(hipMemcpyAsync(hbb.data(), bb, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    SPD_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < m; ++c) rel[c] = hbb[c] > 0 ? std::sqrt(hrr[c] / hbb[c]) : std::sqrt(hrr[c]);
+  };
+  iterate();
+  true_residual();
+  // Residual replacement (beyond the paper): a column whose recursively updated
+  // residual met rtol while its true residual is above kRestartFactor * rtol
+  // (the two drift apart on ill-conditioned systems) restarts from the true
+  // residual, within maxit and at most kMaxRestarts times.
+  constexpr double kRestartFactor = 10.0;
+  constexpr int kMaxRestarts = 4;
+  for (int restart = 0; restart < kMaxRestarts && done < maxit; ++restart) {
+    std::vector<int> act(m + 1, 0);
+    SPD_HIP(hipMemcpyAsync(act.data(), active, (m + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+    SPD_HIP(hipStreamSynchronize(s));
+    bool again = false;
+    for (int c = 0; c < m; ++c) {
+      act[c] = (!act[c] && rel[c] > kRestartFactor * rtol) ? 1 : act[c];
+      again |= act[c] != 0;
+    }
+    if (!again) break;
+    act[m] = 1;  // any
+    SPD_HIP(hipMemcpyAsync(active, act.data(), (m + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    // r holds the true residual: z = M r, p = z, then the iteration continues
+    precond(r, z);
+    SPD_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, s));
+    launch_coldot_partial(s, r, z, N, m, N, rzp);
+    SPD_HIP(hipStreamSynchronize(s));
+    iterate();
+    true_residual();
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   PcgResult res;
   std::vector<int> act(2 * m + 1);
   SPD_HIP(hipMemcpyAsync(act.data(), active, act.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-  // true residual
-  SPD_HIP(hipMemcpyAsync(p, xt, bytes, hipMemcpyDeviceToDevice, s));
-  h2_plan_run(H);
-  SPD_HIP(hipMemcpyAsync(r, bt, bytes, hipMemcpyDeviceToDevice, s));
-  launch_axpby(s, r, q, -1.0, 1.0, N, m, N);
-  launch_coldot(s, r, r, N, m, N, partial, rr);
-  std::vector<double> hrr(m), hbb(m);
-  SPD_HIP(hipMemcpyAsync(hrr.data(), rr, m * sizeof(double), hipMemcpyDeviceToHost, s));
-  SPD_HIP(hipMemcpyAsync(hbb.data(), bb, m * sizeof(double), hipMemcpyDeviceToHost, s));
   SPD_HIP(hipStreamSynchronize(s));
   res.iters.assign(act.begin() + m + 1, act.end());
-  res.relres.resize(m);
-  for (int c = 0; c < m; ++c) {
-    res.relres[c] = hbb[c] > 0 ? std::sqrt(hrr[c] / hbb[c]) : std::sqrt(hrr[c]);
-    if (act[c]) res.converged = false;
-  }
+  res.relres = rel;
+  for (int c = 0; c < m; ++c)
+    if (act[c] || rel[c] > kRestartFactor * rtol) res.converged = false;
   return res;
 }
 
