@@ -506,16 +506,21 @@ static void launch_skinny(hipStream_t s, const GemmProblem* d_p, const GemmTerm*
 template <int NC, int RG, int NW>
 __global__ __launch_bounds__(64 * NW) void k_symv(const SymProblem* __restrict__ probs,
                                                    const SymTerm* __restrict__ terms, int tiles_max,
-                                                   int nwork) {
+                                                   int nwork, int nprob) {
   constexpr int U = (RG == 1) ? 8 : 4;
   constexpr int V = U * NC;
   constexpr int TR = 64 * RG;
   __shared__ double red[NW / 2][TR][NC];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // a capped grid walks the (problem, row tile) items with a stride
+  // a capped grid walks the (problem, row tile) items with a stride.  XCD-aware
+  // decode: items are dealt to the 8 XCDs round-robin (item & 7), and the row
+  // tiles of one problem take consecutive slots of the same XCD, so the cache
+  // line they share at their boundary is fetched once into that XCD's L2.
   for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
-  const int p = item / tiles_max, tile = item % tiles_max;
+  const int x8 = item & 7, rest = item >> 3;
+  const int tile = rest % tiles_max, p = (rest / tiles_max) * 8 + x8;
+  if (p >= nprob) continue;
   const SymProblem P = probs[p];
   const int i0 = tile * TR;
   if (i0 >= P.m || P.n <= 0) continue;
@@ -634,14 +639,15 @@ template <int NC, int NW>
 static void launch_symv_nw(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
                            int max_m, int cap) {
   const int tiles = max_m <= 128 ? 1 : ceil_div(max_m, 256);
-  const int nwork = nprob * tiles;
-  const dim3 grid((unsigned)(cap > 0 ? std::min(cap, nwork) : nwork));
+  const int nwork = ceil_div(nprob, 8) * 8 * tiles;  // problems padded to a multiple of 8 (XCDs)
+  const int capped = cap > 0 ? std::max(8, cap / 8 * 8) : nwork;  // keep item & 7 == block & 7
+  const dim3 grid((unsigned)std::min(capped, nwork));
   if (max_m <= 64)
-    hipLaunchKernelGGL((k_symv<NC, 1, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, 1, nwork);
+    hipLaunchKernelGGL((k_symv<NC, 1, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, 1, nwork, nprob);
   else if (max_m <= 128)
-    hipLaunchKernelGGL((k_symv<NC, 2, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, 1, nwork);
+    hipLaunchKernelGGL((k_symv<NC, 2, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, 1, nwork, nprob);
   else
-    hipLaunchKernelGGL((k_symv<NC, 4, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, tiles, nwork);
+    hipLaunchKernelGGL((k_symv<NC, 4, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, tiles, nwork, nprob);
 }
 
 // 16-wave workgroups for small launches with one right-hand column only (more
