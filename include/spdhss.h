@@ -69,7 +69,9 @@ typedef enum {
 typedef struct {
   int32_t kind;   /* spd_kernel_kind */
   double ell;     /* length scale (> 0) */
-  double shift;   /* diagonal shift sigma (>= 0) */
+  double shift;   /* diagonal shift sigma (finite; the paper's are >= 0.  A
+                   * negative one can make the leaf blocks indefinite, which
+                   * spdhss_build reports as SPD_E_NOT_SPD) */
 } spd_kernel;
 
 /* H^2 construction options (Section 5.1; construction method: proxy-point

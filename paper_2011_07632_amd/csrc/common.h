@@ -190,7 +190,6 @@ void launch_gaussian_fill(hipStream_t s, double* dst, int64_t n, int ncols,
                           int64_t ldd, const int64_t* perm, uint64_t seed);
 void launch_soa_points(hipStream_t s, const double* pts_rowmajor,
                        const int64_t* perm, int64_t n, double* soa);
-// column dot products: out[c] = sum_i x[i,c] * y[i,c] (deterministic, two-stage)
 // Fused PCG step kernels over per-chunk partial dot products (coldot_chunks(n)
 // chunks per column): partials of x.y; x, r update with the partials of the
 // new r.r; the active test; the p update.
@@ -206,15 +205,9 @@ void launch_pcg_active_partial(hipStream_t s, const double* rrp, int64_t n, cons
 void launch_pcg_update_p_partial(hipStream_t s, double* p, const double* z, const double* rzp,
                                  const double* rzv, const int* active, int64_t n, int ncols,
                                  int64_t ld, const double* rzop = nullptr);
+// column dot products: out[c] = sum_i x[i,c] * y[i,c] (deterministic, two-stage)
 void launch_coldot(hipStream_t s, const double* x, const double* y, int64_t n,
                    int ncols, int64_t ld, double* partial, double* out);
-void launch_pcg_update_xr(hipStream_t s, double* x, double* r, const double* p,
-                          const double* q, const double* rz, const double* pq,
-                          const int* active, int64_t n, int ncols, int64_t ld,
-                          int* iters);
-void launch_pcg_update_p(hipStream_t s, double* p, const double* z,
-                         const double* rz_new, double* rz, const int* active,
-                         int64_t n, int ncols, int64_t ld);
 void launch_pcg_active(hipStream_t s, const double* rr, const double* bb,
                        double rtol, int* active, int ncols, int* any_active);
 void launch_axpby(hipStream_t s, double* y, const double* x, double a, double b,

@@ -1616,52 +1616,6 @@ void launch_pcg_update_p_partial(hipStream_t s, double* p, const double* z, cons
   SPD_HIP(hipGetLastError());
 }
 
-__global__ void k_pcg_update_xr(double* __restrict__ x, double* __restrict__ r,
-                                const double* __restrict__ p, const double* __restrict__ q,
-                                const double* __restrict__ rz, const double* __restrict__ pq,
-                                const int* __restrict__ active, int64_t n, int64_t ld,
-                                int* __restrict__ iters) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (!active[c]) return;
-  const double alpha = rz[c] / pq[c];
-  if (i == 0 && iters) iters[c] += 1;
-  if (i < n) {
-    x[i + c * ld] += alpha * p[i + c * ld];
-    r[i + c * ld] -= alpha * q[i + c * ld];
-  }
-}
-void launch_pcg_update_xr(hipStream_t s, double* x, double* r, const double* p, const double* q,
-                          const double* rz, const double* pq, const int* active, int64_t n,
-                          int ncols, int64_t ld, int* iters) {
-  hipLaunchKernelGGL(k_pcg_update_xr, dim3(ceil_div(n, 256), ncols), dim3(256), 0, s, x, r, p, q,
-                     rz, pq, active, n, ld, iters);
-  SPD_HIP(hipGetLastError());
-}
-
-__global__ void k_pcg_update_p(double* __restrict__ p, const double* __restrict__ z,
-                               const double* __restrict__ rz_new, const double* __restrict__ rz,
-                               const int* __restrict__ active, int64_t n, int64_t ld) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (!active[c] || i >= n) return;
-  const double beta = rz_new[c] / rz[c];
-  p[i + c * ld] = z[i + c * ld] + beta * p[i + c * ld];
-}
-__global__ void k_copy_active(double* __restrict__ dst, const double* __restrict__ src,
-                              const int* __restrict__ active, int ncols) {
-  const int c = threadIdx.x;
-  if (c < ncols && active[c]) dst[c] = src[c];
-}
-void launch_pcg_update_p(hipStream_t s, double* p, const double* z, const double* rz_new, double* rz,
-                         const int* active, int64_t n, int ncols, int64_t ld) {
-  hipLaunchKernelGGL(k_pcg_update_p, dim3(ceil_div(n, 256), ncols), dim3(256), 0, s, p, z, rz_new,
-                     rz, active, n, ld);
-  hipLaunchKernelGGL(k_copy_active, dim3(1), dim3(64 * ceil_div(ncols, 64)), 0, s, rz, rz_new,
-                     active, ncols);
-  SPD_HIP(hipGetLastError());
-}
-
 __global__ void k_pcg_active(const double* __restrict__ rr, const double* __restrict__ bb,
                              double rtol, int* __restrict__ active, int ncols, int* any_active) {
   __shared__ int any;

@@ -1,7 +1,8 @@
 """Degenerate and edge cases of the HIP path against the oracle and closed
 forms (GPU): a single leaf (the HSS matrix is the dense block), the
 block-Jacobi limit r_max = 0, more than 4 right-hand sides (the MFMA product
-and apply), and argument errors reported through the C ABI."""
+and apply), a negative shift (indefinite leaf blocks), and argument errors
+reported through the C ABI."""
 import numpy as np
 import pytest
 
@@ -91,6 +92,25 @@ def test_more_than_four_columns(B):
     xo[perm] = xo_t
     assert it.tolist() == ito.tolist()
     assert rel(x.cpu().numpy(), xo) <= 1e-10
+
+
+def test_negative_shift_reports_not_spd(B):
+    """sigma = -0.05 makes every leaf block K_ii + sigma I of the Gaussian
+    kernel indefinite (its smallest eigenvalue is about -0.05): the build stops
+    at a leaf Cholesky with SPD_E_NOT_SPD and names the node.  The H^2
+    product itself is defined for any shift and matches the oracle's."""
+    w = workloads.SMALL.with_(name="gaussian-l0.5-N1200-indefinite", n=1200, shift=-0.05)
+    X = w.points()
+    h2 = B.h2_build(torch.from_numpy(X).cuda(), w.kernel, w.ell, w.shift, leaf=w.leaf, tol=w.h2_tol)
+    o_h2 = OH2(X, w.kernel, w.ell, w.shift, w.leaf, w.h2_tol, eta=w.eta)
+    perm = o_h2.tree.perm
+    x = workloads.gaussian_matrix(w.n, 2, 31)
+    yo = np.empty_like(x)
+    yo[perm] = o_h2.matvec(x[perm])
+    assert rel(B.h2_matvec(h2, cols(B, x)).cpu().numpy(), yo) <= 1e-10
+    with pytest.raises(B.SpdError) as e:
+        B.spdhss_build(h2, w.hss_tol, w.max_rank, w.oversample, omega=cols(B, w.omega()))
+    assert e.value.code == B.SPD_E_NOT_SPD and "node" in str(e.value)
 
 
 def test_argument_errors(B):
