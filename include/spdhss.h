@@ -149,6 +149,17 @@ spd_status ulv_apply(spd_ulv_t F, const double* b, double* x, int32_t nrhs,
 spd_status h2_matvec(spd_h2_t A, const double* x, double* y, int32_t nrhs,
                      int64_t ld, void* stream);
 
+/* h2_matvec with a choice of precision for the stored blocks.  SPD_SOLVE_F32
+ * (at most 4 columns) streams FP32 copies of the near-field and coupling
+ * blocks (made on first use and kept with the handle, about half the bytes of
+ * the FP64 blocks the product reads) and accumulates in FP64; the
+ * interpolation, vectors and sums stay FP64.  This is a different operator
+ * from the FP64 one: each block entry is rounded to FP32 (relative 6e-8).
+ * Argument errors as for h2_matvec; an unknown precision, or SPD_SOLVE_F32
+ * with more than 4 columns, gives SPD_E_INVALID. */
+spd_status h2_matvec_ex(spd_h2_t A, const double* x, double* y, int32_t nrhs,
+                        int64_t ld, int32_t precision, void* stream);
+
 /* Solve A x = b column by column with PCG preconditioned by M (M = NULL: plain
  * CG), x0 = 0, stopping column c when ||r_c|| <= rtol * ||b_c||.
  * b, x: DEVICE N x nrhs (ld >= N, original order).
@@ -163,6 +174,26 @@ spd_status h2_matvec(spd_h2_t A, const double* x, double* y, int32_t nrhs,
 spd_status pcg_solve(spd_h2_t A, spd_ulv_t M, const double* b, double* x,
                      int32_t nrhs, int64_t ld, double rtol, int32_t maxit,
                      void* stream, int32_t* iters, double* relres);
+
+/* pcg_solve with a choice of precision for the product inside the iteration
+ * (mixed-precision PCG, beyond the paper).  With SPD_SOLVE_F32 (at most 4
+ * columns) every iteration applies the FP32-block product of h2_matvec_ex,
+ * and the residual is kept honest with the FP64 product: whenever an active
+ * column's recursively updated residual has halved since the last
+ * replacement (checked every 8 iterations), r = b - A x is recomputed with the
+ * FP64 product for every column (reliable updates), without restarting the
+ * recurrence.  It pays when the FP32 rounding of the blocks is small against
+ * the smallest eigenvalues (roughly cond(A) * 6e-8 << 1); otherwise the
+ * iteration count grows.  The
+ * stopping test, the reported true residuals and the final restarts use the
+ * FP64 product, so the result meets rtol against the FP64 operator.
+ * op_precision SPD_SOLVE_F64 is pcg_solve.  Errors as for pcg_solve; an
+ * unknown precision, or SPD_SOLVE_F32 with more than 4 columns, gives
+ * SPD_E_INVALID. */
+spd_status pcg_solve_ex(spd_h2_t A, spd_ulv_t M, const double* b, double* x,
+                        int32_t nrhs, int64_t ld, double rtol, int32_t maxit,
+                        int32_t op_precision, void* stream, int32_t* iters,
+                        double* relres);
 
 /* ---- many independent instances ---------------------------------------
  * One solve request: points, kernel and options as for h2_build and

@@ -75,7 +75,9 @@ def _load():
         "ulv_factor_ex": [vp, C.c_int32, vp, C.POINTER(vp)],
         "ulv_apply": [vp, vp, vp, i32, i64, vp],
         "h2_matvec": [vp, vp, vp, i32, i64, vp],
+        "h2_matvec_ex": [vp, vp, vp, i32, i64, i32, vp],
         "pcg_solve": [vp, vp, vp, vp, i32, i64, dbl, i32, vp, vp, vp],
+        "pcg_solve_ex": [vp, vp, vp, vp, i32, i64, dbl, i32, i32, vp, vp, vp],
         "spd_h2_query_get": [vp, i32, vp, i64],
         "spd_hss_query_get": [vp, i32, i32, i32, vp, i64],
         "spd_h2_time_near": [vp, i32, i32, vp, vp, vp],
@@ -336,28 +338,36 @@ def ulv_apply(F: ULVFactor, b: torch.Tensor, out: torch.Tensor | None = None, st
     return out
 
 
-def h2_matvec(A: H2Matrix, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+def h2_matvec(A: H2Matrix, x: torch.Tensor, out: torch.Tensor | None = None, stream=None,
+              precision: str = "f64") -> torch.Tensor:
+    """y = A x; precision "f32" streams FP32 copies of the near and coupling
+    blocks (at most 4 columns, FP64 accumulation)."""
     x, nc, ld = _as_cols(x, A.n)
     if out is None:
         out = cols_like(A.n, nc, x.device) if x.dim() == 2 else torch.empty_like(x)
     out_, nc2, ld2 = _as_cols(out, A.n)
     if nc2 != nc or ld2 != ld:
         raise ValueError("output shape / leading dimension must match the input")
-    _check(lib.h2_matvec(A._h, x.data_ptr(), out.data_ptr(), nc, ld, _stream(stream)))
+    _check(lib.h2_matvec_ex(A._h, x.data_ptr(), out.data_ptr(), nc, ld, SOLVE_PRECISION[precision],
+                            _stream(stream)))
     return out
 
 
 def pcg_solve(A: H2Matrix, M: ULVFactor | None, b: torch.Tensor, rtol: float = 1e-8, maxit: int = 1000,
-              out: torch.Tensor | None = None, stream=None, raise_on_nonconvergence: bool = True):
-    """Returns (x, iterations per column, true relative residual per column)."""
+              out: torch.Tensor | None = None, stream=None, raise_on_nonconvergence: bool = True,
+              op_precision: str = "f64"):
+    """Returns (x, iterations per column, true relative residual per column).
+    op_precision "f32": the iterations use the FP32-block product, with
+    residual replacement by the FP64 product (at most 4 columns)."""
     b, nc, ld = _as_cols(b, A.n)
     if out is None:
         out = cols_like(A.n, nc, b.device) if b.dim() == 2 else torch.empty_like(b)
     _as_cols(out, A.n)
     iters = np.zeros(nc, dtype=np.int32)
     relres = np.zeros(nc, dtype=np.float64)
-    code = lib.pcg_solve(A._h, None if M is None else M._h, b.data_ptr(), out.data_ptr(), nc, ld,
-                         float(rtol), int(maxit), _stream(stream), iters.ctypes.data, relres.ctypes.data)
+    code = lib.pcg_solve_ex(A._h, None if M is None else M._h, b.data_ptr(), out.data_ptr(), nc, ld,
+                            float(rtol), int(maxit), SOLVE_PRECISION[op_precision], _stream(stream),
+                            iters.ctypes.data, relres.ctypes.data)
     if code == SPD_E_NOT_CONVERGED and not raise_on_nonconvergence:
         return out, iters, relres
     _check(code)

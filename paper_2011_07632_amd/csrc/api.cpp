@@ -128,31 +128,51 @@ spd_status ulv_apply(spd_ulv_t F, const double* b, double* x, int32_t nrhs, int6
   SPD_API_END
 }
 
-spd_status h2_matvec(spd_h2_t A, const double* x, double* y, int32_t nrhs, int64_t ld,
-                     void* stream) {
+spd_status h2_matvec_ex(spd_h2_t A, const double* x, double* y, int32_t nrhs, int64_t ld,
+                        int32_t precision, void* stream) {
   SPD_API_BEGIN
   SPD_REQUIRE(A && x && y, SPD_E_INVALID, "null argument");
   const int64_t N = A->m.T.N;
   SPD_REQUIRE(nrhs >= 1 && ld >= N, SPD_E_INVALID, "bad nrhs or ld");
   SPD_REQUIRE(x != y, SPD_E_INVALID, "x and y must not alias");
+  SPD_REQUIRE(precision == SPD_SOLVE_F64 || precision == SPD_SOLVE_F32, SPD_E_INVALID,
+              "unknown precision");
+  SPD_REQUIRE(precision == SPD_SOLVE_F64 || nrhs <= 4, SPD_E_INVALID,
+              "the FP32 product takes at most 4 columns");
   hipStream_t s = as_stream(stream);
   A->m.s = s;
   double* xt = h2_plan_x(A->m, nrhs);
   double* yt = h2_plan_y(A->m, nrhs);
   launch_gather_rows(s, x, ld, xt, N, A->m.perm_d, N, nrhs);
-  h2_plan_run(A->m);
+  if (precision == SPD_SOLVE_F32) h2_plan_run32(A->m, nrhs);
+  else h2_plan_run(A->m);
   launch_scatter_rows(s, yt, N, y, ld, A->m.perm_d, N, nrhs);
   SPD_HIP(hipStreamSynchronize(s));
   SPD_API_END
 }
 
+spd_status h2_matvec(spd_h2_t A, const double* x, double* y, int32_t nrhs, int64_t ld,
+                     void* stream) {
+  return h2_matvec_ex(A, x, y, nrhs, ld, SPD_SOLVE_F64, stream);
+}
+
 spd_status pcg_solve(spd_h2_t A, spd_ulv_t M, const double* b, double* x, int32_t nrhs, int64_t ld,
                      double rtol, int32_t maxit, void* stream, int32_t* iters, double* relres) {
+  return pcg_solve_ex(A, M, b, x, nrhs, ld, rtol, maxit, SPD_SOLVE_F64, stream, iters, relres);
+}
+
+spd_status pcg_solve_ex(spd_h2_t A, spd_ulv_t M, const double* b, double* x, int32_t nrhs,
+                        int64_t ld, double rtol, int32_t maxit, int32_t op_precision, void* stream,
+                        int32_t* iters, double* relres) {
   SPD_API_BEGIN
   SPD_REQUIRE(A && b && x, SPD_E_INVALID, "null argument");
   const int64_t N = A->m.T.N;
   SPD_REQUIRE(nrhs >= 1 && nrhs <= 4096 && ld >= N, SPD_E_INVALID, "bad nrhs or ld");
   SPD_REQUIRE(rtol >= 0 && maxit >= 0, SPD_E_INVALID, "bad rtol or maxit");
+  SPD_REQUIRE(op_precision == SPD_SOLVE_F64 || op_precision == SPD_SOLVE_F32, SPD_E_INVALID,
+              "unknown precision");
+  SPD_REQUIRE(op_precision == SPD_SOLVE_F64 || nrhs <= 4, SPD_E_INVALID,
+              "the FP32 product takes at most 4 columns");
   if (M) SPD_REQUIRE(M->m.f->T.N == N, SPD_E_INVALID, "preconditioner size mismatch");
   hipStream_t s = as_stream(stream);
   A->m.s = s;
@@ -161,7 +181,8 @@ spd_status pcg_solve(spd_h2_t A, spd_ulv_t M, const double* b, double* x, int32_
   double* bt = a.get_n<double>((size_t)N * nrhs);
   double* xt = a.get_n<double>((size_t)N * nrhs);
   launch_gather_rows(s, b, ld, bt, N, A->m.perm_d, N, nrhs);
-  PcgResult r = pcg_tree(A->m, M ? &M->m : nullptr, bt, xt, nrhs, rtol, maxit);
+  PcgResult r = pcg_tree(A->m, M ? &M->m : nullptr, bt, xt, nrhs, rtol, maxit,
+                         op_precision == SPD_SOLVE_F32);
   launch_scatter_rows(s, xt, N, x, ld, A->m.perm_d, N, nrhs);
   SPD_HIP(hipStreamSynchronize(s));
   for (int c = 0; c < nrhs; ++c) {

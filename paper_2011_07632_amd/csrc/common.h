@@ -79,7 +79,7 @@ struct SymProblem {
   double alpha, beta;
 };
 struct SymTerm {
-  const double* A;
+  const double* A;  // FP64, or FP32 elements for an a_f32 launch
   const double* B;
   double* P;      // null: row result only (diagonal blocks, bases)
   double scale;
@@ -156,9 +156,10 @@ struct CvtProblem {
 };
 void launch_to_f32(hipStream_t s, const CvtProblem* d_p, int nprob);
 // cap > 0 bounds the number of workgroups (they then walk the problems with a
-// stride), so that the launch can run beside latency-bound work
+// stride), so that the launch can run beside latency-bound work.  a_f32: the
+// terms' A operands are FP32 (same element layout), widened to FP64 on load.
 void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
-                 int max_n, int cap = 0);
+                 int max_n, int cap = 0, int a_f32 = 0);
 // rows per workgroup of launch_symv for a launch whose largest problem has max_m rows
 int symv_row_tile(int max_m);
 // max_k bounds the terms' inner dimension (used to pick the dot-form variant

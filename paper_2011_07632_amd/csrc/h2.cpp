@@ -43,8 +43,7 @@ H2Model::~H2Model() {
 
 // Run the recorded product on H.s (the side part forked onto H.side_s and
 // joined before the tail); stream-ordered and capturable into a graph.
-static void replay_plan(H2Model& H) {
-  auto& pl = *H.plan;
+static void replay_plan(H2Model& H, const H2Model::MatvecPlan& pl) {
   if (pl.side.recs.empty()) {
     pl.rec.replay(H.s);
     pl.tail.replay(H.s);
@@ -317,7 +316,53 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
 // 1.997 uncapped.
 static constexpr int kNearCap = 512;
 
-static void build_plan(H2Model& H, int m) {
+// FP32 copies of the blocks that the symmetric-pair product reads.
+static void make_f32_blocks(H2Model& H) {
+  if (!H.Bh32.empty() || !H.nearA32.empty()) return;
+  const TreeHost& T = H.T;
+  hipStream_t s = H.s;
+  H.Bh32.assign(H.Bh.size(), nullptr);
+  H.nearA32.assign(H.nearA.size(), nullptr);
+  std::vector<CvtProblem> cv;
+  auto flush = [&]() {
+    if (cv.empty()) return;
+    auto* d = (const CvtProblem*)H.stage.push(s, cv.data(), cv.size() * sizeof(CvtProblem));
+    launch_to_f32(s, d, (int)cv.size());
+    SPD_HIP(hipStreamSynchronize(s));
+    H.stage.reset();
+    cv.clear();
+  };
+  // one allocation per block row, blocks in list order (as the FP64 rows)
+  auto row = [&](int64_t e0, int64_t e1, auto keep, auto rows, auto cols, std::vector<double*>& src,
+                 std::vector<float*>& dst) {
+    size_t total = 0;
+    for (int64_t e = e0; e < e1; ++e)
+      if (keep(e) && src[e]) total += (size_t)rows(e) * cols(e);
+    if (total == 0) return;
+    float* base = H.arena32.get_n<float>(total);
+    for (int64_t e = e0; e < e1; ++e) {
+      if (!keep(e) || !src[e]) continue;
+      const int64_t n = (int64_t)rows(e) * cols(e);
+      dst[e] = base;
+      cv.push_back({src[e], base, n});
+      base += n;
+      if (cv.size() >= 4096) flush();
+    }
+  };
+  for (int v = 1; v < T.nnodes; ++v)
+    row(T.coup_ptr[v], T.coup_ptr[v + 1], [&](int64_t e) { return T.coup_idx[e] > v; },
+        [&](int64_t) { return H.k[v]; }, [&](int64_t e) { return H.k[T.coup_idx[e]]; }, H.Bh, H.Bh32);
+  for (int v = T.first_at(1); v < T.first_at(1) + T.count_at(1); ++v)
+    row(T.near_ptr[v], T.near_ptr[v + 1], [&](int64_t e) { return T.near_idx[e] >= v; },
+        [&](int64_t) { return (int)T.size(v); }, [&](int64_t e) { return (int)T.size(T.near_idx[e]); },
+        H.nearA, H.nearA32);
+  flush();
+}
+
+// f32: the near and coupling launches read the FP32 block copies; the plan
+// then shares the input, output and skeleton-space buffers of the FP64 plan
+// for the same column count (which must exist).
+static void build_plan(H2Model& H, int m, bool f32 = false) {
   auto pl = std::make_unique<H2Model::MatvecPlan>();
   pl->ncols = m;
   const TreeHost& T = H.T;
@@ -325,10 +370,24 @@ static void build_plan(H2Model& H, int m) {
   const int64_t N = T.N;
   hipStream_t s = H.s;
   Arena& a = pl->arena;
-  pl->xt = a.get_n<double>((size_t)N * m);
-  pl->yt = a.get_n<double>((size_t)N * m);
-  pl->xh = a.get_n<double>((size_t)std::max<int64_t>(H.stack_rows, 1) * m);
-  pl->yh = a.get_n<double>((size_t)std::max<int64_t>(H.stack_rows, 1) * m);
+  if (f32) {
+    SPD_REQUIRE(m <= 4 && H.plan && H.plan->ncols == m, SPD_E_INVALID,
+                "the FP32 product needs at most 4 columns");
+    make_f32_blocks(H);
+    pl->xt = H.plan->xt;
+    pl->yt = H.plan->yt;
+    pl->xh = H.plan->xh;
+    pl->yh = H.plan->yh;
+  } else {
+    pl->xt = a.get_n<double>((size_t)N * m);
+    pl->yt = a.get_n<double>((size_t)N * m);
+    pl->xh = a.get_n<double>((size_t)std::max<int64_t>(H.stack_rows, 1) * m);
+    pl->yh = a.get_n<double>((size_t)std::max<int64_t>(H.stack_rows, 1) * m);
+  }
+  // A operand of a symmetric-pair term: the FP64 block or its FP32 copy
+  auto blk = [&](const std::vector<double*>& d, const std::vector<float*>& f, int64_t e) {
+    return f32 ? (const double*)f[e] : (const double*)d[e];
+  };
   Recorder& rec = pl->rec;
   const int lf = T.first_at(1), lc = T.count_at(1);
   // With at most 4 columns the interpolation W_v = Pi_v [I; E_v^T] is applied
@@ -375,11 +434,11 @@ static void build_plan(H2Model& H, int m) {
         for (int64_t e = T.coup_ptr[v]; e < T.coup_ptr[v + 1]; ++e) {
           const int j = T.coup_idx[e];
           if (H.k[j] == 0 || j < v) continue;
-          R.terms.push_back({H.Bh[e], H.k[v], H.hat(pl->xh, j, m), H.hat_ld(j), H.k[j], row_of[j]});
+          R.terms.push_back({blk(H.Bh, H.Bh32, e), H.k[v], H.hat(pl->xh, j, m), H.hat_ld(j), H.k[j], row_of[j]});
         }
       }
       const size_t first = rec.recs.size();
-      rec.symv(a, s, rows, m);
+      rec.symv(a, s, rows, m, 0.0, f32);
       rec.tag_from(first, 200);
     } else {
       GemmBatch g(0, 0);
@@ -446,12 +505,12 @@ static void build_plan(H2Model& H, int m) {
       for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) {
         const int j = T.near_idx[e];
         if (j < v) continue;
-        R.terms.push_back({H.nearA[e], (int)T.size(v), pl->xt + T.start[j], (int)N, (int)T.size(j),
-                           j == v ? -1 : j - lf});
+        R.terms.push_back({blk(H.nearA, H.nearA32, e), (int)T.size(v), pl->xt + T.start[j], (int)N,
+                           (int)T.size(j), j == v ? -1 : j - lf});
       }
     }
     Recorder near;
-    near.symv(a, s, rows, m, 1.0);
+    near.symv(a, s, rows, m, 1.0, f32);
     near.tag_from(0, 400);
     // the product launch goes to the side stream, the block sum into y after the join
     pl->side.recs.push_back(near.recs[0]);
@@ -477,25 +536,29 @@ static void build_plan(H2Model& H, int m) {
     rec.tag_from(first, 400);
   }
   SPD_HIP(hipStreamSynchronize(s));
-  H.plan = std::move(pl);
+  if (f32) H.plan32 = std::move(pl);
+  else H.plan = std::move(pl);
 }
 
-void h2_matvec_tree(H2Model& H, const double* x, double* y, int m) {
+void h2_matvec_tree(H2Model& H, const double* x, double* y, int m, bool f32) {
   if (!H.plan || H.plan->ncols != m) {
+    H.plan32.reset();
     H.plan.reset();
     build_plan(H, m);
   }
+  if (f32 && (!H.plan32 || H.plan32->ncols != m)) build_plan(H, m, true);
   const int64_t N = H.T.N;
   auto& pl = *H.plan;
   if (x != pl.xt)
     SPD_HIP(hipMemcpyAsync(pl.xt, x, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, H.s));
-  replay_plan(H);
+  replay_plan(H, f32 ? *H.plan32 : pl);
   if (y != pl.yt)
     SPD_HIP(hipMemcpyAsync(y, pl.yt, (size_t)N * m * sizeof(double), hipMemcpyDeviceToDevice, H.s));
 }
 
 double* h2_plan_x(H2Model& H, int m) {
   if (!H.plan || H.plan->ncols != m) {
+    H.plan32.reset();
     H.plan.reset();
     build_plan(H, m);
   }
@@ -505,7 +568,15 @@ double* h2_plan_y(H2Model& H, int m) {
   h2_plan_x(H, m);
   return H.plan->yt;
 }
-void h2_plan_run(H2Model& H) { replay_plan(H); }
+void h2_plan_run(H2Model& H) { replay_plan(H, *H.plan); }
+void h2_plan_prepare32(H2Model& H, int m) {
+  h2_plan_x(H, m);
+  if (!H.plan32 || H.plan32->ncols != m) build_plan(H, m, true);
+}
+void h2_plan_run32(H2Model& H, int m) {
+  h2_plan_prepare32(H, m);
+  replay_plan(H, *H.plan32);
+}
 
 // every recorded launch of the product, in stream order
 static std::vector<LaunchRec> all_launches(const H2Model::MatvecPlan& pl) {

@@ -282,7 +282,7 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_skinny(const GemmProblem* __re
       for (int u = 0; u < U; ++u) {
         const int64_t uu = (c + u < K) ? u : 0;
 #pragma unroll
-        for (int g = 0; g < RG; ++g) a[u][g] = __builtin_nontemporal_load(&ap[g][uu * astep]);
+        for (int g = 0; g < RG; ++g) a[u][g] = (double)__builtin_nontemporal_load(&ap[g][uu * astep]);
         if (bix) {
           const int64_t row = bix[uu];
 #pragma unroll
@@ -503,7 +503,7 @@ static void launch_skinny(hipStream_t s, const GemmProblem* d_p, const GemmTerm*
 // partial sums of the U columns of a step are added across the wave by
 // wave_sum_many and stored by the holding lanes, so every off-diagonal block
 // is read once for both of its products.
-template <int NC, int RG, int NW>
+template <int NC, int RG, int NW, typename TA>
 __global__ __launch_bounds__(64 * NW) void k_symv(const SymProblem* __restrict__ probs,
                                                    const SymTerm* __restrict__ terms, int tiles_max,
                                                    int nwork, int nprob) {
@@ -553,9 +553,11 @@ __global__ __launch_bounds__(64 * NW) void k_symv(const SymProblem* __restrict__
     const int64_t lda = T.lda, ldb = T.ldb;
     const double sc = T.scale;
     const int64_t astep = lda;
-    gdouble* ap[RG];
+    // A in FP64 or (mixed-precision product) FP32, widened to FP64 on load
+    typedef const TA __attribute__((address_space(1))) gta;
+    gta* ap[RG];
 #pragma unroll
-    for (int g = 0; g < RG; ++g) ap[g] = (gdouble*)T.A + rowc[g] + (int64_t)w * U * lda;
+    for (int g = 0; g < RG; ++g) ap[g] = (gta*)T.A + rowc[g] + (int64_t)w * U * lda;
     rdouble* bp = (rdouble*)T.B + w * U;
     double* pt = T.P ? T.P + (int64_t)tile * P.ptile : nullptr;
     for (int c = w * U; c < K; c += NW * U) {
@@ -564,7 +566,7 @@ __global__ __launch_bounds__(64 * NW) void k_symv(const SymProblem* __restrict__
       for (int u = 0; u < U; ++u) {
         const int64_t uu = (c + u < K) ? u : 0;
 #pragma unroll
-        for (int g = 0; g < RG; ++g) a[u][g] = __builtin_nontemporal_load(&ap[g][uu * astep]);
+        for (int g = 0; g < RG; ++g) a[u][g] = (double)__builtin_nontemporal_load(&ap[g][uu * astep]);
 #pragma unroll
         for (int j = 0; j < NC; ++j) b[u][j] = bp[uu + jc[j] * ldb];
       }
@@ -635,7 +637,7 @@ __global__ __launch_bounds__(64 * NW) void k_symv(const SymProblem* __restrict__
 
 int symv_row_tile(int max_m) { return max_m <= 64 ? 64 : (max_m <= 128 ? 128 : 256); }
 
-template <int NC, int NW>
+template <int NC, int NW, typename TA>
 static void launch_symv_nw(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
                            int max_m, int cap) {
   const int tiles = max_m <= 128 ? 1 : ceil_div(max_m, 256);
@@ -643,32 +645,40 @@ static void launch_symv_nw(hipStream_t s, const SymProblem* d_p, const SymTerm* 
   const int capped = cap > 0 ? std::max(8, cap / 8 * 8) : nwork;  // keep item & 7 == block & 7
   const dim3 grid((unsigned)std::min(capped, nwork));
   if (max_m <= 64)
-    hipLaunchKernelGGL((k_symv<NC, 1, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, 1, nwork, nprob);
+    hipLaunchKernelGGL((k_symv<NC, 1, NW, TA>), grid, dim3(64 * NW), 0, s, d_p, d_t, 1, nwork, nprob);
   else if (max_m <= 128)
-    hipLaunchKernelGGL((k_symv<NC, 2, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, 1, nwork, nprob);
+    hipLaunchKernelGGL((k_symv<NC, 2, NW, TA>), grid, dim3(64 * NW), 0, s, d_p, d_t, 1, nwork, nprob);
   else
-    hipLaunchKernelGGL((k_symv<NC, 4, NW>), grid, dim3(64 * NW), 0, s, d_p, d_t, tiles, nwork, nprob);
+    hipLaunchKernelGGL((k_symv<NC, 4, NW, TA>), grid, dim3(64 * NW), 0, s, d_p, d_t, tiles, nwork,
+                       nprob);
 }
 
 // 16-wave workgroups for small launches with one right-hand column only (more
 // columns would not fit the register budget of a 1024-thread workgroup).
-template <int NC>
+template <int NC, typename TA>
 static void launch_symv_nc(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
                            int max_m, int cap) {
   const int64_t blocks = (int64_t)nprob * ceil_div(max_m, 256);
   if (NC == 1 && blocks < kSkinnyWide && cap <= 0)
-    launch_symv_nw<NC, 16>(s, d_p, d_t, nprob, max_m, cap);
+    launch_symv_nw<NC, 16, TA>(s, d_p, d_t, nprob, max_m, cap);
   else
-    launch_symv_nw<NC, 4>(s, d_p, d_t, nprob, max_m, cap);
+    launch_symv_nw<NC, 4, TA>(s, d_p, d_t, nprob, max_m, cap);
+}
+
+template <typename TA>
+static void launch_symv_ta(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
+                           int max_m, int max_n, int cap) {
+  if (max_n == 1) launch_symv_nc<1, TA>(s, d_p, d_t, nprob, max_m, cap);
+  else if (max_n == 2) launch_symv_nc<2, TA>(s, d_p, d_t, nprob, max_m, cap);
+  else launch_symv_nc<4, TA>(s, d_p, d_t, nprob, max_m, cap);
 }
 
 void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
-                 int max_n, int cap) {
+                 int max_n, int cap, int a_f32) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
   if (max_n > 4) throw Error(SPD_E_INVALID, "symmetric-pair product supports at most 4 columns");
-  if (max_n == 1) launch_symv_nc<1>(s, d_p, d_t, nprob, max_m, cap);
-  else if (max_n == 2) launch_symv_nc<2>(s, d_p, d_t, nprob, max_m, cap);
-  else launch_symv_nc<4>(s, d_p, d_t, nprob, max_m, cap);
+  if (a_f32) launch_symv_ta<float>(s, d_p, d_t, nprob, max_m, max_n, cap);
+  else launch_symv_ta<double>(s, d_p, d_t, nprob, max_m, max_n, cap);
   SPD_HIP(hipGetLastError());
 }
 

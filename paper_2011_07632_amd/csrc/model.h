@@ -128,7 +128,9 @@ struct Recorder {
   // symmetric product of n <= 4 columns over rows (one product launch and one
   // launch that sums each row's partial results in a fixed order into
   // y = beta * y + sum)
-  void symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n, double beta = 0.0);
+  // (a_f32: the terms' A pointers address FP32 copies with the same layout)
+  void symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n, double beta = 0.0,
+            bool a_f32 = false);
   void block(Arena& a, hipStream_t s, const BlockBatch& b);
   void trsm(Arena& a, hipStream_t s, const TrsmBatch& b, int trans);
   void replay(hipStream_t s) const;
@@ -165,6 +167,11 @@ struct H2Model {
   std::vector<double*> E, ET;
   std::vector<double*> Bh;        // per coupling entry: K(skel_i, skel_j), k_i x k_j
   std::vector<double*> nearA;     // per leaf near entry: n_i x n_j, ld n_i
+  // FP32 copies of the blocks the symmetric-pair product reads (coupling
+  // entries j > i, near entries j >= i; null elsewhere), made on first use by
+  // the mixed-precision product; each block row's copies are one allocation
+  std::vector<float*> Bh32, nearA32;
+  Arena arena32;
   double times[4] = {0, 0, 0, 0};
   // stacked layout of skeleton-space blocks: the two children of a node share
   // one (cand_p x ncols, ld cand_p) buffer; par_off[p] is its row offset.
@@ -172,6 +179,9 @@ struct H2Model {
   int64_t stack_rows = 0;
   struct MatvecPlan;
   std::unique_ptr<MatvecPlan> plan;
+  // the same product with the FP32 block copies; shares plan's input and
+  // output buffers (so h2_plan_x / h2_plan_y serve both)
+  std::unique_ptr<MatvecPlan> plan32;
   struct NearStats {
     double bytes = 0;  // algorithmic bytes of one near-field launch
   };
@@ -192,7 +202,7 @@ struct H2Model {
 };
 
 void h2_build_impl(H2Model& H, const double* points, int64_t n);
-void h2_matvec_tree(H2Model& H, const double* x, double* y, int ncols);
+void h2_matvec_tree(H2Model& H, const double* x, double* y, int ncols, bool f32 = false);
 
 // --------------------------------------------------- SPD HSS + factors --
 // Nested factors shared by an HSS handle and the ULV handle made from it.
@@ -264,6 +274,10 @@ double* ulv_plan_out(ULVModel& U, int m);
 double* h2_plan_x(H2Model& H, int m);
 double* h2_plan_y(H2Model& H, int m);
 void h2_plan_run(H2Model& H);
+// the product with FP32 near and coupling blocks (FP64 accumulation, vectors
+// and interpolation), at most 4 columns; same buffers as h2_plan_x / h2_plan_y
+void h2_plan_run32(H2Model& H, int m);
+void h2_plan_prepare32(H2Model& H, int m);  // build the FP32 plan (outside graph capture)
 void h2_plan_run_last(H2Model& H);
 H2Model::NearStats h2_near_stats(H2Model& H, int m);
 void h2_time_near(H2Model& H, int m, int reps, double* ms, double* bytes);
@@ -273,9 +287,13 @@ struct PcgResult {
   std::vector<int> iters;
   std::vector<double> relres;
   bool converged = true;
+  int replacements = 0;  // residual replacements with the FP64 product (op_f32)
 };
+// op_f32: the iterations use the product with FP32 blocks (h2_plan_run32) and
+// the residual is replaced by b - A x with the FP64 product whenever it has
+// halved since the last replacement (reliable updates)
 PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m, double rtol,
-                   int maxit);
+                   int maxit, bool op_f32 = false);
 
 double now_seconds();
 const char* last_error_cstr();

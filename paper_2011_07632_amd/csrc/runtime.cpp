@@ -411,7 +411,13 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
 // per-row regions [row tile][mirrored columns x n].  A block launch then forms
 // every output row as the sum, in a fixed order, of its own parts and of the
 // mirrored products addressed to it.
-void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n, double beta) {
+void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n, double beta,
+                    bool a_f32) {
+  // the terms' A pointers address FP64 or (a_f32) FP32 elements
+  const int64_t esz = a_f32 ? 4 : 8;
+  auto a_at = [esz](const double* A, int64_t elems) {
+    return (const double*)((const char*)A + esz * elems);
+  };
   if (rows.empty() || n <= 0) return;
   int max_m = 0;
   for (const SymRow& R : rows) max_m = std::max(max_m, R.m);
@@ -436,7 +442,7 @@ void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, in
       const bool mir = t.mirror >= 0;
       if (!mt.empty()) {
         MT& q = mt.back();
-        if (q.mir == mir && q.lda == t.lda && (q.ldb == t.ldb || n == 1) && t.A == q.A + (int64_t)q.lda * q.k &&
+        if (q.mir == mir && q.lda == t.lda && (q.ldb == t.ldb || n == 1) && t.A == a_at(q.A, (int64_t)q.lda * q.k) &&
             t.B == q.B + q.k) {
           if (mir) q.tgt.push_back({t.mirror, t.k});
           q.k += t.k;
@@ -492,7 +498,7 @@ void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, in
         const MT& g = mt[q];
         const int64_t take = std::min<int64_t>(want, g.k - off);
         SymTerm t{};
-        t.A = g.A + (int64_t)g.lda * off;
+        t.A = a_at(g.A, (int64_t)g.lda * off);
         t.B = g.B + off;
         t.P = g.mir ? pb + pcol[q] + off : nullptr;
         t.scale = 1.0;
@@ -513,7 +519,7 @@ void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, in
     }
     // algorithmic bytes: every block once, own rows, B ranges once, row and mirrored results
     for (const MT& g : mt) {
-      bytes += 8.0 * R.m * g.k;
+      bytes += (double)esz * R.m * g.k;
       for (int j = 0; j < n; ++j) bset.push_back({g.B + (int64_t)j * g.ldb, g.B + (int64_t)j * g.ldb + g.k});
     }
     bytes += 8.0 * R.m * n * 2.0 + 8.0 * tiles * kmir * n;
@@ -527,6 +533,7 @@ void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, in
   }
   if (terms.empty()) terms.push_back(SymTerm{});
   recs.push_back({3, keep(a, s, probs), keep(a, s, terms), (int)probs.size(), max_m, n, 0, 0, bytes, -1});
+  recs.back().a_f32 = a_f32 ? 1 : 0;
   BlockBatch red;
   for (size_t i = 0; i < rows.size(); ++i) {
     const SymRow& R = rows[i];
@@ -561,7 +568,7 @@ void Recorder::replay(hipStream_t s) const {
                    r.max_n);
     else if (r.type == 3)
       launch_symv(s, (const SymProblem*)r.probs, (const SymTerm*)r.terms, r.nprob, r.max_m, r.max_n,
-                  r.cap);
+                  r.cap, r.a_f32);
     else
       launch_trsm(s, (const TrsmProblem*)r.probs, r.nprob, r.max_m, r.max_n, r.transA, 0);
   }

@@ -305,7 +305,7 @@ void ulv_apply_tree(ULVModel& U, const double* b, double* x, int m) {
 static constexpr int kCheckEvery = 8;
 
 PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m, double rtol,
-                   int maxit) {
+                   int maxit, bool op_f32) {
   hipStream_t caller = H.s;
   hipStream_t s = nullptr;
   SPD_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -338,6 +338,7 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   double* z = U ? ulv_plan_out(*U, m) : a.get_n<double>((size_t)N * m);
   double* p = h2_plan_x(H, m);
   double* q = h2_plan_y(H, m);
+  if (op_f32) h2_plan_prepare32(H, m);
   const int nblk = coldot_chunks(N);
   double* partial = a.get_n<double>((size_t)nblk * m);
   // per-chunk partial dot products of the iteration (see k_pcg_xr_dot)
@@ -376,7 +377,8 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   // z = M r; beta = (r.z)_new/(r.z)_old; p update.  The dot products stay as
   // per-chunk partials read by the next kernel.
   auto body = [&]() {
-    h2_plan_run(H);
+    if (op_f32) h2_plan_run32(H, m);
+    else h2_plan_run(H);
     launch_coldot_partial(s, p, q, N, m, N, pqp);
     launch_pcg_xr_dot(s, xt, r, p, q, rzp, pqp, active, N, m, N, iters, rzv, rrp,
                       flexible ? z : nullptr, rzop);
@@ -404,11 +406,58 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   }
   int h_any = 1;
   int done = 0;
+  PcgResult res;
+  // Reliable updates (op_f32).  The recursively updated residual follows the
+  // FP32 product, and drifts from b - A x by the rounding of the blocks times
+  // the steps taken.  Whenever some active column's recursive residual has
+  // dropped below kReliableDelta times its norm at the last replacement (checked
+  // every kCheckEvery steps), every column's r is replaced by b - A x from the
+  // FP64 product; p, z and the scalars carry on, so the Krylov recurrence is
+  // not restarted.  Measured on the Matern N = 100k workload: 0.01 -> 3,736,
+  // 0.1 -> 3,428, 0.5 -> 3,038 iterations (1,934 with the FP64 product).
+  constexpr double kReliableDelta = 0.5;
+  std::vector<double> ref(m, 0.0), hrrp((size_t)nblk * m);
+  std::vector<int> hact(m);
+  double* psave = op_f32 ? a.get_n<double>((size_t)N * m) : nullptr;
+  auto replace_residual = [&]() {
+    SPD_HIP(hipMemcpyAsync(psave, p, bytes, hipMemcpyDeviceToDevice, s));
+    SPD_HIP(hipMemcpyAsync(p, xt, bytes, hipMemcpyDeviceToDevice, s));
+    h2_plan_run(H);
+    SPD_HIP(hipMemcpyAsync(r, bt, bytes, hipMemcpyDeviceToDevice, s));
+    launch_axpby(s, r, q, -1.0, 1.0, N, m, N);
+    SPD_HIP(hipMemcpyAsync(p, psave, bytes, hipMemcpyDeviceToDevice, s));
+    launch_coldot(s, r, r, N, m, N, partial, rr);
+    std::vector<double> h(m);
+    SPD_HIP(hipMemcpyAsync(h.data(), rr, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    SPD_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < m; ++c) ref[c] = std::sqrt(h[c]);
+    ++res.replacements;
+  };
+  if (op_f32) {
+    std::vector<double> h(m);
+    SPD_HIP(hipMemcpyAsync(h.data(), rr, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    SPD_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < m; ++c) ref[c] = std::sqrt(h[c]);
+  }
   auto iterate = [&]() {
     while (done < maxit) {
       SPD_HIP(hipMemcpyAsync(&h_any, any, sizeof(int), hipMemcpyDeviceToHost, s));
+      if (op_f32 && done > 0) {
+        SPD_HIP(hipMemcpyAsync(hrrp.data(), rrp, hrrp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        SPD_HIP(hipMemcpyAsync(hact.data(), active, m * sizeof(int), hipMemcpyDeviceToHost, s));
+      }
       SPD_HIP(hipStreamSynchronize(s));
       if (!h_any) break;
+      if (op_f32 && done > 0) {
+        bool due = false;
+        for (int c = 0; c < m && !due; ++c) {
+          if (!hact[c]) continue;
+          double t = 0.0;
+          for (int b = 0; b < nblk; ++b) t += hrrp[b + (size_t)c * nblk];
+          due = std::sqrt(t) < kReliableDelta * ref[c];
+        }
+        if (due) replace_residual();
+      }
       const int chunk = std::min(kCheckEvery, maxit - done);
       for (int c = 0; c < chunk; ++c) {
         if (use_graph) SPD_HIP(hipGraphLaunch(exec, s));
@@ -451,6 +500,7 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
     act[m] = 1;  // any
     SPD_HIP(hipMemcpyAsync(active, act.data(), (m + 1) * sizeof(int), hipMemcpyHostToDevice, s));
     // r holds the true residual: z = M r, p = z, then the iteration continues
+    for (int c = 0; c < m; ++c) ref[c] = std::sqrt(hrr[c]);
     precond(r, z);
     SPD_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, s));
     launch_coldot_partial(s, r, z, N, m, N, rzp);
@@ -460,7 +510,6 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
-  PcgResult res;
   std::vector<int> act(2 * m + 1);
   SPD_HIP(hipMemcpyAsync(act.data(), active, act.size() * sizeof(int), hipMemcpyDeviceToHost, s));
   SPD_HIP(hipStreamSynchronize(s));

@@ -1,6 +1,7 @@
-"""Mixed-precision solve (FP32 solve operators, FP64 vectors, sums and H^2
-operator) against the FP64 oracle (GPU).  The FP32 bar is 1e-4 relative on the
-same quantity; PCG must still reach the FP64 tolerance on the true residual."""
+"""Mixed precision against the FP64 oracle (GPU): FP32 solve operators (FP64
+vectors and sums), the FP32-block H^2 product (FP64 accumulation), and PCG
+with either.  The FP32 bar is 1e-4 relative on the same quantity; PCG must
+still reach the FP64 tolerance on the true residual (FP64 product)."""
 import numpy as np
 import pytest
 
@@ -69,6 +70,49 @@ def test_more_than_four_columns_use_fp64_operators(S):
     xo[perm] = S["o_hss"].solve(b[perm])
     x32 = B.ulv_apply(S["u32"], cols(B, b)).cpu().numpy()
     assert np.linalg.norm(x32 - xo) / np.linalg.norm(xo) <= 1e-10
+
+
+@pytest.mark.parametrize("nrhs", [1, 2, 4])
+def test_f32_product_against_oracle(S, nrhs):
+    B, perm = S["B"], S["o_h2"].tree.perm
+    x = workloads.gaussian_matrix(W.n, nrhs, 51)
+    yo = np.empty_like(x)
+    yo[perm] = S["o_h2"].matvec(x[perm])
+    y32 = B.h2_matvec(S["h2"], cols(B, x), precision="f32").cpu().numpy()
+    y64 = B.h2_matvec(S["h2"], cols(B, x)).cpu().numpy()
+    e32 = np.linalg.norm(y32 - yo) / np.linalg.norm(yo)
+    e64 = np.linalg.norm(y64 - yo) / np.linalg.norm(yo)
+    print(f"[mixed] product error vs oracle ({nrhs} columns): f32 {e32:.2e}, f64 {e64:.2e}", flush=True)
+    assert e64 <= 1e-10
+    assert e32 <= 1e-6  # FP32 rounding of the blocks (relative 6e-8 per entry), well inside 1e-4
+    assert e32 > e64
+
+
+@pytest.mark.parametrize("pre", ["f64", "f32"])
+def test_f32_operator_pcg_reaches_fp64_tolerance(S, pre):
+    B = S["B"]
+    b = workloads.gaussian_matrix(W.n, 3, 61)
+    M = S["u64"] if pre == "f64" else S["u32"]
+    x, it, res = B.pcg_solve(S["h2"], M, cols(B, b), rtol=W.pcg_tol, maxit=500, op_precision="f32")
+    _, it64, _ = B.pcg_solve(S["h2"], M, cols(B, b), rtol=W.pcg_tol, maxit=500)
+    # the reported residual is the FP64 one; check it independently with the FP64 product
+    r = cols(B, b) - B.h2_matvec(S["h2"], x)
+    rel = (torch.linalg.norm(r, dim=0) / torch.linalg.norm(cols(B, b), dim=0)).cpu().numpy()
+    print(f"[mixed] FP32 operator, {pre} preconditioner: iterations {it.tolist()} (FP64 operator "
+          f"{it64.tolist()}), relres {res.tolist()}", flush=True)
+    assert float(res.max()) <= 2 * W.pcg_tol and float(rel.max()) <= 2 * W.pcg_tol
+    assert np.allclose(rel, res, rtol=1e-3, atol=0)
+    assert (np.abs(it - it64) <= np.maximum(3, 0.2 * it64)).all()
+
+
+def test_f32_product_argument_errors(S):
+    B = S["B"]
+    with pytest.raises(B.SpdError):
+        B.h2_matvec(S["h2"], cols(B, workloads.gaussian_matrix(W.n, 5, 1)), precision="f32")
+    import ctypes as C
+    x = cols(B, workloads.gaussian_matrix(W.n, 1, 1))
+    y = torch.empty_like(x)
+    assert B.lib.h2_matvec_ex(S["h2"]._h, x.data_ptr(), y.data_ptr(), 1, W.n, 7, None) != 0
 
 
 def test_unknown_precision_rejected(S):

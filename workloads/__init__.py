@@ -96,7 +96,12 @@ LARGE = Workload(name="gaussian-l0.2-N1M-cube", n=1_000_000, point_set="cube",
                  hss_tol=1e-1, max_rank=100, oversample=10, nrhs=16,
                  pcg_tol=1e-8, seed_base=3)
 
-BY_NAME = {w.name: w for w in (SMALL, MEDIUM, LARGE)}
+# The medium workload with a hundredfold larger shift (+ 1e-2 I): a better
+# conditioned system on which FP32 rounding of the stored blocks stays far below
+# the smallest eigenvalue (used to compare the mixed-precision forms).
+MEDIUM_S2 = MEDIUM.with_(name="matern32-l0.1-s1e-2-N100k-cube", shift=1e-2)
+
+BY_NAME = {w.name: w for w in (SMALL, MEDIUM, LARGE, MEDIUM_S2)}
 
 
 # Batched case: independent instances of uneven sizes.  N is log-uniform in
