@@ -119,3 +119,22 @@ def test_pcg_mixed_precision_reaches_tolerance(F):
     print(f"[fullsize] mixed-precision PCG iterations {it.tolist()} true relative residual {res.tolist()}",
           flush=True)
     assert float(res.max()) <= 2 * W.pcg_tol
+
+
+def test_pcg_fp32_product_reaches_tolerance(F):
+    """The FP32-block product inside PCG on this ill-conditioned system
+    (sigma = 1e-4): reliable updates with the FP64 product bring the true
+    residual to the FP64 tolerance; the FP32 product itself stays within FP32
+    rounding of the FP64 one."""
+    v = cols(F, np.random.default_rng(17).standard_normal((W.n, 1)))
+    y64 = F.B.h2_matvec(F.h2, v)
+    y32 = F.B.h2_matvec(F.h2, v, precision="f32")
+    d = float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64))
+    b = cols(F, W.rhs())
+    x, it, res = F.B.pcg_solve(F.h2, F.ulv, b, rtol=W.pcg_tol, maxit=20000, op_precision="f32")
+    r = b - F.B.h2_matvec(F.h2, x)
+    rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+    print(f"[fullsize] FP32-product PCG iterations {it.tolist()} true relative residual {res.tolist()} "
+          f"(checked {rel:.2e}); product difference {d:.2e}", flush=True)
+    assert 0 < d <= 1e-6
+    assert float(res.max()) <= 2 * W.pcg_tol and rel <= 2 * W.pcg_tol
