@@ -1277,7 +1277,6 @@ __global__ __launch_bounds__(1024) void k_cpqr_glob(const CpqrProblem* __restric
   constexpr int NW = 16;
   extern __shared__ double sm[];  // vbuf[64*RCH] | nrm2[n]
   __shared__ double sh_beta;
-  __shared__ int sh_rank;
   const CpqrProblem P = probs[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = P.m, n = P.n;
@@ -1359,7 +1358,7 @@ __global__ __launch_bounds__(1024) void k_cpqr_glob(const CpqrProblem* __restric
     rank = t + 1;
     __syncthreads();
   }
-  if (threadIdx.x == 0) { *P.rank = rank; sh_rank = rank; }
+  if (threadIdx.x == 0) *P.rank = rank;
   __syncthreads();
   // complete the permutation with the unused columns in ascending order
   if (threadIdx.x == 0) {
