@@ -44,6 +44,11 @@ CASES = {
     "deep20000": dict(w=workloads.SMALL.with_(name="gaussian-l0.2-N20000-deep", n=20000, ell=0.2, shift=1e-1,
                                               leaf=10, max_rank=30, hss_tol=1e-1, seed_base=10),
                       shells=4, per_shell=64, pcg_maxit=60),
+    # constant-density ball (the paper's point set), Matern kernel
+    "ball1800": dict(w=workloads.SMALL.with_(name="matern32-l0.2-N1800-ball", n=1800, point_set="ball",
+                                             kernel="matern32", ell=0.2, shift=1e-2, leaf=48, max_rank=40,
+                                             seed_base=11),
+                     shells=6, per_shell=96),
     # inverse multiquadric, fixed-rank form (tol = 0)
     "imq1200": dict(w=workloads.SMALL.with_(name="imq-c0.1-N1200", n=1200, kernel="imq", ell=0.1,
                                             shift=1e-3, leaf=30, max_rank=20, hss_tol=0.0, seed_base=9),

@@ -7,7 +7,9 @@ it without sharing any computation.
 Point sets follow the workload descriptions used for the experiments: points
 uniform in the unit cube, or uniform on the unit sphere surface (normalised
 standard-normal triples).  The paper itself uses constant-density balls and
-spheres (Section 6); the unit cube/sphere recipes stand in for them.
+spheres (Section 6); 'ball' gives the former (a uniform direction times a
+radius U^(1/3)), and the unit cube/sphere recipes stand in for them in the
+benchmark configurations.
 
 Array conventions
 -----------------
@@ -24,13 +26,18 @@ KERNELS = ("gaussian", "matern32", "exponential", "imq")
 
 
 def points(kind: str, n: int, seed: int) -> np.ndarray:
-    """Seeded point set: 'cube' = iid U[0,1)^3, 'sphere' = unit-sphere surface."""
+    """Seeded point set: 'cube' = iid U[0,1)^3, 'sphere' = unit-sphere surface,
+    'ball' = uniform (constant density) in the unit ball."""
     rng = np.random.default_rng(seed)
     if kind == "cube":
         x = rng.random((n, 3))
     elif kind == "sphere":
         g = rng.standard_normal((n, 3))
         x = g / np.linalg.norm(g, axis=1, keepdims=True)
+    elif kind == "ball":
+        g = rng.standard_normal((n, 3))
+        r = rng.random(n) ** (1.0 / 3.0)
+        x = g / np.linalg.norm(g, axis=1, keepdims=True) * r[:, None]
     else:
         raise ValueError(f"unknown point set {kind!r}")
     return np.ascontiguousarray(x, dtype=np.float64)
