@@ -261,7 +261,8 @@ spd_status spd_server_submit(spd_server_t S, const spd_instance* request, int64_
  * (block == 0, not finished) or SPD_OK with *result filled and, if not NULL,
  * the seconds from submission to admission (*seconds_queued) and to
  * completion (*seconds_total); the ticket is then retired.  Unknown or
- * retired tickets give SPD_E_INVALID. */
+ * retired tickets give SPD_E_INVALID, and so does a blocking wait whose
+ * ticket another thread collected meanwhile.  Thread-safe. */
 spd_status spd_server_wait(spd_server_t S, int64_t ticket, int32_t block,
                            spd_instance_result* result, double* seconds_queued,
                            double* seconds_total);

@@ -37,9 +37,15 @@ struct spd_server {
   std::vector<std::thread> workers;
 
   void work() {
-    if (hipSetDevice(dev) != hipSuccess) return;
+    // a worker that cannot set the device or make a stream still drains the
+    // queue (run_instance then reports the device error per request, or runs
+    // on the null stream), so that no request waits forever
+    (void)hipSetDevice(dev);
     hipStream_t s = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      s = nullptr;
+    }
     for (;;) {
       int64_t t = 0;
       spd_instance inst{};
@@ -75,8 +81,10 @@ struct spd_server {
       cv_done.notify_all();
       cv_work.notify_all();
     }
-    (void)hipStreamSynchronize(s);
-    (void)hipStreamDestroy(s);
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
   }
 };
 
@@ -144,12 +152,21 @@ spd_status spd_server_wait(spd_server_t S, int64_t ticket, int32_t block, spd_in
   std::unique_lock<std::mutex> lk(S->mu);
   auto it = S->reqs.find(ticket);
   if (it == S->reqs.end()) {
-    spd::set_last_error("unknown ticket");
+    spd::set_last_error("unknown or already collected ticket");
     return SPD_E_INVALID;
   }
   if (!it->second.done) {
     if (!block) return SPD_PENDING;
-    S->cv_done.wait(lk, [&] { return it->second.done; });
+    // look the ticket up again after every wake-up: another thread waiting for
+    // the same ticket may have collected (and erased) it meanwhile
+    S->cv_done.wait(lk, [&] {
+      it = S->reqs.find(ticket);
+      return it == S->reqs.end() || it->second.done;
+    });
+    if (it == S->reqs.end()) {
+      spd::set_last_error("ticket collected by another waiter");
+      return SPD_E_INVALID;
+    }
   }
   const spd_server::Request& r = it->second;
   *result = r.res;

@@ -74,3 +74,31 @@ def test_footprint_grows_with_n(B):
     big = small.with_(n=8000)
     assert S.footprint(request(B, big)) > S.footprint(request(B, small))
     S.close()
+
+
+def test_two_waiters_on_one_ticket(B):
+    """Two threads block on the same ticket: one collects the result, the
+    other is told the ticket was collected (no hang, no stale entry)."""
+    import threading
+    w = workloads.batch_instances(count=1, seed=79, n_lo=1500, n_hi=2000)[0]
+    S = B.Server(workers=1)
+    t = S.submit(request(B, w))
+    out = {}
+
+    def waiter(k):
+        try:
+            out[k] = S.wait(t)["status"]
+        except B.SpdError as e:
+            out[k] = e.code
+
+    th = [threading.Thread(target=waiter, args=(k,)) for k in range(2)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join(timeout=120)
+    S.close()
+    assert not any(x.is_alive() for x in th)
+    got = sorted(out.values(), key=str)
+    assert len(got) == 2
+    assert sum(1 for v in got if v == B.SPD_E_INVALID) == 1
+    assert sum(1 for v in got if v in ("SPD_OK", "SPD_E_NOT_CONVERGED", "SPD_E_NOT_SPD")) == 1
