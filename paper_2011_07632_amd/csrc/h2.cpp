@@ -243,19 +243,21 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
     for (int v = 1; v < nn; ++v) {
       size_t row = 0;
       for (int64_t e = T.coup_ptr[v]; e < T.coup_ptr[v + 1]; ++e) row += (size_t)H.k[T.coup_idx[e]];
-      double* base = (H.k[v] > 0 && row > 0) ? H.arena.get_n<double>((size_t)H.k[v] * row) : nullptr;
+      const int ld = H.coup_ld(v);
+      double* base = (H.k[v] > 0 && row > 0) ? H.arena.get_n<double>((size_t)ld * row) : nullptr;
+      if (base) launch_fill(s, base, 0.0, (int64_t)ld * row);
       for (int64_t e = T.coup_ptr[v]; e < T.coup_ptr[v + 1]; ++e) {
         const int j = T.coup_idx[e];
         if (H.k[v] == 0 || H.k[j] == 0) continue;
         H.Bh[e] = base;
-        base += (size_t)H.k[v] * H.k[j];
+        base += (size_t)ld * H.k[j];
         KBlockProblem kp{};
         kp.out = H.Bh[e];
         kp.ia = H.skel_d(v);
         kp.ib = H.skel_d(j);
         kp.na = H.k[v];
         kp.nb = H.k[j];
-        kp.ld = H.k[v];
+        kp.ld = ld;
         kb.push_back(kp);
         mm = std::max(mm, kp.na);
         mn = std::max(mn, kp.nb);
@@ -264,19 +266,21 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
     for (int v = T.first_at(1); v < T.first_at(1) + T.count_at(1); ++v) {
       size_t row = 0;
       for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) row += (size_t)T.size(T.near_idx[e]);
-      double* base = H.arena.get_n<double>(std::max<size_t>((size_t)T.size(v) * row, 1));
+      const int ld = std::max(H.near_ld(v), 16);
+      double* base = H.arena.get_n<double>(std::max<size_t>((size_t)ld * row, 1));
+      launch_fill(s, base, 0.0, std::max<int64_t>((int64_t)ld * row, 1));
       for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) {
         const int j = T.near_idx[e];
         const int ni = (int)T.size(v), nj = (int)T.size(j);
         H.nearA[e] = base;
-        base += (size_t)ni * nj;
+        base += (size_t)ld * nj;
         KBlockProblem kp{};
         kp.out = H.nearA[e];
         kp.offa = T.start[v];
         kp.offb = T.start[j];
         kp.na = ni;
         kp.nb = nj;
-        kp.ld = std::max(ni, 1);
+        kp.ld = ld;
         kp.diag_shift = (v == j);
         kb.push_back(kp);
         mm = std::max(mm, ni);
@@ -351,11 +355,11 @@ static void make_f32_blocks(H2Model& H) {
   };
   for (int v = 1; v < T.nnodes; ++v)
     row(T.coup_ptr[v], T.coup_ptr[v + 1], [&](int64_t e) { return T.coup_idx[e] > v; },
-        [&](int64_t) { return H.k[v]; }, [&](int64_t e) { return H.k[T.coup_idx[e]]; }, H.Bh, H.Bh32);
+        [&](int64_t) { return H.coup_ld(v); }, [&](int64_t e) { return H.k[T.coup_idx[e]]; }, H.Bh, H.Bh32);
   for (int v = T.first_at(1); v < T.first_at(1) + T.count_at(1); ++v)
     row(T.near_ptr[v], T.near_ptr[v + 1], [&](int64_t e) { return T.near_idx[e] >= v; },
-        [&](int64_t) { return (int)T.size(v); }, [&](int64_t e) { return (int)T.size(T.near_idx[e]); },
-        H.nearA, H.nearA32);
+        [&](int64_t) { return std::max(H.near_ld(v), 16); },
+        [&](int64_t e) { return (int)T.size(T.near_idx[e]); }, H.nearA, H.nearA32);
   flush();
 }
 
@@ -434,7 +438,8 @@ static void build_plan(H2Model& H, int m, bool f32 = false) {
         for (int64_t e = T.coup_ptr[v]; e < T.coup_ptr[v + 1]; ++e) {
           const int j = T.coup_idx[e];
           if (H.k[j] == 0 || j < v) continue;
-          R.terms.push_back({blk(H.Bh, H.Bh32, e), H.k[v], H.hat(pl->xh, j, m), H.hat_ld(j), H.k[j], row_of[j]});
+          R.terms.push_back({blk(H.Bh, H.Bh32, e), H.coup_ld(v), H.hat(pl->xh, j, m), H.hat_ld(j), H.k[j],
+                             row_of[j]});
         }
       }
       const size_t first = rec.recs.size();
@@ -448,7 +453,7 @@ static void build_plan(H2Model& H, int m, bool f32 = false) {
         for (int64_t e = T.coup_ptr[v]; e < T.coup_ptr[v + 1]; ++e) {
           const int j = T.coup_idx[e];
           if (H.k[j] == 0) continue;
-          g.term(H.Bh[e], H.k[v], H.hat(pl->xh, j, m), H.hat_ld(j), H.k[j]);
+          g.term(H.Bh[e], H.coup_ld(v), H.hat(pl->xh, j, m), H.hat_ld(j), H.k[j]);
         }
       }
       const size_t first = rec.recs.size();
@@ -505,8 +510,8 @@ static void build_plan(H2Model& H, int m, bool f32 = false) {
       for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) {
         const int j = T.near_idx[e];
         if (j < v) continue;
-        R.terms.push_back({blk(H.nearA, H.nearA32, e), (int)T.size(v), pl->xt + T.start[j], (int)N,
-                           (int)T.size(j), j == v ? -1 : j - lf});
+        R.terms.push_back({blk(H.nearA, H.nearA32, e), std::max(H.near_ld(v), 16), pl->xt + T.start[j],
+                           (int)N, (int)T.size(j), j == v ? -1 : j - lf});
       }
     }
     Recorder near;
@@ -528,7 +533,7 @@ static void build_plan(H2Model& H, int m, bool f32 = false) {
       if (L > 1 && H.k[v] > 0) g.term(H.W[v], H.cand[v], H.hat(pl->yh, v, m), H.hat_ld(v), H.k[v]);
       for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) {
         const int j = T.near_idx[e];
-        g.term(H.nearA[e], (int)T.size(v), pl->xt + T.start[j], (int)N, (int)T.size(j));
+        g.term(H.nearA[e], std::max(H.near_ld(v), 16), pl->xt + T.start[j], (int)N, (int)T.size(j));
       }
     }
     const size_t first = rec.recs.size();

@@ -113,8 +113,10 @@ void couplings(Ctx& c, int lev, Arena& out) {
         const int ri = c.F.rho[i], rj = c.F.rho[j];
         double* Mt = tmp.get_n<double>((size_t)ri * r[j]);
         const double* Aij;
+        int ldA = ri;
         if (lev == 1) {
           Aij = c.H.nearA[p.e];
+          ldA = std::max(c.H.near_ld(i), 16);
         } else {
           double* Bb = tmp.get_n<double>((size_t)ri * rj);
           const int ci[2] = {2 * i + 1, 2 * i + 2}, cj[2] = {2 * j + 1, 2 * j + 2};
@@ -134,7 +136,7 @@ void couplings(Ctx& c, int lev, Arena& out) {
           Aij = Bb;
         }
         g1.add(Mt, ri, r[j], ri);
-        g1.term(Aij, ri, c.M.Z[j], rj, rj);
+        g1.term(Aij, ldA, c.M.Z[j], rj, rj);
         g2.add(Bij, r[i], r[j], r[i]);
         g2.term(c.M.Z[i], ri, Mt, ri, ri);
       } else {
@@ -145,7 +147,7 @@ void couplings(Ctx& c, int lev, Arena& out) {
         }
         double* Mt = tmp.get_n<double>((size_t)ki * r[j]);
         g1t.add(Mt, ki, r[j], ki);
-        g1t.term(c.H.Bh[p.e], ki, c.M.PhiU[j], r[j], kj);
+        g1t.term(c.H.Bh[p.e], c.H.coup_ld(i), c.M.PhiU[j], r[j], kj);
         g2n.add(Bij, r[i], r[j], r[i]);
         g2n.term(c.M.PhiU[i], r[i], Mt, ki, ki);
       }
@@ -227,7 +229,7 @@ void spdhss_build_impl(H2Model& H, const spd_hss_opts& o, HSSModel& M, hipStream
     F.S[0] = F.arena.get_n<double>((size_t)N * N);
     BlockBatch cp;
     cp.add(F.S[0], (int)N, (int)N, (int)N);
-    cp.term(H.nearA[T.near_ptr[0]], (int)N);
+    cp.term(H.nearA[T.near_ptr[0]], std::max(H.near_ld(0), 16));
     cp.run(s, c.st);
     std::vector<CholProblem> ch{{F.S[0], (int)N, (int)N}};
     launch_fill(s, (double*)d_fail, 0.0, (nn + 1) / 2);
@@ -271,7 +273,7 @@ void spdhss_build_impl(H2Model& H, const spd_hss_opts& o, HSSModel& M, hipStream
         g.add(slot, hk[v], S, hk[v]);
         for (int64_t e : kv.second) {
           const int j = T.coup_idx[e];
-          g.term(H.Bh[e], hk[v], H.hat(xh, j, S), H.hat_ld(j), hk[j]);
+          g.term(H.Bh[e], H.coup_ld(v), H.hat(xh, j, S), H.hat_ld(j), hk[j]);
         }
       }
     }
@@ -316,7 +318,7 @@ void spdhss_build_impl(H2Model& H, const spd_hss_opts& o, HSSModel& M, hipStream
         g.add(slot, nv, S, std::max(nv, 1));
         for (int64_t e : kv.second) {
           const int j = T.near_idx[e];
-          g.term(H.nearA[e], std::max(nv, 1), Om + T.start[j], (int)N, (int)T.size(j));
+          g.term(H.nearA[e], std::max(H.near_ld(v), 16), Om + T.start[j], (int)N, (int)T.size(j));
         }
       }
     }
@@ -340,7 +342,7 @@ void spdhss_build_impl(H2Model& H, const spd_hss_opts& o, HSSModel& M, hipStream
       F.rho[v] = nv;
       F.S[v] = F.arena.get_n<double>((size_t)std::max(nv * nv, 1));
       cp.add(F.S[v], nv, nv, std::max(nv, 1));
-      cp.term(H.nearA[T.near_pos(v, v)], std::max(nv, 1));
+      cp.term(H.nearA[T.near_pos(v, v)], std::max(H.near_ld(v), 16));
       ch.push_back({F.S[v], nv, std::max(nv, 1)});
       Psi[v] = lvl_tmp.get_n<double>((size_t)std::max(nv, 1) * S);
       y1.add(Psi[v], nv, S, std::max(nv, 1));

@@ -165,8 +165,14 @@ struct H2Model {
   // skeleton first) and E_v = R11^{-1} R12 (k_v x (cand_v - k_v)) and its transpose
   std::vector<int*> piv_d;
   std::vector<double*> E, ET;
-  std::vector<double*> Bh;        // per coupling entry: K(skel_i, skel_j), k_i x k_j
-  std::vector<double*> nearA;     // per leaf near entry: n_i x n_j, ld n_i
+  std::vector<double*> Bh;        // per coupling entry: K(skel_i, skel_j), k_i x k_j, ld coup_ld(i)
+  std::vector<double*> nearA;     // per leaf near entry: n_i x n_j, ld near_ld(i)
+  // Leading dimensions of the stored blocks: the rows rounded up to 16
+  // doubles, so that every column starts on a 128-byte line and a streamed
+  // column touches no partial line at its start (the pad rows hold zeros and
+  // are never read as data).
+  int coup_ld(int v) const { return (k[v] + 15) / 16 * 16; }
+  int near_ld(int v) const { return ((int)T.size(v) + 15) / 16 * 16; }
   // FP32 copies of the blocks the symmetric-pair product reads (coupling
   // entries j > i, near entries j >= i; null elsewhere), made on first use by
   // the mixed-precision product; each block row's copies are one allocation
