@@ -31,7 +31,8 @@
  *     level whose factorization failed).
  *   - Determinism: results are bitwise reproducible for identical inputs on
  *     the same device (no floating-point atomics).
- *   - Precision: all arithmetic is IEEE FP64.
+ *   - Precision: all arithmetic is IEEE FP64.  The *_ex entry points can keep
+ *     operators in FP32 (rounded once, widened to FP64 on every use).
  */
 #ifndef SPDHSS_H
 #define SPDHSS_H
