@@ -90,7 +90,9 @@ typedef struct {
 typedef struct {
   double tol;           /* relative CPQR threshold, 0 = fixed rank max_rank */
   int32_t max_rank;     /* rank cap r (>= 0; 0 gives block Jacobi) */
-  int32_t oversample;   /* p; Omega has max_rank + oversample columns */
+  int32_t oversample;   /* p; Omega has max_rank + oversample columns, at
+                           most 256 (above 128 the compression runs in the
+                           global-memory pivoted QR) */
   uint64_t seed;        /* seed of the internal Gaussian generator */
   const double* omega;  /* optional DEVICE N x (max_rank+oversample), column-
                            major, ld = N, ORIGINAL point order; NULL = internal

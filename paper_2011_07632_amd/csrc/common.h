@@ -139,6 +139,7 @@ struct CpqrProblem {
   int m, n, lda, ldq;
   int maxrank;
   double tol;
+  double* hbeta;    // global variant with Q: out, Householder factors (maxrank); else null
 };
 
 // ----------------------------------------------------------- launchers --
@@ -178,6 +179,10 @@ void launch_trsm(hipStream_t s, const TrsmProblem* d_p, int nprob, int max_n,
                  int max_nrhs, int trans, int upper);
 void launch_cpqr_reg(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_m,
                      int max_n);
+// After launch_cpqr_glob on problems with V (m x maxrank, ld m) and hbeta set:
+// Q's first rank columns from the stored Householder vectors, the signs
+// making R's diagonal non-negative (as the register kernel's Q).
+void launch_cpqr_formq(hipStream_t s, const CpqrProblem* d_p, int nprob);
 void launch_cpqr_glob(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_m,
                       int max_n);
 bool cpqr_reg_fits(int m, int n);

@@ -183,7 +183,7 @@ void spdhss_build_impl(H2Model& H, const spd_hss_opts& o, HSSModel& M, hipStream
   const int64_t N = T.N;
   const int S = o.max_rank + o.oversample;
   SPD_REQUIRE(o.max_rank >= 0 && o.oversample >= 0 && S >= 1, SPD_E_INVALID, "bad rank options");
-  SPD_REQUIRE(S <= 128, SPD_E_INVALID, "max_rank + oversample must not exceed 128");
+  SPD_REQUIRE(S <= 256, SPD_E_INVALID, "max_rank + oversample must not exceed 256");
   SPD_REQUIRE(o.tol >= 0.0, SPD_E_INVALID, "negative tolerance");
   M.opts = o;
   M.opts.omega = nullptr;
@@ -370,6 +370,10 @@ void spdhss_build_impl(H2Model& H, const spd_hss_opts& o, HSSModel& M, hipStream
   const double t_leaf_scale = now_seconds();
 
   // compress the samples of one level; returns ranks on the host
+  // More than 128 samples (r_max + p > 128) exceed the register-resident
+  // kernel; the global-memory kernel then factors the samples in place
+  // (they are not needed afterwards) and a second launch forms Q.
+  const bool glob = S > 128;
   auto compress = [&](const std::vector<int>& nodes) {
     std::vector<CpqrProblem> cq;
     Arena wk;
@@ -379,7 +383,8 @@ void spdhss_build_impl(H2Model& H, const spd_hss_opts& o, HSSModel& M, hipStream
       const int m = F.rho[v];
       const int mr = std::min(std::min(m, S), o.max_rank);
       F.V[v] = F.arena.get_n<double>((size_t)std::max(m * mr, 1));
-      M.piv[v] = out.get_n<int>(std::max(mr, 1));
+      // the global kernel writes the whole column order (S entries)
+      M.piv[v] = out.get_n<int>(std::max(glob ? S : mr, 1));
       CpqrProblem p{};
       p.A = Psi[v];
       p.Q = F.V[v];
@@ -392,12 +397,19 @@ void spdhss_build_impl(H2Model& H, const spd_hss_opts& o, HSSModel& M, hipStream
       p.ldq = std::max(m, 1);
       p.maxrank = mr;
       p.tol = o.tol;
+      if (glob) p.hbeta = wk.get_n<double>((size_t)std::max(mr, 1));
       cq.push_back(p);
       mm = std::max(mm, m);
-      SPD_REQUIRE(cpqr_reg_fits(m, S), SPD_E_INVALID, "basis rows exceed 512");
+      if (glob) SPD_REQUIRE(m <= 2048, SPD_E_INVALID, "basis rows exceed 2048");
+      else SPD_REQUIRE(cpqr_reg_fits(m, S), SPD_E_INVALID, "basis rows exceed 512");
     }
     auto* d = (const CpqrProblem*)c.st.push(s, cq.data(), cq.size() * sizeof(CpqrProblem));
-    launch_cpqr_reg(s, d, (int)cq.size(), mm, S);
+    if (glob) {
+      launch_cpqr_glob(s, d, (int)cq.size(), mm, S);
+      launch_cpqr_formq(s, d, (int)cq.size());
+    } else {
+      launch_cpqr_reg(s, d, (int)cq.size(), mm, S);
+    }
     std::vector<int> rk(nodes.size());
     SPD_HIP(hipMemcpyAsync(rk.data(), d_rank, rk.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     c.sync();

@@ -1321,8 +1321,11 @@ __global__ __launch_bounds__(1024) void k_cpqr_glob(const CpqrProblem* __restric
         if (row < m && row >= t) v = (row == t) ? xt - alpha : A[row + bi * lda];
         vbuf[row] = v;
         if (row < m && row >= t) A[row + bi * lda] = (row == t) ? alpha : 0.0;
+        // keep the reflector for Q (rows above t are zero)
+        if (P.hbeta && row < m) P.V[row + (int64_t)t * m] = v;
       }
       if (lane == 0) {
+        if (P.hbeta) P.hbeta[t] = beta;
         sh_beta = beta;
         P.piv[t] = bi;
         if (P.diag) P.diag[t] = nrm;
@@ -1375,6 +1378,49 @@ __global__ __launch_bounds__(1024) void k_cpqr_glob(const CpqrProblem* __restric
     }
   }
   (void)nrm_ws;
+}
+
+// Q = H_0 H_1 ... H_{rank-1} [I; 0] by backward accumulation: start from the
+// first rank columns of the identity and apply H_t = I - beta_t v_t v_t^T for
+// t = rank-1 down to 0 (it touches rows >= t of columns >= t only); then flip
+// column c where R_cc (the in-place alpha of the global kernel) is negative.
+// One 1024-thread workgroup per problem, a wave per column.
+__global__ __launch_bounds__(1024) void k_cpqr_formq(const CpqrProblem* __restrict__ probs) {
+  constexpr int NW = 16;
+  const CpqrProblem P = probs[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = P.m, rank = *P.rank;
+  const int64_t ldq = P.ldq;
+  double* Q = P.Q;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * rank; e += blockDim.x) {
+    const int i = (int)(e % m), c = (int)(e / m);
+    Q[i + c * ldq] = (i == c) ? 1.0 : 0.0;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int t = rank - 1; t >= 0; --t) {
+    const double beta = P.hbeta[t];
+    const double* v = P.V + (int64_t)t * m;
+    for (int c = t + w; c < rank; c += NW) {
+      double d = 0.0;
+      for (int i = t + lane; i < m; i += 64) d += v[i] * Q[i + c * ldq];
+      d = wave_sum(d);
+      for (int i = t + lane; i < m; i += 64) Q[i + c * ldq] -= beta * d * v[i];
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  for (int c = w; c < rank; c += NW) {
+    const double rcc = P.A[c + (int64_t)P.piv[c] * P.lda];
+    if (rcc < 0.0)
+      for (int i = lane; i < m; i += 64) Q[i + c * ldq] = -Q[i + c * ldq];
+  }
+}
+
+void launch_cpqr_formq(hipStream_t s, const CpqrProblem* d_p, int nprob) {
+  if (nprob <= 0) return;
+  hipLaunchKernelGGL(k_cpqr_formq, dim3(nprob), dim3(1024), 0, s, d_p);
+  SPD_HIP(hipGetLastError());
 }
 
 void launch_cpqr_glob(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_m, int max_n) {

@@ -124,8 +124,8 @@ def test_argument_errors(B):
     with pytest.raises(B.SpdError):
         B.h2_build(X, "gaussian", -0.5, 1e-2)
     h2 = B.h2_build(X, "gaussian", 0.5, 1e-2, leaf=32)
-    with pytest.raises(B.SpdError):
-        B.spdhss_build(h2, 1e-2, max_rank=120, oversample=10)
+    with pytest.raises(B.SpdError):  # more than 256 samples
+        B.spdhss_build(h2, 1e-2, max_rank=250, oversample=10)
     hss = B.spdhss_build(h2, 1e-2, max_rank=20, oversample=10)
     ulv = B.ulv_factor(hss)
     b = B.cols_like(200, 1, "cuda").fill_(1.0)
