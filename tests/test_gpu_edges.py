@@ -131,3 +131,21 @@ def test_argument_errors(B):
     b = B.cols_like(200, 1, "cuda").fill_(1.0)
     with pytest.raises(B.SpdError):
         B.pcg_solve(h2, ulv, b, rtol=-1.0, maxit=10)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_tiny_problems(B, n):
+    """N = 1, 2, 3 points: one leaf, the matrix is dense K + sigma I; the
+    product, the HSS solve and PCG must reproduce it exactly up to rounding."""
+    w = workloads.SMALL.with_(name=f"gaussian-l0.5-N{n}", n=n)
+    X = w.points()
+    A = okern.evaluate(w.kernel, w.ell, X, X) + w.shift * np.eye(n)
+    h2 = B.h2_build(torch.from_numpy(X).cuda(), w.kernel, w.ell, w.shift, leaf=64, tol=w.h2_tol)
+    assert h2.levels == 1
+    x = workloads.gaussian_matrix(n, 2, 5)
+    assert rel(B.h2_matvec(h2, cols(B, x)).cpu().numpy(), A @ x) <= 1e-14
+    ulv = B.ulv_factor(B.spdhss_build(h2, w.hss_tol, 2, 1, omega=cols(B, workloads.gaussian_matrix(n, 3, 6))))
+    assert rel(B.ulv_apply(ulv, cols(B, x)).cpu().numpy(), np.linalg.solve(A, x)) <= 1e-12
+    sol, it, res = B.pcg_solve(h2, ulv, cols(B, x), rtol=1e-12, maxit=10)
+    assert rel(sol.cpu().numpy(), np.linalg.solve(A, x)) <= 1e-12
+    assert it.tolist() == [1, 1]
