@@ -62,9 +62,15 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem* __restrict__ pr
   constexpr int BK = 16;
   constexpr int NWM = BM / WM;
   constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int LA = BM * BK / 256, LB = BK * BN / 256;  // elements each thread stages
   static_assert((BM / WM) * (BN / WN) == 4, "four waves");
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
+  static_assert(LA * 256 == BM * BK && LB * 256 == BK * BN, "whole tiles per thread");
+  // Two LDS buffers: the (term, k) step after the current one is fetched into
+  // registers while the current one is multiplied, then stored into the other
+  // buffer, so one barrier per step separates the two.  Steps run in the same
+  // order as a single-buffered loop, so the sums are the same bit for bit.
+  __shared__ double As[2][BK][BM + 1];
+  __shared__ double Bs[2][BK][BN + 1];
   const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
   const GemmProblem P = probs[p];
   const int tm = (P.m + BM - 1) / BM, tn = (P.n + BN - 1) / BN;
@@ -78,46 +84,92 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem* __restrict__ pr
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int t = P.term_begin; t < P.term_end; ++t) {
-    const GemmTerm T = terms[t];
-    for (int k0 = 0; k0 < T.k; k0 += BK) {
+  // the (term, k0) steps in order; t == term_end marks the end
+  int t = P.term_begin, k0 = 0;
+  while (t < P.term_end && terms[t].k <= 0) ++t;
+  if (t >= P.term_end) goto store;
+  {
+    double ra[LA], rb[LB];
+    auto fetch = [&](int tt, int kk0) {
+      const GemmTerm T = terms[tt];
 #pragma unroll
-      for (int e = tid; e < BM * BK; e += 256) {
+      for (int q = 0; q < LA; ++q) {
+        const int e = tid + 256 * q;
         int i, kk;
         if (!transA) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
-        const int gi = i0 + i, gk = k0 + kk;
+        const int gi = i0 + i, gk = kk0 + kk;
         double v = 0.0;
         if (gi < P.m && gk < T.k)
           v = T.scale * (transA ? T.A[gk + (int64_t)gi * T.lda] : T.A[gi + (int64_t)gk * T.lda]);
-        As[kk][i] = v;
+        ra[q] = v;
       }
 #pragma unroll
-      for (int e = tid; e < BK * BN; e += 256) {
+      for (int q = 0; q < LB; ++q) {
+        const int e = tid + 256 * q;
         int j, kk;
         if (!transB) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
-        const int gj = j0 + j, gk = k0 + kk;
+        const int gj = j0 + j, gk = kk0 + kk;
         double v = 0.0;
         if (gj < P.n && gk < T.k)
           v = transB ? T.B[gj + (int64_t)gk * T.ldb] : T.B[gk + (int64_t)gj * T.ldb];
-        Bs[kk][j] = v;
+        rb[q] = v;
       }
-      __syncthreads();
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        const int e = tid + 256 * q;
+        int i, kk;
+        if (!transA) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
+        As[buf][kk][i] = ra[q];
+      }
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int e = tid + 256 * q;
+        int j, kk;
+        if (!transB) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
+        Bs[buf][kk][j] = rb[q];
+      }
+    };
+    auto advance = [&](int& tt, int& kk0) {
+      kk0 += BK;
+      if (kk0 >= terms[tt].k) {
+        kk0 = 0;
+        ++tt;
+        while (tt < P.term_end && terms[tt].k <= 0) ++tt;
+      }
+    };
+    fetch(t, k0);
+    stash(0);
+    __syncthreads();
+    int cur = 0;
+    for (;;) {
+      int tn_ = t, kn = k0;
+      advance(tn_, kn);
+      const bool more = tn_ < P.term_end;
+      if (more) fetch(tn_, kn);
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 4) {
         double af[FM], bf[FN];
 #pragma unroll
-        for (int a = 0; a < FM; ++a) af[a] = As[ks + (lane >> 4)][wm * WM + a * 16 + (lane & 15)];
+        for (int a = 0; a < FM; ++a) af[a] = As[cur][ks + (lane >> 4)][wm * WM + a * 16 + (lane & 15)];
 #pragma unroll
-        for (int b = 0; b < FN; ++b) bf[b] = Bs[ks + (lane >> 4)][wn * WN + b * 16 + (lane & 15)];
+        for (int b = 0; b < FN; ++b) bf[b] = Bs[cur][ks + (lane >> 4)][wn * WN + b * 16 + (lane & 15)];
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
           for (int b = 0; b < FN; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
       }
+      if (!more) break;
+      stash(cur ^ 1);
       __syncthreads();
+      cur ^= 1;
+      t = tn_;
+      k0 = kn;
     }
   }
+store:
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
