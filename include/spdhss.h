@@ -29,6 +29,10 @@
  *     across the ABI.  On failure *out is set to NULL and spd_last_error()
  *     returns a thread-local message (for SPD_E_NOT_SPD it names the node and
  *     level whose factorization failed).
+ *   - Threads: a handle keeps per-call workspace (product plans, staging
+ *     vectors) and the stream of its last call, so one handle serves one call
+ *     at a time; calls on distinct handles may run concurrently from
+ *     different host threads (the device memory pool is locked).
  *   - Determinism: results are bitwise reproducible for identical inputs on
  *     the same device (no floating-point atomics).
  *   - Precision: all arithmetic is IEEE FP64.  The *_ex entry points can keep
