@@ -314,11 +314,13 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
 
 // ------------------------------------------------------------- product --
 // Workgroups of the near-field product when it runs beside the far-field
-// chain (two per CU): few enough to leave the latency-bound level passes
-// room.  Measured on the N = 100k Matern workload: 64 -> 2.67, 128 -> 2.01,
-// 256 -> 1.979, 512 -> 1.975, 1024 -> 1.994 ms per PCG iteration, against
-// 1.997 uncapped.
-static constexpr int kNearCap = 512;
+// chain: few enough to leave the latency-bound level passes room.  With
+// 512 leaves each workgroup takes one or two leaf rows.  Measured on the
+// N = 100k Matern workload (ms per PCG iteration, 1,934 iterations in every
+// case, since the cap only changes which workgroup takes which row):
+// 128 -> 1.976, 256 -> 1.941, 320 -> 1.935, 352 -> 1.931, 384 -> 1.927,
+// 416 -> 1.924, 448 -> 1.929, 512 (one row per workgroup) -> 1.939.
+static constexpr int kNearCap = 416;
 
 // FP32 copies of the blocks that the symmetric-pair product reads.
 static void make_f32_blocks(H2Model& H) {
