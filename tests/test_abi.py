@@ -14,13 +14,14 @@ LIB = os.path.join(ROOT, "paper_2011_07632_amd", "libspdhss.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:spd_status|void|const char\*)\s+([a-z_0-9]+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:spd_status|void|const char\*|int64_t)\s+([a-z_0-9]+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for fn in ("h2_build", "spdhss_build", "ulv_factor", "ulv_apply", "h2_matvec", "pcg_solve"):
+    for fn in ("h2_build", "spdhss_build", "ulv_factor", "ulv_apply", "h2_matvec", "pcg_solve",
+               "spd_request_footprint", "spd_last_error", "h2_destroy"):
         assert fn in names
 
 
@@ -41,3 +42,81 @@ def test_binding_rejects_bad_arguments_without_a_device():
     code = B.lib.spdhss_build(None, None, None, ctypes.byref(out))
     assert code == B.SPD_E_INVALID and out.value is None
     assert b"null" in B.lib.spd_last_error()
+
+
+# A stand-in device address: every call below fails its argument checks first,
+# so the address is never dereferenced and no device is touched.
+FAKE = ctypes.c_void_p(0x1000)
+
+
+def _h2_args(**kw):
+    from paper_2011_07632_amd import binding as B
+    k = dict(kind=1, ell=0.1, shift=1e-4)
+    o = dict(leaf_size=64, eta=1.0, tol=1e-8, proxy_shells=8, proxy_per_shell=128)
+    for key, v in kw.items():
+        (k if key in k else o)[key] = v
+    return B._Kernel(**k), B._H2Opts(**o)
+
+
+@pytest.mark.parametrize("n,bad,msg", [
+    (0, {}, b"n must be positive"),
+    (1 << 31, {}, b"below 2^31"),
+    (100, {"kind": 4}, b"unknown kernel"),
+    (100, {"ell": 0.0}, b"ell"),
+    (100, {"ell": float("nan")}, b"ell"),
+    (100, {"shift": float("inf")}, b"shift"),
+    (100, {"leaf_size": 0}, b"leaf_size"),
+    (100, {"leaf_size": 513}, b"leaf_size"),
+    (100, {"eta": 0.0}, b"eta"),
+    (100, {"tol": 1.0}, b"tol"),
+    (100, {"proxy_shells": 0}, b"proxy"),
+    (100, {"proxy_shells": 17, "proxy_per_shell": 128}, b"2048 proxy"),
+])
+def test_h2_build_argument_checks(n, bad, msg):
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_2011_07632_amd import binding as B
+    k, o = _h2_args(**bad)
+    out = ctypes.c_void_p(0x1)
+    code = B.lib.h2_build(FAKE, n, k, ctypes.byref(o), None, ctypes.byref(out))
+    assert code == B.SPD_E_INVALID
+    assert out.value is None  # *out is cleared on failure
+    assert msg in B.lib.spd_last_error()
+
+
+def test_null_handles_are_rejected():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_2011_07632_amd import binding as B
+    L, out = B.lib, ctypes.c_void_p()
+    assert L.ulv_factor(None, None, ctypes.byref(out)) == B.SPD_E_INVALID
+    assert L.ulv_apply(None, FAKE, FAKE, 1, 10, None) == B.SPD_E_INVALID
+    assert L.h2_matvec(None, FAKE, FAKE, 1, 10, None) == B.SPD_E_INVALID
+    assert L.pcg_solve(None, None, FAKE, FAKE, 1, 10, 1e-8, 10, None, None, None) == B.SPD_E_INVALID
+    assert L.spd_h2_query_get(None, 0, FAKE, 8) == B.SPD_E_INVALID
+    assert L.spd_hss_query_get(None, 0, 0, 0, FAKE, 8) == B.SPD_E_INVALID
+    L.h2_destroy(None)  # destroying a null handle is a no-op
+    L.spdhss_destroy(None)
+    L.ulv_destroy(None)
+
+
+def test_server_and_footprint_host_checks():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_2011_07632_amd import binding as B
+    L, out = B.lib, ctypes.c_void_p(0x1)
+    assert L.spd_server_create(0, 1 << 30, ctypes.byref(out)) == B.SPD_E_INVALID
+    assert out.value is None
+    assert L.spd_server_create(2, 0, ctypes.byref(out)) == B.SPD_E_INVALID
+    assert L.spd_request_footprint(None) == 0
+    k, o = _h2_args()
+    q = B._Instance(n=10_000, kernel=k, h2=o, hss=B._HSSOpts(tol=1e-2, max_rank=100, oversample=10), nrhs=1)
+    f1 = L.spd_request_footprint(ctypes.byref(q))
+    q.n = 20_000
+    f2 = L.spd_request_footprint(ctypes.byref(q))
+    q.nrhs = 32
+    f3 = L.spd_request_footprint(ctypes.byref(q))
+    # at least the points and the near blocks; linear in N; grows with the right-hand sides
+    assert f1 >= 24 * 10_000 + 8 * 10_000 * 64
+    assert f2 == pytest.approx(2 * f1, rel=1e-9)
+    assert f3 > f2
