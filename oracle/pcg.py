@@ -1,4 +1,4 @@
-"""Preconditioned conjugate gradients and the matvec-error metric (oracle).
+"""Preconditioned conjugate gradients and the matvec-error metric (oracle; test infrastructure only).
 
 Section 6 solves the kernel systems with PCG preconditioned by the SPD HSS
 approximation, random right-hand sides, and a relative-residual stopping
