@@ -323,7 +323,7 @@ def main():
         _, it, res = P.pcg_solve(h2, ulv, b, rtol=w.pcg_tol, maxit=args.maxit, out=x, op_precision=op)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        step.ulv = ulv
+        step.ulv, step.hss = ulv, hss
         return t1 - t0, t2 - t1, it, res
 
     for i in range(args.warmup):
@@ -342,6 +342,15 @@ def main():
     wall = time.perf_counter() - t0
     ms = 1e3 * wall / args.steps
     ulv64 = step.ulv
+    # HSS ranks per tree level (leaves are level 1, as in the paper) and how
+    # many nodes reached the rank cap, from the last timed step
+    r = step.hss.ranks()
+    depth = np.floor(np.log2(np.arange(1, len(r) + 1))).astype(int)
+    top = int(depth.max())
+    hss_ranks = {"by_level_min_mean_max": {str(top + 1 - d): [int(r[depth == d].min()), round(float(r[depth == d].mean()), 1),
+                                                             int(r[depth == d].max())] for d in range(top, 0, -1)},
+                 "max_rank": w.max_rank, "rank_cap_hits": int((r[1:] >= w.max_rank).sum()), "nodes": int(len(r) - 1)}
+    step.hss = None
 
     # mixed-precision forms, one step each beside the plain form (not part of
     # `value`): the FP32-block product inside PCG with FP64 residual
@@ -417,6 +426,7 @@ def main():
         "relres_max": float(res.max()),
         "h2_build_s": round(t_h2, 3),
         "h2_rel_err_sampled": float(f"{h2_err:.3e}"),
+        "hss_ranks": hss_ranks,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": mixed,
