@@ -39,3 +39,34 @@ def test_gaussian_matrix_is_column_major():
     g = workloads.gaussian_matrix(100, 3, 9)
     assert g.shape == (100, 3) and g.flags.f_contiguous
     assert np.array_equal(g, workloads.gaussian_matrix(100, 3, 9))
+
+
+def test_batch_recipe():
+    inst = workloads.batch_instances()
+    assert len(inst) == 64
+    ns = np.array([w.n for w in inst])
+    assert ns.min() >= 5000 and ns.max() <= 50000
+    # log-uniform: the median sits near the geometric mean of the range
+    assert abs(np.log(np.median(ns)) - 0.5 * (np.log(5000) + np.log(50000))) < 0.35
+    assert [w.point_set for w in inst] == ["cube", "sphere"] * 32
+    assert {(w.kernel, w.ell) for w in inst} == set(workloads.BATCH_KERNELS)
+    for w in inst:
+        assert (w.shift, w.leaf, w.hss_tol, w.max_rank, w.oversample, w.nrhs, w.pcg_tol) == \
+            (1e-3, 128, 1e-2, 100, 10, 4, 1e-8)
+    assert len({w.seed_base for w in inst}) == 64  # every instance draws its own data
+    assert [w.name for w in workloads.batch_instances()] == [w.name for w in inst]  # seeded
+
+
+def test_serve_recipe():
+    reqs = workloads.serve_requests()
+    assert len(reqs) == 64
+    t = np.array([a for a, _ in reqs])
+    assert np.all(np.diff(t) > 0)
+    # Poisson arrivals at 20/s: 64 exponential gaps with mean 0.05 s
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert 0.03 < gaps.mean() < 0.07 and gaps.std() / gaps.mean() > 0.6
+    ws = [w for _, w in reqs]
+    assert all(10_000 <= w.n <= 100_000 and w.point_set == "cube" for w in ws)
+    assert {w.kernel for w in ws} == set(workloads.SERVE_KERNELS)
+    assert all(0.05 <= w.ell <= 0.5 and 1 <= w.nrhs <= 32 for w in ws)
+    assert all((w.shift, w.leaf, w.pcg_tol) == (1e-3, 400, 1e-8) for w in ws)
