@@ -56,3 +56,14 @@ def test_traffic_only_for_the_recorded_sources(tmp_path, monkeypatch):
     p = t / bench.KERNEL_SOURCES[0]
     p.write_bytes(p.read_bytes() + b"// changed\n")
     assert bench.recorded_traffic(w, "coupling") is None  # sources changed since the counters
+
+
+def test_default_workload_is_the_100k_matern_configuration():
+    # the metric's configuration: 100,000 uniform cube points, Matern-3/2 with
+    # l = 0.1 plus 1e-4 I, leaf 200, H^2 tolerance 1e-8, HSS tolerance 1e-2,
+    # one N(0,1) right-hand side, PCG to 1e-8
+    w = bench.workloads.MEDIUM
+    assert (w.n, w.point_set, w.kernel, w.ell, w.shift, w.leaf, w.h2_tol, w.hss_tol, w.nrhs, w.pcg_tol) == \
+        (100_000, "cube", "matern32", 0.1, 1e-4, 200, 1e-8, 1e-2, 1, 1e-8)
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    assert 'ap.add_argument("--workload", default=workloads.MEDIUM.name' in src
