@@ -133,14 +133,32 @@ def _as_cols(t: torch.Tensor, n: int) -> tuple[torch.Tensor, int, int]:
         if t.shape[0] != n or t.stride(0) != 1:
             raise ValueError("vector length / stride mismatch")
         return t, 1, n
-    if t.dim() != 2 or t.shape[0] != n or t.stride(0) != 1 or t.stride(1) < n:
+    if t.dim() != 2 or t.shape[0] != n or t.stride(0) != 1:
         raise ValueError("expected an (N, ncols) column-major tensor")
-    return t, t.shape[1], t.stride(1)
+    ncols = t.shape[1]
+    ld = t.stride(1) if ncols > 1 else n  # one column: its stride is never used
+    if ld < n:
+        raise ValueError("expected an (N, ncols) column-major tensor")
+    return t, ncols, ld
 
 
 def cols_like(n: int, ncols: int, device) -> torch.Tensor:
     """An uninitialised (n, ncols) column-major FP64 device tensor."""
     return torch.empty((ncols, n), dtype=torch.float64, device=device).t()
+
+
+def _out_like(t: torch.Tensor, n: int, ncols: int, ld: int) -> torch.Tensor:
+    """An output block with the input's layout: the C ABI takes one leading
+    dimension for the input and the output."""
+    if t.dim() == 1:
+        return torch.empty_like(t)
+    return torch.empty((ncols, ld), dtype=torch.float64, device=t.device).t()[:n]
+
+
+def _check_out(out: torch.Tensor, n: int, ncols: int, ld: int) -> None:
+    _, nc2, ld2 = _as_cols(out, n)
+    if nc2 != ncols or ld2 != ld:
+        raise ValueError("output shape / leading dimension must match the input")
 
 
 class H2Matrix:
@@ -330,10 +348,8 @@ def ulv_factor(M: HSSMatrix, stream=None, precision: str = "f64") -> ULVFactor:
 def ulv_apply(F: ULVFactor, b: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     b, nc, ld = _as_cols(b, F.n)
     if out is None:
-        out = cols_like(F.n, nc, b.device) if b.dim() == 2 else torch.empty_like(b)
-    out_, nc2, ld2 = _as_cols(out, F.n)
-    if nc2 != nc or ld2 != ld:
-        raise ValueError("output shape / leading dimension must match the input")
+        out = _out_like(b, F.n, nc, ld)
+    _check_out(out, F.n, nc, ld)
     _check(lib.ulv_apply(F._h, b.data_ptr(), out.data_ptr(), nc, ld, _stream(stream)))
     return out
 
@@ -344,10 +360,8 @@ def h2_matvec(A: H2Matrix, x: torch.Tensor, out: torch.Tensor | None = None, str
     blocks (at most 4 columns, FP64 accumulation)."""
     x, nc, ld = _as_cols(x, A.n)
     if out is None:
-        out = cols_like(A.n, nc, x.device) if x.dim() == 2 else torch.empty_like(x)
-    out_, nc2, ld2 = _as_cols(out, A.n)
-    if nc2 != nc or ld2 != ld:
-        raise ValueError("output shape / leading dimension must match the input")
+        out = _out_like(x, A.n, nc, ld)
+    _check_out(out, A.n, nc, ld)
     _check(lib.h2_matvec_ex(A._h, x.data_ptr(), out.data_ptr(), nc, ld, SOLVE_PRECISION[precision],
                             _stream(stream)))
     return out
@@ -361,8 +375,8 @@ def pcg_solve(A: H2Matrix, M: ULVFactor | None, b: torch.Tensor, rtol: float = 1
     residual replacement by the FP64 product (at most 4 columns)."""
     b, nc, ld = _as_cols(b, A.n)
     if out is None:
-        out = cols_like(A.n, nc, b.device) if b.dim() == 2 else torch.empty_like(b)
-    _as_cols(out, A.n)
+        out = _out_like(b, A.n, nc, ld)
+    _check_out(out, A.n, nc, ld)
     iters = np.zeros(nc, dtype=np.int32)
     relres = np.zeros(nc, dtype=np.float64)
     code = lib.pcg_solve_ex(A._h, None if M is None else M._h, b.data_ptr(), out.data_ptr(), nc, ld,

@@ -120,3 +120,54 @@ def test_server_and_footprint_host_checks():
     assert f1 >= 24 * 10_000 + 8 * 10_000 * 64
     assert f2 == pytest.approx(2 * f1, rel=1e-9)
     assert f3 > f2
+
+
+class _FakeCols:
+    """Duck-typed stand-in for a float64 device tensor (shape and strides only)."""
+
+    def __init__(self, shape, strides):
+        import torch
+        self.is_cuda, self.dtype = True, torch.float64
+        self.shape, self._st = shape, strides
+
+    def dim(self):
+        return len(self.shape)
+
+    def stride(self, i):
+        return self._st[i]
+
+
+@pytest.mark.parametrize("shape,strides,want", [
+    ((10,), (1,), (1, 10)),
+    ((10, 1), (1, 1), (1, 10)),      # one column, e.g. x.unsqueeze(1): stride unused
+    ((10, 1), (1, 10), (1, 10)),
+    ((10, 3), (1, 10), (3, 10)),
+    ((10, 3), (1, 16), (3, 16)),     # padded leading dimension
+    ((10, 3), (3, 1), None),         # row-major
+    ((10, 3), (1, 8), None),         # overlapping columns
+    ((9, 3), (1, 10), None),         # wrong N
+    ((10,), (2,), None),             # strided vector
+])
+def test_binding_column_layouts(shape, strides, want):
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_2011_07632_amd import binding as B
+    t = _FakeCols(shape, strides)
+    if want is None:
+        with pytest.raises(ValueError):
+            B._as_cols(t, 10)
+    else:
+        assert B._as_cols(t, 10)[1:] == want
+
+
+def test_default_outputs_take_the_input_layout():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    import torch
+    from paper_2011_07632_amd import binding as B
+    v = torch.zeros(10, dtype=torch.float64)
+    assert B._out_like(v, 10, 1, 10).shape == (10,)
+    o = B._out_like(torch.zeros(3, 16, dtype=torch.float64).t()[:10], 10, 3, 16)
+    assert o.shape == (10, 3) and o.stride() == (1, 16)
+    o = B._out_like(torch.zeros(1, 10, dtype=torch.float64).t(), 10, 1, 10)
+    assert o.shape == (10, 1) and o.stride(0) == 1

@@ -149,3 +149,27 @@ def test_tiny_problems(B, n):
     sol, it, res = B.pcg_solve(h2, ulv, cols(B, x), rtol=1e-12, maxit=10)
     assert rel(sol.cpu().numpy(), np.linalg.solve(A, x)) <= 1e-12
     assert it.tolist() == [1, 1]
+
+
+def test_padded_leading_dimension(B):
+    """Right-hand sides with ld > N (columns of a taller buffer): the default
+    outputs take the same layout, and product, apply and PCG give the same
+    results bit for bit as with ld = N."""
+    w = workloads.SMALL.with_(n=700)
+    X = torch.from_numpy(w.points()).cuda()
+    h2 = B.h2_build(X, w.kernel, w.ell, w.shift, leaf=64, tol=w.h2_tol)
+    ulv = B.ulv_factor(B.spdhss_build(h2, w.hss_tol, 20, 10))
+    x = workloads.gaussian_matrix(w.n, 3, 71)
+    ld = w.n + 7
+    print(f"[edges] padded ld = {ld}, N = {w.n}, 3 columns", flush=True)
+    big = torch.full((3, ld), float("nan"), dtype=torch.float64, device="cuda")
+    xp = big.t()[:w.n]
+    xp.copy_(torch.from_numpy(x))
+    xc = cols(B, x)
+    for f in (lambda v: B.h2_matvec(h2, v), lambda v: B.ulv_apply(ulv, v),
+              lambda v: B.pcg_solve(h2, ulv, v, rtol=1e-8, maxit=200, raise_on_nonconvergence=False)[0]):
+        yp, yc = f(xp), f(xc)
+        assert yp.stride() == (1, ld) and yc.stride() == (1, w.n)
+        assert torch.equal(yp, yc)
+    with pytest.raises(ValueError):  # an output whose layout differs from the input's
+        B.pcg_solve(h2, ulv, xp, out=B.cols_like(w.n, 3, "cuda"))
