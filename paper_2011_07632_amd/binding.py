@@ -444,12 +444,19 @@ def test_cpqr(A, Q, piv, rank, diag, maxrank, tol, which):
 
 def _fill_instance(I: _Instance, d: dict):
     """Fill a request descriptor from a dict; returns the objects it points to."""
-    P = d["points"].contiguous()
+    P = d["points"]
+    if not P.is_cuda or P.dtype != torch.float64 or P.dim() != 2 or P.shape[1] != 3:
+        raise ValueError("points must be an (N, 3) float64 device tensor")
+    P = P.contiguous()
     b, nc, ld = _as_cols(d["b"], P.shape[0])
     if ld != P.shape[0]:
         raise ValueError("b must have ld = N")
     x = cols_like(P.shape[0], nc, P.device)
     om = d.get("omega")
+    if om is not None:
+        om, nco, ldo = _as_cols(om, P.shape[0])
+        if nco != int(d["max_rank"]) + int(d["oversample"]) or ldo != P.shape[0]:
+            raise ValueError("omega must be (N, max_rank + oversample) with ld = N")
     it = np.zeros(nc, dtype=np.int32)
     rr = np.zeros(nc, dtype=np.float64)
     I.points, I.n = P.data_ptr(), P.shape[0]

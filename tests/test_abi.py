@@ -171,3 +171,15 @@ def test_default_outputs_take_the_input_layout():
     assert o.shape == (10, 3) and o.stride() == (1, 16)
     o = B._out_like(torch.zeros(1, 10, dtype=torch.float64).t(), 10, 1, 10)
     assert o.shape == (10, 1) and o.stride(0) == 1
+
+
+def test_request_points_are_checked_before_any_device_use():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    import torch
+    from paper_2011_07632_amd import binding as B
+    for pts in (torch.zeros(10, 3, dtype=torch.float64),   # host memory
+                torch.zeros(10, 3, dtype=torch.float32),
+                torch.zeros(10, 2, dtype=torch.float64)):
+        with pytest.raises(ValueError):
+            B._fill_instance(B._Instance(), {"points": pts})

@@ -54,3 +54,11 @@ def test_batch_equals_alone(B):
 def test_batch_argument_errors(B):
     with pytest.raises(B.SpdError):
         B.solve_batch([], workers=0)
+
+
+def test_request_omega_shape_is_checked(B):
+    w = workloads.batch_instances(count=1, n_lo=1500, n_hi=1600)[0]
+    r = request(B, w, "f64")
+    r["omega"] = B.cols_like(w.n, w.s - 1, "cuda").zero_()  # one column short
+    with pytest.raises(ValueError):
+        B.solve_batch([r], workers=1)
