@@ -179,9 +179,9 @@ class H2Matrix:
             self._h = None
 
     def _get(self, what: str, dtype, count: int) -> np.ndarray:
-        out = np.empty(count, dtype=dtype)
+        out = np.empty(max(count, 1), dtype=dtype)  # never a zero-size (possibly null) buffer
         _check(lib.spd_h2_query_get(self._h, Q[what], out.ctypes.data, out.nbytes))
-        return out
+        return out[:count]
 
     def scalar(self, what: str) -> int:
         return int(self._get(what, np.int64, 1)[0])
