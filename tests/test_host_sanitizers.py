@@ -1,7 +1,10 @@
-"""Host C++ of the library under AddressSanitizer and UndefinedBehaviorSanitizer
-(CPU): the partition tree and admissibility lists, checked for structure by
-tests/host/tree_check.cpp over several sizes and leaf sizes.  Only the host
-pass is instrumented (each -fsanitize follows -Xarch_host)."""
+"""Host-side checks of the library (CPU).
+
+The partition tree and admissibility lists run under AddressSanitizer and
+UndefinedBehaviorSanitizer, checked for structure by tests/host/tree_check.cpp
+over several sizes and leaf sizes; only the host pass is instrumented (each
+-fsanitize follows -Xarch_host).  tests/host/abi_c_check.c is a plain C99
+client of include/spdhss.h, linked against the library."""
 import os
 import subprocess
 
@@ -27,3 +30,18 @@ def test_tree_under_asan_ubsan(tmp_path):
     env = dict(os.environ, ASAN_OPTIONS="halt_on_error=1", UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
     assert r.returncode == 0 and "tree_check ok" in r.stdout, (r.stdout + r.stderr)[-3000:]
+
+
+def test_plain_c_client(tmp_path):
+    """include/spdhss.h is C99 and the library links and answers from C."""
+    lib_dir = os.path.join(ROOT, "paper_2011_07632_amd")
+    if not os.path.exists(os.path.join(lib_dir, "libspdhss.so")):
+        pytest.skip("library not built")
+    exe = str(tmp_path / "abi_c_check")
+    cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+           "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "host", "abi_c_check.c"),
+           "-L", lib_dir, "-lspdhss", f"-Wl,-rpath,{lib_dir}", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-3000:]
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "abi_c_check ok" in r.stdout, (r.stdout + r.stderr)[-3000:]
