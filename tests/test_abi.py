@@ -183,3 +183,14 @@ def test_request_points_are_checked_before_any_device_use():
                 torch.zeros(10, 2, dtype=torch.float64)):
         with pytest.raises(ValueError):
             B._fill_instance(B._Instance(), {"points": pts})
+
+
+def test_import_fails_loudly_without_the_library(tmp_path):
+    """No CPU fallback: without the built library the package does not import."""
+    import subprocess
+    import sys
+    env = dict(os.environ, SPDHSS_LIB=str(tmp_path / "missing" / "libspdhss.so"))
+    r = subprocess.run([sys.executable, "-c", "import paper_2011_07632_amd"], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "not built" in r.stderr
