@@ -194,3 +194,21 @@ def test_import_fails_loudly_without_the_library(tmp_path):
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "not built" in r.stderr
+
+
+def test_product_path_does_not_load_the_oracle():
+    """The oracle is test infrastructure: the package (and bench.py at import)
+    never import it, and no library source refers to it."""
+    import subprocess
+    import sys
+    code = ("import sys, paper_2011_07632_amd, bench; "
+            "bad = [m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')]; "
+            "assert not bad, bad")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    pkg = os.path.join(ROOT, "paper_2011_07632_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f), encoding="utf-8").read()
+                assert "import oracle" not in text and "from oracle" not in text, f
