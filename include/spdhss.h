@@ -277,7 +277,9 @@ spd_status spd_server_wait(spd_server_t S, int64_t ticket, int32_t block,
 /* Estimated device bytes of a request (the admission estimate). */
 int64_t spd_request_footprint(const spd_instance* request);
 
-/* Finishes every submitted request, then stops the workers. */
+/* Finishes every submitted request, then stops the workers and frees S.  No
+ * other call on S may run during it or follow it; results not yet collected
+ * with spd_server_wait are discarded. */
 void spd_server_destroy(spd_server_t S);
 
 /* Device memory released by destroyed handles is kept in a process-wide cache
