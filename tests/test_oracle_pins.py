@@ -283,6 +283,24 @@ def test_exact_limit_full_rank():
     assert it[0] <= 2 and res[0] <= 1e-8
 
 
+def test_largest_leaf_and_sample_count():
+    """At the library's largest leaf (512 points) and sample count (s = 256,
+    fixed rank 246): each leaf rank is min(r_max, rows, s), the diagonal
+    blocks are kept exactly, and the HSS matrix is SPD (Section 3.2), as its
+    dense eigenvalues show."""
+    h = small_h2(n=1024, leaf=512, kind="matern32", ell=0.3, shift=1e-3, seed=77)
+    T = h.tree
+    assert [T.size(v) for v in T.leaves()] == [512, 512]
+    om = workloads.gaussian_matrix(1024, 256, 5)[T.perm]
+    s = SPDHSS(h, om, 0.0, 246, "chol")
+    assert all(s.rank[v] == 246 for v in T.leaves())
+    D, A = s.dense(), h.dense()
+    for v in T.leaves():
+        assert np.array_equal(D[T.rng(v), T.rng(v)], A[T.rng(v), T.rng(v)])
+    assert np.linalg.eigvalsh(0.5 * (D + D.T)).min() > 0
+    assert np.linalg.norm(D - A) <= 1e-4 * np.linalg.norm(A)
+
+
 def test_block_jacobi_limit():
     """max_rank = 0 leaves A_hss = blockdiag(A_ii); PCG then follows
     block-Jacobi PCG step for step (compared with SciPy's CG)."""
