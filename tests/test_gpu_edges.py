@@ -173,3 +173,32 @@ def test_padded_leading_dimension(B):
         assert torch.equal(yp, yc)
     with pytest.raises(ValueError):  # an output whose layout differs from the input's
         B.pcg_solve(h2, ulv, xp, out=B.cols_like(w.n, 3, "cuda"))
+
+
+def test_largest_leaf_and_sample_count(B):
+    """The library's largest leaf (512 points) and sample count (s = 256 with
+    fixed rank 246, so the compression runs in the global-memory pivoted QR):
+    ranks and pivots equal the oracle's, and the product and the HSS solve
+    agree with it to 1e-10."""
+    w = workloads.SMALL.with_(name="matern32-l0.3-N1024-leaf512", n=1024, kernel="matern32", ell=0.3,
+                              shift=1e-3, leaf=512, max_rank=246, oversample=10, hss_tol=0.0, seed_base=12)
+    print(f"[edges] {w.name}: s = {w.s}", flush=True)
+    X = w.points()
+    h2 = B.h2_build(torch.from_numpy(X).cuda(), w.kernel, w.ell, w.shift, leaf=w.leaf, tol=w.h2_tol,
+                    proxy_shells=4, proxy_per_shell=64)
+    hss = B.spdhss_build(h2, w.hss_tol, w.max_rank, w.oversample, omega=cols(B, w.omega()))
+    o_h2 = OH2(X, w.kernel, w.ell, w.shift, w.leaf, w.h2_tol, shells=4, per_shell=64)
+    o_hss = OHSS(o_h2, w.omega()[o_h2.tree.perm], w.hss_tol, w.max_rank, "chol")
+    T = o_h2.tree
+    assert [T.size(v) for v in T.leaves()] == [512, 512]
+    r = hss.ranks()
+    for v in T.leaves():
+        assert r[v] == o_hss.rank[v] == 246
+        assert hss.pivots(v).tolist() == o_hss.piv[v].tolist()
+    x = workloads.gaussian_matrix(w.n, 2, 13)
+    yo = np.empty_like(x)
+    yo[T.perm] = o_h2.matvec(x[T.perm])
+    assert rel(B.h2_matvec(h2, cols(B, x)).cpu().numpy(), yo) <= 1e-10
+    xo = np.empty_like(x)
+    xo[T.perm] = o_hss.solve(x[T.perm])
+    assert rel(B.ulv_apply(B.ulv_factor(hss), cols(B, x)).cpu().numpy(), xo) <= 1e-10
