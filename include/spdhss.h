@@ -81,13 +81,30 @@ typedef struct {
 
 /* H^2 construction options (Section 5.1; construction method: proxy-point
  * interpolative decomposition, this library's choice since the paper does not
- * describe one). */
+ * describe one).
+ *
+ * Every node with a far field gets proxy_shells Fibonacci spheres centred at
+ * its box, from the nearest far box to the farthest root-box corner.  Each
+ * sphere has P_v = proxy_density * (rho_in / ell)^2 points (rho_in: radius of
+ * the innermost sphere), rounded up to a multiple of 64 and clamped to
+ * [proxy_per_shell, proxy_per_shell_max]; proxy_density = 0 keeps
+ * P_v = proxy_per_shell.  The densities resolve the kernel's length scale on
+ * the spheres of large boxes, without which the ID misses tol by orders of
+ * magnitude at the upper levels.  When the M = proxy_shells * P_v proxy rows
+ * exceed l = max(2c, c + 16) (c candidates), the proxy matrix is first
+ * multiplied by an M x l standard normal sketch (entry (t, j): SplitMix64 on
+ * the counter (t << 24) | j under sketch_seed, then Box-Muller), a randomized
+ * interpolative decomposition.  c may not exceed 4000 (SPD_E_INVALID). */
 typedef struct {
-  int32_t leaf_size;        /* max points per leaf of the binary kd-tree */
-  double eta;               /* admissibility: r_i + r_j <= eta * |c_i - c_j| */
-  double tol;               /* relative truncation of the ID (|R_tt| > tol |R_00|) */
-  int32_t proxy_shells;     /* proxy spheres per node (>= 1) */
-  int32_t proxy_per_shell;  /* Fibonacci points per sphere (>= 4) */
+  int32_t leaf_size;            /* max points per leaf of the binary kd-tree */
+  double eta;                   /* admissibility: r_i + r_j <= eta * |c_i - c_j| */
+  double tol;                   /* relative truncation of the ID (|R_tt| > tol |R_00|) */
+  int32_t proxy_shells;         /* proxy spheres per node, in [1, 64] */
+  int32_t proxy_per_shell;      /* minimum points per sphere (>= 4) */
+  int32_t proxy_per_shell_max;  /* maximum points per sphere (>= proxy_per_shell;
+                                   proxy_shells * maximum <= 65536) */
+  double proxy_density;         /* >= 0, see above */
+  uint64_t sketch_seed;         /* seed of the sketch's generator */
 } spd_h2_opts;
 
 /* SPD HSS construction options (Algorithm 5.3, Algorithm 5.1). */
@@ -310,7 +327,10 @@ typedef enum {
   SPD_Q_COUP_IDX = 9,     /* int32[..] */
   SPD_Q_NNODES = 10,      /* int64[1] */
   SPD_Q_BYTES = 11,       /* int64[1]: device bytes held by the handle */
-  SPD_Q_H2_TIMES = 12     /* double[4]: seconds for tree+lists, bases, blocks, total */
+  SPD_Q_H2_TIMES = 12,    /* double[4]: seconds for tree+lists, bases, blocks, total */
+  SPD_Q_PROXY_COUNT = 13, /* int32[nnodes]: points per proxy sphere (0: no ID ran) */
+  SPD_Q_H2_STORAGE = 14   /* int64[3]: bytes of the near blocks, coupling blocks and
+                             interpolation matrices (W_v, W_v^T, E_v, E_v^T) */
 } spd_h2_query;
 
 spd_status spd_h2_query_get(spd_h2_t A, int32_t what, void* host_out, int64_t bytes);

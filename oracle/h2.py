@@ -12,12 +12,22 @@ decomposition against proxy points, bottom-up):
 
 * candidates of a node: its points (leaf) or its children's skeletons,
   concatenated in child order (nonleaf);
-* proxy points: Q spheres of P points each (Fibonacci lattice), centred at the
-  node's box centre, at radii geometrically spaced from rho_in to rho_out, where
-  rho_in is the smallest distance from the centre to a box of the node's far
-  field (couplings of the node and all its ancestors) and rho_out the largest
-  distance from the centre to a corner of the root box;
-* G = K(X_cand, proxies); a column-pivoted QR of G^T with relative truncation
+* proxy points: Q spheres of P_v points each (Fibonacci lattice), centred at
+  the node's box centre, at radii geometrically spaced from rho_in to rho_out,
+  where rho_in is the smallest distance from the centre to a box of the node's
+  far field (couplings of the node and all its ancestors) and rho_out the
+  largest distance from the centre to a corner of the root box;
+* the number of points per sphere resolves the kernel's length scale on the
+  innermost sphere: P_v = density * (rho_in / ell)^2, rounded up to a multiple
+  of 64 and clamped to [per_shell, per_shell_max] (density = 0 keeps
+  P_v = per_shell).  A fixed count under-resolves the large boxes of the upper
+  levels, whose far field then misses the tolerance by orders of magnitude;
+* G = K(X_cand, proxies) (c x M).  When M exceeds l = max(2c, c + 16) it is
+  first sketched, S = G Omega with an M x l standard normal Omega from the
+  counter-based generator of oracle/rng.py (a randomized interpolative
+  decomposition: Liberty, Woolfe, Martinsson, Rokhlin and Tygert, PNAS 2007;
+  Halko, Martinsson and Tropp, SIAM Review 2011, Section 5.2); otherwise
+  S = G.  A column-pivoted QR of S^T with relative truncation
   |R_tt| > eps * |R_00| selects the skeleton; E = R11^{-1} R12;
 * the interpolation matrix W has identity rows at the skeleton and E^T rows
   elsewhere: U_i = W at a leaf, R_i = W at a nonleaf;
@@ -32,7 +42,7 @@ from __future__ import annotations
 import math
 import numpy as np
 
-from . import kernels
+from . import kernels, rng
 from .linalg import CPQR
 from .tree import Tree
 
@@ -46,18 +56,41 @@ def fibonacci_sphere(npts: int) -> np.ndarray:
     return np.stack([rho * np.cos(phi), rho * np.sin(phi), z], axis=1)
 
 
+def proxy_count(rin: float, ell: float, per_shell: int, per_shell_max: int,
+                density: float) -> int:
+    """Points per proxy sphere of a node whose innermost sphere has radius rin."""
+    if density <= 0.0:
+        return int(per_shell)
+    t = rin / ell
+    n = 64 * int(math.ceil(density * (t * t) / 64.0))
+    return int(min(max(n, per_shell), per_shell_max))
+
+
+def sketch_rows(c: int) -> int:
+    """Rows of the sketch of a proxy matrix with c candidate columns."""
+    return max(2 * c, c + 16)
+
+
 def box_distance(c: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> float:
     """Distance from point c to the axis-aligned box [lo, hi]."""
     d = np.maximum(np.maximum(lo - c, 0.0), c - hi)
     return float(math.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]))
 
 
+SKETCH_SEED = 0x5EEDF00D
+
+
 class H2:
     def __init__(self, X, kind, ell, shift, leaf, tol, eta=1.0,
-                 shells=8, per_shell=128, tree: Tree | None = None):
+                 shells=8, per_shell=128, per_shell_max=2048, density=90.0,
+                 sketch_seed=SKETCH_SEED, tree: Tree | None = None):
         self.X = np.ascontiguousarray(X, dtype=np.float64)
         self.kind, self.ell, self.shift, self.tol = kind, float(ell), float(shift), float(tol)
         self.shells, self.per_shell = int(shells), int(per_shell)
+        self.per_shell_max, self.density = max(int(per_shell_max), int(per_shell)), float(density)
+        self.sketch_seed = int(sketch_seed)
+        self.proxy_n: dict[int, int] = {}   # points per sphere of each node
+        self.sketched: dict[int, bool] = {}
         self.tree = tree if tree is not None else Tree(self.X, leaf, eta)
         T = self.tree
         self.skel: dict[int, np.ndarray] = {}
@@ -93,7 +126,9 @@ class H2:
         rout = float(np.sqrt(dc[:, 0] * dc[:, 0] + dc[:, 1] * dc[:, 1] + dc[:, 2] * dc[:, 2]).max())
         rout = max(rout, rin)
         Q = self.shells
-        unit = fibonacci_sphere(self.per_shell)
+        P = proxy_count(rin, self.ell, self.per_shell, self.per_shell_max, self.density)
+        self.proxy_n[v] = P
+        unit = fibonacci_sphere(P)
         pts = []
         for q in range(Q):
             rad = rin if Q == 1 else rin * (rout / rin) ** (q / (Q - 1))
@@ -118,7 +153,11 @@ class H2:
                     self.W[v] = np.zeros((len(cand), 0))
                     continue
                 G = kernels.evaluate(self.kind, self.ell, self.X[cand], P)
-                f = CPQR(G.T, self.tol, min(G.shape))
+                c, M = G.shape
+                l = sketch_rows(c)
+                self.sketched[v] = M > l
+                S = G @ rng.sketch(M, l, self.sketch_seed) if M > l else G
+                f = CPQR(S.T, self.tol, min(S.shape))
                 r = f.rank
                 E = f.interp()
                 W = np.zeros((len(cand), r))

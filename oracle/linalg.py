@@ -8,8 +8,45 @@ and tie rules.
 """
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
+
 import numpy as np
 import scipy.linalg as sla
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_CSRC = os.path.join(_HERE, "cpqr.c")
+_CLIB = os.path.join(_HERE, "_cpqr.so")
+_clib = None
+
+
+def build_c() -> str:
+    """Compile oracle/cpqr.c with gcc into oracle/_cpqr.so (plain IEEE
+    arithmetic: no fast-math, no contraction)."""
+    tmp = f"{_CLIB}.{os.getpid()}.tmp"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
+                    "-o", tmp, _CSRC, "-lm"], check=True, capture_output=True)
+    os.replace(tmp, _CLIB)
+    return _CLIB
+
+
+def _c_cpqr():
+    """The C pivoted QR, built on first use; None where no compiler is found."""
+    global _clib
+    if _clib is None:
+        try:
+            if not os.path.exists(_CLIB) or os.path.getmtime(_CLIB) < os.path.getmtime(_CSRC):
+                build_c()
+            lib = ctypes.CDLL(_CLIB)
+            P = ctypes.c_void_p
+            lib.oracle_cpqr.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
+                                        P, P, P, P]
+            lib.oracle_cpqr.restype = ctypes.c_int
+            _clib = lib
+        except (OSError, subprocess.CalledProcessError):
+            _clib = False
+    return _clib or None
 
 
 def chol(A: np.ndarray) -> np.ndarray:
@@ -54,10 +91,14 @@ class CPQR:
     by flipping the sign of the matching Q column and R row.
     """
 
-    def __init__(self, M: np.ndarray, tol: float, max_rank: int):
-        A = np.array(M, dtype=np.float64, copy=True)
-        m, n = A.shape
+    def __init__(self, M: np.ndarray, tol: float, max_rank: int, use_c: bool = True):
+        m, n = np.shape(M)
         kmax = min(m, n, max(int(max_rank), 0))
+        lib = _c_cpqr() if use_c and m * n > 0 else None
+        if lib is not None:
+            self._factor_c(lib, M, tol, kmax)
+            return
+        A = np.array(M, dtype=np.float64, copy=True)
         used = np.zeros(n, dtype=bool)
         piv, vs, betas, diag = [], [], [], []
         ref = None
@@ -99,6 +140,30 @@ class CPQR:
         R = A[: self.rank, :][:, self.perm] if self.rank else np.zeros((0, n))
         self.R = sign[:, None] * R if self.rank else R
         self.diag = np.abs(np.array(diag))
+
+    def _factor_c(self, lib, M, tol, kmax):
+        """The same factorization by oracle/cpqr.c (column-major copy of M)."""
+        A = np.array(M, dtype=np.float64, order="F", copy=True)
+        m, n = A.shape
+        piv = np.zeros(max(kmax, 1), dtype=np.int32)
+        alpha = np.zeros(max(kmax, 1))
+        betas = np.zeros(max(kmax, 1))
+        V = np.zeros((m, max(kmax, 1)), order="F")
+        r = lib.oracle_cpqr(m, n, A.ctypes.data, float(tol), int(kmax), piv.ctypes.data,
+                            alpha.ctypes.data, betas.ctypes.data, V.ctypes.data)
+        used = np.zeros(n, dtype=bool)
+        used[piv[:r]] = True
+        self.m, self.n = m, n
+        self.rank = r
+        self.piv = piv[:r].astype(np.int64)
+        self.perm = np.concatenate([self.piv, np.flatnonzero(~used).astype(np.int64)])
+        self._vs = [V[t:, t].copy() for t in range(r)]
+        self._betas = [float(b) for b in betas[:r]]
+        sign = np.where(alpha[:r] < 0, -1.0, 1.0)
+        self._sign = sign
+        R = A[:r, :][:, self.perm] if r else np.zeros((0, n))
+        self.R = sign[:, None] * R if r else R
+        self.diag = np.abs(alpha[:r])
 
     def q(self) -> np.ndarray:
         """First rank columns of Q (m x rank), orthonormal."""

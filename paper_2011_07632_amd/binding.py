@@ -26,7 +26,7 @@ STATUS_NAMES = {1: "SPD_PENDING", 0: "SPD_OK", -1: "SPD_E_INVALID", -2: "SPD_E_N
 
 # query ids (include/spdhss.h)
 Q = dict(N=0, LEVELS=1, PERM=2, NODE_START=3, H2_RANK=4, SKELETON=5, NEAR_PTR=6, NEAR_IDX=7,
-         COUP_PTR=8, COUP_IDX=9, NNODES=10, BYTES=11, H2_TIMES=12)
+         COUP_PTR=8, COUP_IDX=9, NNODES=10, BYTES=11, H2_TIMES=12, PROXY_COUNT=13, H2_STORAGE=14)
 HQ = dict(RANK=0, PIVOTS=1, BASIS=2, TRANSFER=3, PHIU=4, COUPLING=5, FACTOR=6, ROWS=7, BYTES=8,
           TIMES=9, FLOPS=10)
 
@@ -43,7 +43,21 @@ class _Kernel(C.Structure):
 
 class _H2Opts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("eta", C.c_double), ("tol", C.c_double),
-                ("proxy_shells", C.c_int32), ("proxy_per_shell", C.c_int32)]
+                ("proxy_shells", C.c_int32), ("proxy_per_shell", C.c_int32),
+                ("proxy_per_shell_max", C.c_int32), ("proxy_density", C.c_double),
+                ("sketch_seed", C.c_uint64)]
+
+
+# defaults of the H^2 construction options (spd_h2_opts)
+H2_DEFAULTS = dict(proxy_shells=8, proxy_per_shell=128, proxy_per_shell_max=2048, proxy_density=90.0,
+                   sketch_seed=0x5EEDF00D)
+
+
+def _h2_opts(leaf, eta, tol, d: dict) -> "_H2Opts":
+    g = {k: d.get(k, v) for k, v in H2_DEFAULTS.items()}
+    g["proxy_per_shell_max"] = max(int(g["proxy_per_shell_max"]), int(g["proxy_per_shell"]))
+    return _H2Opts(int(leaf), float(eta), float(tol), int(g["proxy_shells"]), int(g["proxy_per_shell"]),
+                   int(g["proxy_per_shell_max"]), float(g["proxy_density"]), int(g["sketch_seed"]))
 
 
 class _HSSOpts(C.Structure):
@@ -228,6 +242,15 @@ class H2Matrix:
     def device_bytes(self) -> int:
         return self.scalar("BYTES")
 
+    def proxy_counts(self) -> np.ndarray:
+        """Points per proxy sphere of every node (0 where no ID ran)."""
+        return self._get("PROXY_COUNT", np.int32, self.nnodes)
+
+    def storage(self) -> dict:
+        """Bytes of the near blocks, coupling blocks and interpolation matrices."""
+        v = self._get("H2_STORAGE", np.int64, 3)
+        return {"near": int(v[0]), "coupling": int(v[1]), "bases": int(v[2])}
+
 
 class HSSMatrix:
     """SPD HSS approximation built by Algorithm 5.3 (handle)."""
@@ -310,12 +333,15 @@ class ULVFactor:
 # ------------------------------------------------------------------ entry points --
 def h2_build(points: torch.Tensor, kernel: str, ell: float, shift: float, leaf: int = 64,
              tol: float = 1e-8, eta: float = 1.0, proxy_shells: int = 8, proxy_per_shell: int = 128,
+             proxy_per_shell_max: int = 2048, proxy_density: float = 90.0, sketch_seed: int = 0x5EEDF00D,
              stream=None) -> H2Matrix:
     if not points.is_cuda or points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 3:
         raise ValueError("points must be an (N, 3) float64 device tensor")
     points = points.contiguous()
     k = _Kernel(KERNELS[kernel], float(ell), float(shift))
-    o = _H2Opts(int(leaf), float(eta), float(tol), int(proxy_shells), int(proxy_per_shell))
+    o = _h2_opts(leaf, eta, tol, dict(proxy_shells=proxy_shells, proxy_per_shell=proxy_per_shell,
+                                      proxy_per_shell_max=proxy_per_shell_max,
+                                      proxy_density=proxy_density, sketch_seed=sketch_seed))
     out = C.c_void_p()
     _check(lib.h2_build(points.data_ptr(), points.shape[0], k, C.byref(o), _stream(stream), C.byref(out)))
     return H2Matrix(out.value, points.shape[0], points.device)
@@ -461,8 +487,7 @@ def _fill_instance(I: _Instance, d: dict):
     rr = np.zeros(nc, dtype=np.float64)
     I.points, I.n = P.data_ptr(), P.shape[0]
     I.kernel = _Kernel(KERNELS[d["kernel"]], float(d["ell"]), float(d["shift"]))
-    I.h2 = _H2Opts(int(d["leaf"]), float(d.get("eta", 1.0)), float(d["h2_tol"]),
-                   int(d.get("proxy_shells", 8)), int(d.get("proxy_per_shell", 128)))
+    I.h2 = _h2_opts(d["leaf"], d.get("eta", 1.0), d["h2_tol"], d)
     I.hss = _HSSOpts(float(d["hss_tol"]), int(d["max_rank"]), int(d["oversample"]), int(d.get("seed", 0)),
                      _ptr(om))
     I.solve_precision = SOLVE_PRECISION[d.get("precision", "f64")]
@@ -528,7 +553,7 @@ def solve_batch(instances: list[dict], workers: int = 8) -> list[dict]:
     Each instance is a dict with points ((N, 3) FP64 device tensor), kernel,
     ell, shift, leaf, h2_tol, hss_tol, max_rank, oversample, b ((N, nrhs)
     column-major, ld = N), rtol, maxit and optionally omega ((N, max_rank +
-    oversample), ld = N), seed, eta, proxy_shells, proxy_per_shell and
+    oversample), ld = N), seed, eta, the proxy options of h2_build and
     precision ("f64" or "f32").  Returns per instance: x, iters and relres
     per column, status and wall times."""
     n = len(instances)

@@ -69,10 +69,14 @@ spd_status h2_build(const double* points, int64_t n, spd_kernel kernel, const sp
               "leaf_size must be in [1, 512]");
   SPD_REQUIRE(opts->eta > 0, SPD_E_INVALID, "eta must be positive");
   SPD_REQUIRE(opts->tol >= 0 && opts->tol < 1, SPD_E_INVALID, "tol must be in [0, 1)");
-  SPD_REQUIRE(opts->proxy_shells >= 1 && opts->proxy_per_shell >= 4, SPD_E_INVALID,
-              "bad proxy counts");
-  SPD_REQUIRE((int64_t)opts->proxy_shells * opts->proxy_per_shell <= 2048, SPD_E_INVALID,
-              "at most 2048 proxy points");
+  SPD_REQUIRE(opts->proxy_shells >= 1 && opts->proxy_shells <= 64 && opts->proxy_per_shell >= 4,
+              SPD_E_INVALID, "bad proxy counts");
+  SPD_REQUIRE(opts->proxy_per_shell_max >= opts->proxy_per_shell, SPD_E_INVALID,
+              "proxy_per_shell_max below proxy_per_shell");
+  SPD_REQUIRE((int64_t)opts->proxy_shells * opts->proxy_per_shell_max <= 65536, SPD_E_INVALID,
+              "at most 65536 proxy points");
+  SPD_REQUIRE(opts->proxy_density >= 0 && std::isfinite(opts->proxy_density), SPD_E_INVALID,
+              "proxy_density must be finite and non-negative");
   std::unique_ptr<spd_h2> h(new spd_h2());
   h->m.kern = kernel;
   h->m.opts = *opts;
@@ -253,6 +257,21 @@ spd_status spd_h2_query_get(spd_h2_t A, int32_t what, void* out, int64_t bytes) 
     case SPD_Q_COUP_IDX: put(out, bytes, T.coup_idx.data(), T.coup_idx.size()); break;
     case SPD_Q_BYTES: { int64_t v = (int64_t)A->m.arena.bytes_used(); put(out, bytes, &v, 1); break; }
     case SPD_Q_H2_TIMES: put(out, bytes, H.times, 4); break;
+    case SPD_Q_PROXY_COUNT: put(out, bytes, H.proxy_n.data(), H.proxy_n.size()); break;
+    case SPD_Q_H2_STORAGE: {
+      int64_t v[3] = {0, 0, 0};
+      for (int i = T.first_at(1); i < T.first_at(1) + T.count_at(1); ++i)
+        for (int64_t e = T.near_ptr[i]; e < T.near_ptr[i + 1]; ++e)
+          v[0] += (int64_t)8 * std::max(H.near_ld(i), 16) * T.size(T.near_idx[e]);
+      for (int i = 1; i < T.nnodes; ++i) {
+        for (int64_t e = T.coup_ptr[i]; e < T.coup_ptr[i + 1]; ++e)
+          if (H.Bh[e]) v[1] += (int64_t)8 * H.coup_ld(i) * H.k[T.coup_idx[e]];
+        if (H.W[i]) v[2] += (int64_t)16 * H.cand[i] * H.k[i];
+        if (H.E[i]) v[2] += (int64_t)16 * H.k[i] * (H.cand[i] - H.k[i]);
+      }
+      put(out, bytes, v, 3);
+      break;
+    }
     default: throw Error(SPD_E_INVALID, "unknown query");
   }
   SPD_API_END
@@ -375,7 +394,7 @@ spd_status spd_test_cpqr(double* A, double* Q, int32_t* piv, int32_t* rank, doub
   SPD_REQUIRE(A && piv && rank && batch >= 1 && m >= 1 && n >= 1 && maxrank >= 0, SPD_E_INVALID,
               "bad args");
   if (which == 0) SPD_REQUIRE(cpqr_reg_fits(m, n) && Q, SPD_E_INVALID, "shape exceeds register kernel");
-  if (which == 1) SPD_REQUIRE(m <= 2048 && n <= 4096, SPD_E_INVALID, "shape too large");
+  if (which == 1) SPD_REQUIRE(m <= kCpqrBigRows && n <= 4096, SPD_E_INVALID, "shape too large");
   hipStream_t s = as_stream(stream);
   Stage st;
   Arena a;
@@ -397,6 +416,7 @@ spd_status spd_test_cpqr(double* A, double* Q, int32_t* piv, int32_t* rank, doub
     c.ldq = m;
     c.maxrank = mr;
     c.tol = tol;
+    c.nrm = which == 1 ? a.get_n<double>(n) : nullptr;
   }
   auto* d = (const CpqrProblem*)st.push(s, p.data(), p.size() * sizeof(CpqrProblem));
   if (which == 0) launch_cpqr_reg(s, d, batch, m, n);

@@ -103,8 +103,8 @@ struct BlockTerm {
 // Dense kernel block out(i, j) = K(x_a[ia(i)], x_b[ib(j)]) (+ shift if i == j
 // and diag_shift).  Points are gathered from SoA arrays through index lists
 // (idx == nullptr means the contiguous range starting at off); when proxy is
-// set, the a-side (row) points are generated as Fibonacci shells around the
-// given centre (see proxy_point).
+// set, the a-side (row) points are generated as `shells` Fibonacci spheres of
+// `per_shell` points around the given centre (see proxy_point).
 struct KBlockProblem {
   double* out;
   const int* ia;
@@ -112,6 +112,8 @@ struct KBlockProblem {
   int64_t offa, offb;
   int na, nb, ld, diag_shift;
   int proxy;          // a side is a proxy set
+  int shells, per_shell;
+  int pad;
   double cx, cy, cz;  // proxy centre
   double rin, rout;   // proxy radii
 };
@@ -140,6 +142,7 @@ struct CpqrProblem {
   int maxrank;
   double tol;
   double* hbeta;    // global variant with Q: out, Householder factors (maxrank); else null
+  double* nrm;      // global variant, more than 2048 rows: workspace of n doubles
 };
 
 // ----------------------------------------------------------- launchers --
@@ -172,7 +175,7 @@ void launch_block(hipStream_t s, const BlockProblem* d_p, const BlockTerm* d_t,
                   int nprob, int max_m, int max_n);
 void launch_kblock(hipStream_t s, const KBlockProblem* d_p, int nprob, int max_m,
                    int max_n, const double* px, int64_t stride, int kind,
-                   double ell, double shift, int shells, int per_shell);
+                   double ell, double shift);
 void launch_chol(hipStream_t s, const CholProblem* d_p, int nprob, int max_n,
                  int* d_fail);
 void launch_trsm(hipStream_t s, const TrsmProblem* d_p, int nprob, int max_n,
@@ -183,6 +186,9 @@ void launch_cpqr_reg(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_m
 // Q's first rank columns from the stored Householder vectors, the signs
 // making R's diagonal non-negative (as the register kernel's Q).
 void launch_cpqr_formq(hipStream_t s, const CpqrProblem* d_p, int nprob);
+// Above 2048 rows (at most kCpqrBigRows) every problem must carry its nrm
+// workspace.
+constexpr int kCpqrBigRows = 8000;
 void launch_cpqr_glob(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_m,
                       int max_n);
 bool cpqr_reg_fits(int m, int n);
@@ -194,6 +200,10 @@ void launch_scatter_rows(hipStream_t s, const double* src, int64_t lds, double* 
                          int64_t ldd, const int64_t* perm, int64_t n, int ncols);
 void launch_gaussian_fill(hipStream_t s, double* dst, int64_t n, int ncols,
                           int64_t ldd, const int64_t* perm, uint64_t seed);
+// dst(t, j) = standard normal of the counter (t << 24) | j under seed, for
+// t < rows, j < cols (column-major, ld): the sketch of the proxy ID
+void launch_sketch_fill(hipStream_t s, double* dst, int64_t rows, int cols, int64_t ld,
+                        uint64_t seed);
 void launch_soa_points(hipStream_t s, const double* pts_rowmajor,
                        const int64_t* perm, int64_t n, double* soa);
 // Fused PCG step kernels over per-chunk partial dot products (coldot_chunks(n)

@@ -58,6 +58,39 @@ static void replay_plan(H2Model& H, const H2Model::MatvecPlan& pl) {
   pl.tail.replay(H.s);
 }
 
+// X = R^{-1} B in place for every problem (R upper triangular k x k, ld ldr;
+// B k x n, ld ldb), for orders above what the batched triangular kernel holds
+// in LDS: back substitution by row blocks of 256, each block row first updated
+// with the rows already solved (an MFMA product), then its diagonal block
+// solved by the batched triangular kernel.
+struct UpperSolve {
+  const double* R;
+  int ldr;
+  double* B;
+  int ldb, k, n;
+};
+static void upper_solve_blocked(hipStream_t s, Stage& st, const std::vector<UpperSolve>& ps) {
+  constexpr int NB = 256;
+  int steps = 0;
+  for (const UpperSolve& p : ps) steps = std::max(steps, ceil_div(p.k, NB));
+  for (int step = 0; step < steps; ++step) {
+    GemmBatch g(0, 0);
+    TrsmBatch tb;
+    for (const UpperSolve& p : ps) {
+      const int b = ceil_div(p.k, NB) - 1 - step;
+      if (b < 0 || p.n <= 0) continue;
+      const int r0 = b * NB, rb = std::min(NB, p.k - r0), below = p.k - r0 - rb;
+      if (below > 0) {
+        g.add(p.B + r0, rb, p.n, p.ldb, 1.0, -1.0);
+        g.term(p.R + r0 + (size_t)(r0 + rb) * p.ldr, p.ldr, p.B + r0 + rb, p.ldb, below);
+      }
+      tb.add(p.R + r0 + (size_t)r0 * p.ldr, p.ldr, p.B + r0, p.ldb, rb, p.n);
+    }
+    if (!g.empty()) g.run(s, st);
+    tb.run(s, st, 1, 1);
+  }
+}
+
 void h2_build_impl(H2Model& H, const double* points, int64_t n) {
   hipStream_t s = H.s;
   const double t0 = now_seconds();
@@ -93,22 +126,59 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
       std::iota(H.cand_h[v].begin(), H.cand_h[v].end(), (int)T.start[v]);
     }
   }
-  const int P = H.opts.proxy_shells * H.opts.proxy_per_shell;
+  const int Q = H.opts.proxy_shells;
+  H.proxy_n.assign(nn, 0);
+  H.sketched.assign(nn, 0);
   Stage& st = H.stage;
   for (int lev = 1; lev < L; ++lev) {
-    struct Job { int v; double rin, rout; };
+    // per node: proxies per sphere, proxy rows M, candidates c, and the rows
+    // m of the matrix whose pivoted QR picks the skeleton (the sketch of
+    // l = max(2c, c + 16) rows when M exceeds l, else the proxy matrix)
+    struct Job {
+      int v, per, M, c, m;
+      bool sk;
+      double rin, rout;
+    };
     std::vector<Job> jobs;
     for (int v = T.first_at(lev); v < T.first_at(lev) + T.count_at(lev); ++v) {
       double rin, rout;
-      if (H.cand[v] > 0 && T.proxy_radii(v, rin, rout)) jobs.push_back({v, rin, rout});
+      if (H.cand[v] == 0 || !T.proxy_radii(v, rin, rout)) continue;
+      Job jb;
+      jb.v = v;
+      jb.rin = rin;
+      jb.rout = rout;
+      jb.per = proxy_count(rin, H.kern.ell, H.opts.proxy_per_shell, H.opts.proxy_per_shell_max,
+                           H.opts.proxy_density);
+      jb.M = Q * jb.per;
+      jb.c = H.cand[v];
+      const int l = std::max(2 * jb.c, jb.c + 16);
+      jb.sk = jb.M > l;
+      jb.m = jb.sk ? l : jb.M;
+      SPD_REQUIRE(jb.m <= kCpqrBigRows, SPD_E_INVALID,
+                  "H^2 proxy ID: more than 4000 candidates at node " + std::to_string(v) +
+                      " (level " + std::to_string(lev) + ")");
+      H.proxy_n[v] = jb.per;
+      H.sketched[v] = jb.sk;
+      jobs.push_back(jb);
     }
     size_t i = 0;
     while (i < jobs.size()) {
+      // a batch of nodes whose proxy matrices, sketches, R factors and shared
+      // Omega stay within about 16 GB (a level's nodes then run side by side,
+      // one pivoted QR per workgroup)
       size_t j = i, bytes = 0;
+      int64_t om_rows = 0, om_cols = 0;
       while (j < jobs.size()) {
-        const size_t b = (size_t)P * H.cand[jobs[j].v] * 8 * 2;
-        if (j > i && bytes + b > (size_t(1) << 30)) break;
+        const Job& jb = jobs[j];
+        size_t b = (size_t)jb.M * jb.c + (size_t)std::min(jb.m, jb.c) * jb.c + jb.c;
+        if (jb.sk) b += (size_t)jb.m * jb.c;
+        b *= 8;
+        const int64_t r2 = jb.sk ? std::max<int64_t>(om_rows, jb.M) : om_rows;
+        const int64_t c2 = jb.sk ? std::max<int64_t>(om_cols, jb.m) : om_cols;
+        if (j > i && bytes + b + (size_t)(r2 * c2 * 8) > (size_t(16) << 30)) break;
         bytes += b;
+        om_rows = r2;
+        om_cols = c2;
         ++j;
       }
       const int nj = (int)(j - i);
@@ -118,12 +188,22 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
       std::vector<double*> Rp(nj);
       std::vector<int*> pivp(nj);
       int* d_rank = tmp.get_n<int>(nj);
-      int maxc = 0;
+      int maxc = 0, maxM = 0, maxm = 0;
+      double* Om = om_rows > 0 ? tmp.get_n<double>((size_t)om_rows * om_cols) : nullptr;
+      GemmBatch sketch(1, 0);
       for (int q = 0; q < nj; ++q) {
         const Job& jb = jobs[i + q];
-        const int v = jb.v, c = H.cand[v], mr = std::min(P, c);
+        const int v = jb.v, c = jb.c, mr = std::min(jb.m, c);
         maxc = std::max(maxc, c);
-        double* G = tmp.get_n<double>((size_t)P * c);
+        maxM = std::max(maxM, jb.M);
+        maxm = std::max(maxm, jb.m);
+        double* G = tmp.get_n<double>((size_t)jb.M * c);
+        double* A = G;
+        if (jb.sk) {
+          A = tmp.get_n<double>((size_t)jb.m * c);
+          sketch.add(A, jb.m, c, jb.m);
+          sketch.term(Om, (int)om_rows, G, jb.M, jb.M);
+        }
         Rp[q] = tmp.get_n<double>((size_t)mr * c);
         pivp[q] = tmp.get_n<int>(c);
         KBlockProblem& kp = kb[q];
@@ -133,10 +213,12 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
         kp.ib = T.is_leaf(v) ? nullptr : H.cand_d[v];
         kp.offa = 0;
         kp.offb = T.is_leaf(v) ? T.start[v] : 0;
-        kp.na = P;
+        kp.na = jb.M;
         kp.nb = c;
-        kp.ld = P;
+        kp.ld = jb.M;
         kp.proxy = 1;
+        kp.shells = Q;
+        kp.per_shell = jb.per;
         kp.cx = T.center[3 * v];
         kp.cy = T.center[3 * v + 1];
         kp.cz = T.center[3 * v + 2];
@@ -144,35 +226,47 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
         kp.rout = jb.rout;
         CpqrProblem& cp = cq[q];
         cp = CpqrProblem{};
-        cp.A = G;
+        cp.A = A;
         cp.R = Rp[q];
         cp.piv = pivp[q];
         cp.rank = d_rank + q;
-        cp.m = P;
+        cp.m = jb.m;
         cp.n = c;
-        cp.lda = P;
+        cp.lda = jb.m;
         cp.maxrank = mr;
         cp.tol = H.opts.tol;
+        cp.nrm = tmp.get_n<double>(c);
       }
       auto* dkb = (const KBlockProblem*)st.push(s, kb.data(), kb.size() * sizeof(KBlockProblem));
-      launch_kblock(s, dkb, nj, P, maxc, H.pts, n, H.kern.kind, H.kern.ell, H.kern.shift,
-                    H.opts.proxy_shells, H.opts.proxy_per_shell);
+      launch_kblock(s, dkb, nj, maxM, maxc, H.pts, n, H.kern.kind, H.kern.ell, H.kern.shift);
+      if (!sketch.empty()) {
+        launch_sketch_fill(s, Om, om_rows, (int)om_cols, om_rows, H.opts.sketch_seed);
+        sketch.run(s, st);
+      }
       auto* dcq = (const CpqrProblem*)st.push(s, cq.data(), cq.size() * sizeof(CpqrProblem));
-      launch_cpqr_glob(s, dcq, nj, P, maxc);
+      launch_cpqr_glob(s, dcq, nj, maxm, maxc);
       std::vector<int> ranks(nj);
       SPD_HIP(hipMemcpyAsync(ranks.data(), d_rank, nj * sizeof(int), hipMemcpyDeviceToHost, s));
       SPD_HIP(hipStreamSynchronize(s));
       st.reset();
+      // E = R11^{-1} R12 in place of R12
       TrsmBatch tb;
+      std::vector<UpperSolve> big;
       for (int q = 0; q < nj; ++q) {
-        const int v = jobs[i + q].v, c = H.cand[v], mr = std::min(P, c), k = ranks[q];
-        if (k > 0 && c > k) tb.add(Rp[q], mr, Rp[q] + (size_t)k * mr, mr, k, c - k);
+        const Job& jb = jobs[i + q];
+        const int c = jb.c, mr = std::min(jb.m, c), k = ranks[q];
+        if (k > 0 && c > k) {
+          if (k <= 2048) tb.add(Rp[q], mr, Rp[q] + (size_t)k * mr, mr, k, c - k);
+          else big.push_back({Rp[q], mr, Rp[q] + (size_t)k * mr, mr, k, c - k});
+        }
       }
       tb.run(s, st, 1, 1);
+      if (!big.empty()) upper_solve_blocked(s, st, big);
       std::vector<std::vector<int>> pivh(nj);
       BlockBatch ecp;  // E_v and E_v^T, kept for the streaming product
       for (int q = 0; q < nj; ++q) {
-        const int v = jobs[i + q].v, c = H.cand[v], mr = std::min(P, c), k = ranks[q];
+        const Job& jb = jobs[i + q];
+        const int v = jb.v, c = jb.c, mr = std::min(jb.m, c), k = ranks[q];
         H.k[v] = k;
         if (k > 0) {
           H.W[v] = H.arena.get_n<double>((size_t)c * k);
@@ -292,8 +386,7 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
     for (size_t a = 0; a < kb.size(); a += chunk) {
       const size_t b = std::min(kb.size(), a + chunk);
       auto* d = (const KBlockProblem*)st.push(s, kb.data() + a, (b - a) * sizeof(KBlockProblem));
-      launch_kblock(s, d, (int)(b - a), mm, mn, H.pts, n, H.kern.kind, H.kern.ell, H.kern.shift,
-                    H.opts.proxy_shells, H.opts.proxy_per_shell);
+      launch_kblock(s, d, (int)(b - a), mm, mn, H.pts, n, H.kern.kind, H.kern.ell, H.kern.shift);
     }
     SPD_HIP(hipStreamSynchronize(s));
     st.reset();

@@ -734,6 +734,26 @@ void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int n
   SPD_HIP(hipGetLastError());
 }
 
+// Problems per launch of a kernel with `tiles` workgroups of `threads` per
+// problem, so that one launch stays below 2^31 work-items (the dispatch
+// packet's grid size is a 32-bit count of work-items).
+static int probs_per_launch(int64_t tiles, int threads) {
+  const int64_t lim = ((int64_t)1 << 31) / (tiles * threads);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(lim, 1 << 30));
+}
+
+template <int BM, int BN, int WM, int WN>
+static void launch_gemm_tiles(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
+                              int max_m, int max_n, int transA, int transB) {
+  const int tiles = ceil_div(max_m, BM) * ceil_div(max_n, BN);
+  const int per = probs_per_launch(tiles, 256);
+  for (int p0 = 0; p0 < nprob; p0 += per) {
+    const int np = std::min(per, nprob - p0);
+    hipLaunchKernelGGL((k_gemm<BM, BN, WM, WN>), dim3((unsigned)np * tiles), dim3(256), 0, s,
+                       d_p + p0, d_t, tiles, transA, transB);
+  }
+}
+
 void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
                  int max_m, int max_n, int transA, int transB, int max_k, int a_f32) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
@@ -747,17 +767,11 @@ void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int
     else if (max_n <= 2) launch_skinny<2>(s, d_p, d_t, nprob, max_m, transA, transB);
     else launch_skinny<4>(s, d_p, d_t, nprob, max_m, transA, transB);
   } else if (max_n <= 16) {
-    const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 16);
-    hipLaunchKernelGGL((k_gemm<64, 16, 16, 16>), dim3((unsigned)nprob * tiles), dim3(256), 0, s,
-                       d_p, d_t, tiles, transA, transB);
+    launch_gemm_tiles<64, 16, 16, 16>(s, d_p, d_t, nprob, max_m, max_n, transA, transB);
   } else if (max_n <= 32) {
-    const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 32);
-    hipLaunchKernelGGL((k_gemm<64, 32, 32, 16>), dim3((unsigned)nprob * tiles), dim3(256), 0, s,
-                       d_p, d_t, tiles, transA, transB);
+    launch_gemm_tiles<64, 32, 32, 16>(s, d_p, d_t, nprob, max_m, max_n, transA, transB);
   } else {
-    const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 64);
-    hipLaunchKernelGGL((k_gemm<64, 64, 32, 32>), dim3((unsigned)nprob * tiles), dim3(256), 0, s,
-                       d_p, d_t, tiles, transA, transB);
+    launch_gemm_tiles<64, 64, 32, 32>(s, d_p, d_t, nprob, max_m, max_n, transA, transB);
   }
   SPD_HIP(hipGetLastError());
 }
@@ -802,7 +816,10 @@ void launch_block(hipStream_t s, const BlockProblem* d_p, const BlockTerm* d_t, 
                   int max_m, int max_n) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
   const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 64);
-  hipLaunchKernelGGL(k_block, dim3((unsigned)nprob * tiles), dim3(256), 0, s, d_p, d_t, tiles);
+  const int per = probs_per_launch(tiles, 256);
+  for (int p0 = 0; p0 < nprob; p0 += per)
+    hipLaunchKernelGGL(k_block, dim3((unsigned)std::min(per, nprob - p0) * tiles), dim3(256), 0, s,
+                       d_p + p0, d_t, tiles);
   SPD_HIP(hipGetLastError());
 }
 
@@ -819,8 +836,9 @@ __device__ __forceinline__ double kfun(int kind, double ell, double r2) {
 
 // Proxy point t of a node: sphere q = t / per_shell at radius
 // rin (rout/rin)^(q/(shells-1)), Fibonacci lattice point u = t % per_shell.
-__device__ __forceinline__ void proxy_point(const KBlockProblem& P, int t, int shells,
-                                            int per_shell, double& x, double& y, double& z) {
+__device__ __forceinline__ void proxy_point(const KBlockProblem& P, int t, double& x, double& y,
+                                            double& z) {
+  const int shells = P.shells, per_shell = P.per_shell;
   const int q = t / per_shell, u = t % per_shell;
   const double zz = 1.0 - (2.0 * u + 1.0) / per_shell;
   const double rho = sqrt(fmax(0.0, 1.0 - zz * zz));
@@ -835,7 +853,7 @@ __device__ __forceinline__ void proxy_point(const KBlockProblem& P, int t, int s
 __global__ __launch_bounds__(256) void k_kblock(const KBlockProblem* __restrict__ probs,
                                                 int tiles_max, const double* __restrict__ px,
                                                 int64_t stride, int kind, double ell,
-                                                double shift, int shells, int per_shell) {
+                                                double shift) {
   __shared__ double ax[64], ay[64], az[64], bx[64], by[64], bz[64];
   const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
   const KBlockProblem P = probs[p];
@@ -848,7 +866,7 @@ __global__ __launch_bounds__(256) void k_kblock(const KBlockProblem* __restrict_
     if (i < P.na) {
       double x, y, z;
       if (P.proxy) {
-        proxy_point(P, i, shells, per_shell, x, y, z);
+        proxy_point(P, i, x, y, z);
       } else {
         const int64_t g = P.ia ? (int64_t)P.ia[i] : P.offa + i;
         x = px[g];
@@ -882,12 +900,13 @@ __global__ __launch_bounds__(256) void k_kblock(const KBlockProblem* __restrict_
 }
 
 void launch_kblock(hipStream_t s, const KBlockProblem* d_p, int nprob, int max_m, int max_n,
-                   const double* px, int64_t stride, int kind, double ell, double shift,
-                   int shells, int per_shell) {
+                   const double* px, int64_t stride, int kind, double ell, double shift) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
   const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 64);
-  hipLaunchKernelGGL(k_kblock, dim3((unsigned)nprob * tiles), dim3(256), 0, s, d_p, tiles, px,
-                     stride, kind, ell, shift, shells, per_shell);
+  const int per = probs_per_launch(tiles, 256);
+  for (int p0 = 0; p0 < nprob; p0 += per)
+    hipLaunchKernelGGL(k_kblock, dim3((unsigned)std::min(per, nprob - p0) * tiles), dim3(256), 0, s,
+                       d_p + p0, tiles, px, stride, kind, ell, shift);
   SPD_HIP(hipGetLastError());
 }
 
@@ -1432,6 +1451,110 @@ __global__ __launch_bounds__(1024) void k_cpqr_glob(const CpqrProblem* __restric
   (void)nrm_ws;
 }
 
+// Variant for more rows than the register chunks hold (2048 < m <= 8000):
+// the Householder vector is staged in LDS (m doubles), the squared trailing
+// norms live in the problem's global workspace P.nrm, and each remaining
+// column is read twice per step (its dot product with the vector, then the
+// update).  Pivot choice, norms (rows > t after step t) and outputs are those
+// of k_cpqr_glob; each lane owns the rows lane + 64 q as there.
+__global__ __launch_bounds__(1024) void k_cpqr_big(const CpqrProblem* __restrict__ probs) {
+  constexpr int NW = 16;
+  extern __shared__ double vbuf[];  // m
+  __shared__ double sh_beta;
+  const CpqrProblem P = probs[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = P.m, n = P.n;
+  double* A = P.A;
+  double* nrm2 = P.nrm;
+  const int64_t lda = P.lda;
+  for (int col = w; col < n; col += NW) {
+    double s2 = 0.0;
+    for (int row = lane; row < m; row += 64) {
+      const double x = A[row + col * lda];
+      s2 += x * x;
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) nrm2[col] = s2;
+  }
+  __threadfence_block();
+  __syncthreads();
+  const int kmax = min(min(m, n), P.maxrank);
+  double ref = 0.0;
+  int rank = 0;
+  for (int t = 0; t < kmax; ++t) {
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    for (int j = lane; j < n; j += 64) {
+      const double v = nrm2[j];
+      if (v > best) { best = v; bi = j; }
+    }
+    wave_argmax(best, bi);
+    const double nrm = sqrt(fmax(best, 0.0));
+    if (t == 0) ref = nrm;
+    if (!(nrm > P.tol * ref) || nrm == 0.0) break;
+    __syncthreads();
+    if (w == bi % NW) {
+      const double xt = A[t + bi * lda];
+      const double alpha = (xt >= 0.0) ? -nrm : nrm;
+      const double beta = 1.0 / (nrm * (nrm + fabs(xt)));
+      for (int row = lane; row < m; row += 64) {
+        if (row < t) continue;
+        const double v = (row == t) ? xt - alpha : A[row + bi * lda];
+        vbuf[row] = v;
+        A[row + bi * lda] = (row == t) ? alpha : 0.0;
+        if (P.hbeta) P.V[row + (int64_t)t * m] = v;
+      }
+      if (P.hbeta)
+        for (int row = lane; row < t; row += 64) P.V[row + (int64_t)t * m] = 0.0;
+      if (lane == 0) {
+        if (P.hbeta) P.hbeta[t] = beta;
+        sh_beta = beta;
+        P.piv[t] = bi;
+        if (P.diag) P.diag[t] = nrm;
+        nrm2[bi] = -1.0;
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    const double beta = sh_beta;
+    for (int col = w; col < n; col += NW) {
+      if (nrm2[col] < 0.0) continue;
+      double d = 0.0;
+      for (int row = lane; row < m; row += 64)
+        if (row >= t) d += vbuf[row] * A[row + col * lda];
+      d = wave_sum(d);
+      double s2 = 0.0;
+      for (int row = lane; row < m; row += 64) {
+        if (row < t) continue;
+        const double x = A[row + col * lda] - beta * d * vbuf[row];
+        A[row + col * lda] = x;
+        if (row > t) s2 += x * x;
+      }
+      s2 = wave_sum(s2);
+      if (lane == 0) nrm2[col] = s2;
+    }
+    rank = t + 1;
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *P.rank = rank;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int pos = rank;
+    for (int j = 0; j < n; ++j)
+      if (nrm2[j] >= 0.0) P.piv[pos++] = j;
+  }
+  __threadfence_block();
+  __syncthreads();
+  if (P.R) {
+    const int64_t ldr = P.maxrank;
+    for (int64_t e = threadIdx.x; e < (int64_t)rank * n; e += blockDim.x) {
+      const int i = (int)(e % rank), j = (int)(e / rank);
+      P.R[i + j * ldr] = A[i + (int64_t)P.piv[j] * lda];
+    }
+  }
+}
+
 // Q = H_0 H_1 ... H_{rank-1} [I; 0] by backward accumulation: start from the
 // first rank columns of the identity and apply H_t = I - beta_t v_t v_t^T for
 // t = rank-1 down to 0 (it touches rows >= t of columns >= t only); then flip
@@ -1482,10 +1605,13 @@ void launch_cpqr_glob(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_
   if (max_m <= 1024) {
     const size_t bytes = (64 * 16 + (size_t)max_n) * sizeof(double);
     hipLaunchKernelGGL((k_cpqr_glob<16>), dim3(nprob), dim3(1024), bytes, s, d_p, nullptr);
-  } else {
-    SPD_REQUIRE(max_m <= 2048, SPD_E_INVALID, "cpqr: more than 2048 rows");
+  } else if (max_m <= 2048) {
     const size_t bytes = (64 * 32 + (size_t)max_n) * sizeof(double);
     hipLaunchKernelGGL((k_cpqr_glob<32>), dim3(nprob), dim3(1024), bytes, s, d_p, nullptr);
+  } else {
+    SPD_REQUIRE(max_m <= kCpqrBigRows, SPD_E_INVALID, "cpqr: more than 8000 rows");
+    const size_t bytes = (size_t)max_m * sizeof(double);
+    hipLaunchKernelGGL(k_cpqr_big, dim3(nprob), dim3(1024), bytes, s, d_p);
   }
   SPD_HIP(hipGetLastError());
 }
@@ -1539,6 +1665,27 @@ __global__ void k_gaussian_fill(double* __restrict__ dst, int64_t n, int ncols, 
   const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
   dst[i + c * ldd] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
 }
+__global__ void k_sketch_fill(double* __restrict__ dst, int64_t rows, int cols, int64_t ld,
+                              uint64_t seed) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (t >= rows || j >= cols) return;
+  const uint64_t ctr = ((uint64_t)t << 24) | (uint64_t)j;
+  const uint64_t h1 = splitmix64(seed ^ splitmix64(2 * ctr));
+  const uint64_t h2 = splitmix64(seed ^ splitmix64(2 * ctr + 1));
+  const double u1 = ((h1 >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
+  const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
+  dst[t + j * ld] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+void launch_sketch_fill(hipStream_t s, double* dst, int64_t rows, int cols, int64_t ld,
+                        uint64_t seed) {
+  if (rows <= 0 || cols <= 0) return;
+  SPD_REQUIRE(cols < (1 << 24), SPD_E_INVALID, "sketch: too many columns");
+  hipLaunchKernelGGL(k_sketch_fill, dim3(ceil_div(rows, 256), cols), dim3(256), 0, s, dst, rows,
+                     cols, ld, seed);
+  SPD_HIP(hipGetLastError());
+}
+
 void launch_gaussian_fill(hipStream_t s, double* dst, int64_t n, int ncols, int64_t ldd,
                           const int64_t* perm, uint64_t seed) {
   if (n <= 0 || ncols <= 0) return;

@@ -32,6 +32,7 @@ struct TreeHost {
   int64_t coup_pos(int i, int j) const;
   bool proxy_radii(int v, double& rin, double& rout) const;
 };
+int proxy_count(double rin, double ell, int lo, int hi, double density);
 
 // --------------------------------------------------- descriptor staging --
 // Collects descriptor arrays on the host and copies them to device memory.
@@ -155,6 +156,8 @@ struct H2Model {
   int64_t* perm_d = nullptr;    // tree position -> original index
   // per node (heap order)
   std::vector<int> k;             // skeleton size k_v
+  std::vector<int> proxy_n;       // points per proxy sphere (0: no ID at this node)
+  std::vector<int> sketched;      // the proxy matrix was sketched before the pivoted QR
   std::vector<int> cand;          // candidates: n_v (leaf) or k_c1 + k_c2
   std::vector<int*> cand_d;       // device candidate tree positions (nonleaf: [skel_c1; skel_c2])
   std::vector<std::vector<int>> cand_h;  // host copy (tree positions)

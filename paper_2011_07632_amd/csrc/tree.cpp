@@ -201,4 +201,16 @@ bool TreeHost::proxy_radii(int v, double& rin, double& rout) const {
   return true;
 }
 
+// Points per proxy sphere of a node whose innermost sphere has radius rin:
+// density * (rin / ell)^2 rounded up to a multiple of 64, clamped to [lo, hi]
+// (density 0 keeps lo).  Evaluated without contraction, as the oracle does.
+int proxy_count(double rin, double ell, int lo, int hi, double density) {
+  if (!(density > 0.0)) return lo;
+  const double t = rin / ell;
+  const double x = density * (t * t) / 64.0;
+  const double n = 64.0 * std::ceil(x);
+  if (!(n < (double)hi)) return hi;
+  return std::max((int)n, lo);
+}
+
 }  // namespace spd

@@ -52,7 +52,8 @@ FAKE = ctypes.c_void_p(0x1000)
 def _h2_args(**kw):
     from paper_2011_07632_amd import binding as B
     k = dict(kind=1, ell=0.1, shift=1e-4)
-    o = dict(leaf_size=64, eta=1.0, tol=1e-8, proxy_shells=8, proxy_per_shell=128)
+    o = dict(leaf_size=64, eta=1.0, tol=1e-8, proxy_shells=8, proxy_per_shell=128, proxy_per_shell_max=2048,
+             proxy_density=90.0, sketch_seed=1)
     for key, v in kw.items():
         (k if key in k else o)[key] = v
     return B._Kernel(**k), B._H2Opts(**o)
@@ -70,7 +71,11 @@ def _h2_args(**kw):
     (100, {"eta": 0.0}, b"eta"),
     (100, {"tol": 1.0}, b"tol"),
     (100, {"proxy_shells": 0}, b"proxy"),
-    (100, {"proxy_shells": 17, "proxy_per_shell": 128}, b"2048 proxy"),
+    (100, {"proxy_shells": 65}, b"proxy counts"),
+    (100, {"proxy_per_shell": 256, "proxy_per_shell_max": 128}, b"proxy_per_shell_max below"),
+    (100, {"proxy_shells": 64, "proxy_per_shell_max": 2048}, b"65536 proxy"),
+    (100, {"proxy_density": -1.0}, b"proxy_density"),
+    (100, {"proxy_density": float("nan")}, b"proxy_density"),
 ])
 def test_h2_build_argument_checks(n, bad, msg):
     if not os.path.exists(LIB):
