@@ -167,6 +167,25 @@ spd_status ulv_factor_ex(spd_hss_t M, int32_t precision, void* stream, spd_ulv_t
 spd_status ulv_apply(spd_ulv_t F, const double* b, double* x, int32_t nrhs,
                      int64_t ld, void* stream);
 
+/* ulv_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and result as ulv_apply (the same recorded sweeps), but
+ * every device buffer it needs (tree-order copies of b and x, the stacked
+ * rank-space blocks, launch descriptors, partial sums) lives in one static
+ * device array of SPD_NOALLOC_SCRATCH_BYTES per GPU, held until the process
+ * ends; the call makes no hipMalloc/hipFree.  Vectors need
+ * 16 * nrhs * (N + stack rows) bytes of it (spd_noalloc_bytes); larger
+ * requests fail with SPD_E_INVALID, and descriptors beyond the rest with
+ * SPD_E_NOMEM.  All calls on one GPU share that GPU's array: calls that
+ * overlap on one GPU race (serialize them).  Returns after the stream has
+ * completed the apply. */
+#define SPD_NOALLOC_SCRATCH_BYTES (64ll << 20)
+spd_status ulv_apply_noalloc(spd_ulv_t F, const double* b, double* x, int32_t nrhs, int64_t ld,
+                             void* stream);
+/* Bytes of the array that ulv_apply_noalloc's vectors take for nrhs columns
+ * (-1 for a null handle or nrhs < 1). */
+int64_t spd_noalloc_bytes(spd_ulv_t F, int32_t nrhs);
+
 /* y = A x with the H^2 representation (upward, coupling, downward and
  * near-field passes); x, y: DEVICE N x nrhs, ld >= N, original order; must not
  * alias. */

@@ -88,6 +88,7 @@ def _load():
         "ulv_factor": [vp, vp, C.POINTER(vp)],
         "ulv_factor_ex": [vp, C.c_int32, vp, C.POINTER(vp)],
         "ulv_apply": [vp, vp, vp, i32, i64, vp],
+        "ulv_apply_noalloc": [vp, vp, vp, i32, i64, vp],
         "h2_matvec": [vp, vp, vp, i32, i64, vp],
         "h2_matvec_ex": [vp, vp, vp, i32, i64, i32, vp],
         "pcg_solve": [vp, vp, vp, vp, i32, i64, dbl, i32, vp, vp, vp],
@@ -117,6 +118,8 @@ def _load():
     L.spd_server_destroy.restype = None
     L.spd_request_footprint.argtypes = [C.POINTER(_Instance)]
     L.spd_request_footprint.restype = C.c_int64
+    L.spd_noalloc_bytes.argtypes = [vp, i32]
+    L.spd_noalloc_bytes.restype = C.c_int64
     L.spd_last_error.argtypes = []
     L.spd_last_error.restype = C.c_char_p
     return L
@@ -378,6 +381,23 @@ def ulv_apply(F: ULVFactor, b: torch.Tensor, out: torch.Tensor | None = None, st
     _check_out(out, F.n, nc, ld)
     _check(lib.ulv_apply(F._h, b.data_ptr(), out.data_ptr(), nc, ld, _stream(stream)))
     return out
+
+
+def ulv_apply_noalloc(F: ULVFactor, b: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """ulv_apply that allocates no device memory (the library's fixed per-GPU
+    scratch array serves its buffers); out must be given."""
+    b, nc, ld = _as_cols(b, F.n)
+    _check_out(out, F.n, nc, ld)
+    _check(lib.ulv_apply_noalloc(F._h, b.data_ptr(), out.data_ptr(), nc, ld, _stream(stream)))
+    return out
+
+
+def noalloc_bytes(F: ULVFactor, nrhs: int) -> int:
+    """Bytes of the scratch array that ulv_apply_noalloc's vectors take."""
+    return int(lib.spd_noalloc_bytes(F._h, int(nrhs)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def h2_matvec(A: H2Matrix, x: torch.Tensor, out: torch.Tensor | None = None, stream=None,

@@ -132,6 +132,23 @@ spd_status ulv_apply(spd_ulv_t F, const double* b, double* x, int32_t nrhs, int6
   SPD_API_END
 }
 
+spd_status ulv_apply_noalloc(spd_ulv_t F, const double* b, double* x, int32_t nrhs, int64_t ld,
+                             void* stream) {
+  SPD_API_BEGIN
+  SPD_REQUIRE(F && b && x, SPD_E_INVALID, "null argument");
+  const int64_t N = F->m.f->T.N;
+  SPD_REQUIRE(nrhs >= 1 && ld >= N, SPD_E_INVALID, "bad nrhs or ld");
+  static_assert(SPD_NOALLOC_SCRATCH_BYTES == (long long)kNoAllocScratchBytes, "scratch size");
+  F->m.s = as_stream(stream);
+  ulv_apply_noalloc_impl(F->m, b, x, nrhs, ld);
+  SPD_API_END
+}
+
+int64_t spd_noalloc_bytes(spd_ulv_t F, int32_t nrhs) {
+  if (!F || nrhs < 1) return -1;
+  return ulv_noalloc_bytes(F->m, nrhs);
+}
+
 spd_status h2_matvec_ex(spd_h2_t A, const double* x, double* y, int32_t nrhs, int64_t ld,
                         int32_t precision, void* stream) {
   SPD_API_BEGIN

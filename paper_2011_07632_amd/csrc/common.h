@@ -246,6 +246,10 @@ void launch_gather_skel(hipStream_t s, const int* cand, const int* piv, int k, i
 class Arena {
  public:
   ~Arena();
+  // Hand out memory from [base, base + bytes) only (caller-owned, never freed
+  // here); a request beyond it throws SPD_E_NOMEM.  No device allocation is
+  // made in this mode.
+  void use_region(void* base, size_t bytes);
   void* get(size_t bytes);
   template <class T>
   T* get_n(size_t n) { return static_cast<T*>(get(n * sizeof(T))); }
@@ -257,6 +261,7 @@ class Arena {
   char* cur_ = nullptr;
   size_t left_ = 0;
   size_t used_ = 0;
+  bool region_ = false;
 };
 
 // Upload a host vector into arena memory (synchronous w.r.t. the host data).

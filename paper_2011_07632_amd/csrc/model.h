@@ -275,6 +275,11 @@ struct ULVModel {
 
 void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s);
 void ulv_apply_tree(ULVModel& U, const double* b, double* x, int ncols);
+// The apply with every device buffer in a fixed per-GPU array of
+// kNoAllocScratchBytes (see solve.cpp); b and x as for ulv_apply.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+int64_t ulv_noalloc_bytes(const ULVModel& U, int ncols);
+void ulv_apply_noalloc_impl(ULVModel& U, const double* b, double* x, int ncols, int64_t ld);
 // apply plan buffers: ulv_plan_in is read and ulv_plan_out written in place
 double* ulv_plan_in(ULVModel& U, int m);
 double* ulv_plan_out(ULVModel& U, int m);

@@ -66,7 +66,21 @@ void release_cached_chunks() {
 
 Arena::~Arena() { release(); }
 
+void Arena::use_region(void* base, size_t bytes) {
+  release();
+  region_ = true;
+  cur_ = static_cast<char*>(base);
+  left_ = bytes;
+}
+
 void Arena::release() {
+  if (region_) {
+    region_ = false;
+    cur_ = nullptr;
+    left_ = 0;
+    used_ = 0;
+    return;
+  }
   for (auto& c : chunks_) {
     if (c.second == kChunk) give_chunk(c.first);
     else (void)hipFree(c.first);
@@ -80,6 +94,16 @@ void Arena::release() {
 void* Arena::get(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
   if (bytes == 0) bytes = 256;
+  if (region_) {
+    if (bytes > left_)
+      throw Error(SPD_E_NOMEM, "scratch region exhausted (" + std::to_string(used_ + bytes) +
+                                   " bytes needed, " + std::to_string(used_ + left_) + " available)");
+    void* r = cur_;
+    cur_ += bytes;
+    left_ -= bytes;
+    used_ += bytes;
+    return r;
+  }
   if (bytes > left_) {
     const size_t sz = bytes > kChunk / 4 ? bytes : kChunk;
     void* p = nullptr;

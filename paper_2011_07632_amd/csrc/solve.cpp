@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 
 namespace spd {
 
@@ -171,8 +172,13 @@ void ulv_factor_impl(HSSModel& M, ULVModel& U, hipStream_t s) {
 // columns every product is a dot-form product (transposed storage: Z_v for
 // Z_v^T, Z_v^T for Z_v, and the symmetric Dm_v for itself), whose lanes run
 // down stored columns; with more columns the same products run on MFMA.
-static void build_apply_plan(ULVModel& U, int m) {
+// region: the plan's buffers, descriptors and partial results come from
+// [region, region + region_bytes) only (no device allocation), else from the
+// plan's own arena.
+static std::unique_ptr<ULVModel::ApplyPlan> make_apply_plan(ULVModel& U, int m, void* region = nullptr,
+                                                            size_t region_bytes = 0) {
   auto pl = std::make_unique<ULVModel::ApplyPlan>();
+  if (region) pl->arena.use_region(region, region_bytes);
   pl->ncols = m;
   Factors& F = *U.f;
   const TreeHost& T = F.T;
@@ -202,8 +208,7 @@ static void build_apply_plan(ULVModel& U, int m) {
     g.term(op(F.Dm, F.Dm32, 0), Ni, pl->in, Ni, Ni);
     rec.gemm(a, s, g);
     SPD_HIP(hipStreamSynchronize(s));
-    U.plan = std::move(pl);
-    return;
+    return pl;
   }
   const int64_t rows = std::max<int64_t>(F.stack_rows, 1);
   pl->ts = a.get_n<double>((size_t)rows * m);
@@ -268,8 +273,10 @@ static void build_apply_plan(ULVModel& U, int m) {
     rec.gemm(a, s, g);
   }
   SPD_HIP(hipStreamSynchronize(s));
-  U.plan = std::move(pl);
+  return pl;
 }
+
+static void build_apply_plan(ULVModel& U, int m) { U.plan = make_apply_plan(U, m); }
 
 double* ulv_plan_in(ULVModel& U, int m) {
   if (!U.plan || U.plan->ncols != m) {
@@ -282,6 +289,56 @@ double* ulv_plan_in(ULVModel& U, int m) {
 double* ulv_plan_out(ULVModel& U, int m) {
   ulv_plan_in(U, m);
   return U.plan->out;
+}
+
+// ------------------------------------------------------ allocation-free apply --
+// A fixed device array per GPU for the variant of the apply that allocates
+// nothing: its tree-order right-hand sides and solution, the stacked rank-space
+// blocks, the launch descriptors and any partial results all live here.  Every
+// call on a device shares that device's copy, so calls that overlap on one
+// GPU race; nothing in it has to start at zero (every block is written before
+// it is read).
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+// The array's device address, taken once per device with that device current
+// (the host-side name is only a stand-in for the symbol, not an address).
+static char* scratch_address() {
+  static std::mutex mu;
+  static char* addr[64] = {};
+  int dev = 0;
+  SPD_HIP(hipGetDevice(&dev));
+  SPD_REQUIRE(dev >= 0 && dev < 64, SPD_E_DEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error(SPD_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    addr[dev] = static_cast<char*>(p);
+  }
+  return addr[dev];
+}
+
+int64_t ulv_noalloc_bytes(const ULVModel& U, int m) {
+  const Factors& F = *U.f;
+  const int64_t rows = std::max<int64_t>(F.stack_rows, 1);
+  return 8 * ((int64_t)2 * F.T.N * m + (F.T.L > 1 ? 2 * rows * m : 0));
+}
+
+void ulv_apply_noalloc_impl(ULVModel& U, const double* b, double* x, int m, int64_t ld) {
+  const int64_t need = ulv_noalloc_bytes(U, m);
+  SPD_REQUIRE(need <= (int64_t)kNoAllocScratchBytes, SPD_E_INVALID,
+              "allocation-free apply: " + std::to_string(need) + " bytes of vectors exceed the " +
+                  std::to_string(kNoAllocScratchBytes) + "-byte scratch array (use fewer right-hand sides)");
+  char* base = scratch_address();
+  auto pl = make_apply_plan(U, m, base, kNoAllocScratchBytes);
+  const Factors& F = *U.f;
+  const int64_t N = F.T.N;
+  hipStream_t s = U.s;
+  launch_gather_rows(s, b, ld, pl->in, N, F.perm_d, N, m);
+  pl->rec.replay(s);
+  launch_scatter_rows(s, pl->out, N, x, ld, F.perm_d, N, m);
+  SPD_HIP(hipStreamSynchronize(s));
 }
 
 void ulv_apply_tree(ULVModel& U, const double* b, double* x, int m) {
