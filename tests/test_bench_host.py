@@ -58,12 +58,16 @@ def test_traffic_only_for_the_recorded_sources(tmp_path, monkeypatch):
     assert bench.recorded_traffic(w, "coupling") is None  # sources changed since the counters
 
 
-def test_default_workload_is_the_100k_matern_configuration():
-    # the metric's configuration: 100,000 uniform cube points, Matern-3/2 with
-    # l = 0.1 plus 1e-4 I, leaf 200, H^2 tolerance 1e-8, HSS tolerance 1e-2,
-    # one N(0,1) right-hand side, PCG to 1e-8
-    w = bench.workloads.MEDIUM
-    assert (w.n, w.point_set, w.kernel, w.ell, w.shift, w.leaf, w.h2_tol, w.hss_tol, w.nrhs, w.pcg_tol) == \
-        (100_000, "cube", "matern32", 0.1, 1e-4, 200, 1e-8, 1e-2, 1, 1e-8)
+def test_default_workload_is_the_1m_gaussian_configuration():
+    # the metric's size: 1,000,000 uniform cube points, Gaussian with l = 0.2
+    # plus 1e-3 I, leaf 400, 16 N(0,1) right-hand sides, PCG to 1e-8; with the
+    # two stated changes eps_H 1e-6 -> 1e-8 and (tau, r) (1e-1, 100) -> (1e-2, 200)
+    w = bench.workloads.HEADLINE
+    assert (w.n, w.point_set, w.kernel, w.ell, w.shift, w.leaf, w.nrhs, w.pcg_tol) == \
+        (1_000_000, "cube", "gaussian", 0.2, 1e-3, 400, 16, 1e-8)
+    assert (w.h2_tol, w.hss_tol, w.max_rank, w.oversample) == (1e-8, 1e-2, 200, 10)
+    L = bench.workloads.LARGE
+    assert (L.n, L.kernel, L.ell, L.shift, L.leaf, L.h2_tol, L.hss_tol, L.nrhs) == \
+        (1_000_000, "gaussian", 0.2, 1e-3, 400, 1e-6, 1e-1, 16)
     src = open(os.path.join(ROOT, "bench.py")).read()
-    assert 'ap.add_argument("--workload", default=workloads.MEDIUM.name' in src
+    assert 'ap.add_argument("--workload", default=workloads.HEADLINE.name' in src
