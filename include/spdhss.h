@@ -209,11 +209,12 @@ spd_status h2_matvec_ex(spd_h2_t A, const double* x, double* y, int32_t nrhs,
  * iters, relres: HOST arrays of nrhs entries (may be NULL): iterations taken
  * and the true relative residual ||b - A x|| / ||b|| at exit.
  * A column whose recursively updated residual reaches rtol while its true
- * residual is above 10 rtol (they drift apart on ill-conditioned systems)
- * restarts from the true residual, at most 4 times, within maxit (residual
- * replacement; the paper's PCG stops at the recursive residual).
+ * residual is still above rtol (they drift apart on ill-conditioned systems)
+ * continues from the true residual, at most 4 times, within maxit (residual
+ * replacement; the paper's PCG stops at the recursive residual), so that a
+ * converged column meets rtol on its true residual.
  * Returns SPD_E_NOT_CONVERGED if some column did not reach rtol in maxit, or
- * its true residual stayed above 10 rtol. */
+ * its true residual stayed above rtol. */
 spd_status pcg_solve(spd_h2_t A, spd_ulv_t M, const double* b, double* x,
                      int32_t nrhs, int64_t ld, double rtol, int32_t maxit,
                      void* stream, int32_t* iters, double* relres);

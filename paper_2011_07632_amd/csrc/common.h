@@ -165,7 +165,7 @@ void launch_to_f32(hipStream_t s, const CvtProblem* d_p, int nprob);
 void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
                  int max_n, int cap = 0, int a_f32 = 0);
 // rows per workgroup of launch_symv for a launch whose largest problem has max_m rows
-int symv_row_tile(int max_m);
+int symv_row_tile(int max_m, int ncols);
 // max_k bounds the terms' inner dimension (used to pick the dot-form variant
 // when transA is set and there are at most 4 columns)
 // a_f32: the A operands are FP32 (dot-form product only)

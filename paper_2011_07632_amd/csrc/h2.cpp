@@ -494,6 +494,10 @@ static void build_plan(H2Model& H, int m, bool f32 = false) {
   // (downward) of the vector, and only E_v is streamed, as dot products down
   // the columns of E_v^T (upward) or E_v (downward).
   const bool eform = m <= 4;
+  // with up to 16 columns the coupling and near-field blocks are read once
+  // for both products of a symmetric pair (k_symv up to 4 columns, the MFMA
+  // form k_symm16 above)
+  const bool sym = m <= 16;
   if (L > 1) {
     // upward: x-hat_v = W_v^T x_v (leaf) or W_v^T [x-hat_c1; x-hat_c2]
     //         = x[Pi_v(0:k)] + E_v x[Pi_v(k:cand)]
@@ -516,10 +520,10 @@ static void build_plan(H2Model& H, int m, bool f32 = false) {
       rec.gemm(a, s, g);
       rec.tag_from(first, 100 + lev);
     }
-    // coupling: y-hat_v = sum_j B_vj x-hat_j.  With at most 4 columns the
+    // coupling: y-hat_v = sum_j B_vj x-hat_j.  With at most 16 columns the
     // blocks B_vj with j > v are read once for both B_vj x-hat_j and
     // B_jv x-hat_v = B_vj^T x-hat_v (B^{H2} is symmetric: B_jv = B_vj^T).
-    if (m <= 4) {
+    if (sym) {
       std::vector<SymRow> rows;
       std::vector<int> row_of(T.nnodes, -1);
       for (int v = 1; v < T.nnodes; ++v) {
@@ -621,6 +625,30 @@ static void build_plan(H2Model& H, int m, bool f32 = false) {
       SPD_HIP(hipEventCreateWithFlags(&H.ev_fork, hipEventDisableTiming));
       SPD_HIP(hipEventCreateWithFlags(&H.ev_join, hipEventDisableTiming));
     }
+  } else if (sym) {
+    // far-field part of y at the leaves, y_v = W_v y-hat_v, then the near
+    // field by symmetric pairs added onto it
+    GemmBatch g(0, 0);
+    for (int v = lf; v < lf + lc; ++v) {
+      g.add(pl->yt + T.start[v], (int)T.size(v), m, (int)N);
+      if (L > 1 && H.k[v] > 0) g.term(H.W[v], H.cand[v], H.hat(pl->yh, v, m), H.hat_ld(v), H.k[v]);
+    }
+    size_t first = rec.recs.size();
+    rec.gemm(a, s, g);
+    std::vector<SymRow> rows;
+    for (int v = lf; v < lf + lc; ++v)
+      rows.push_back(SymRow{pl->yt + T.start[v], (int)N, pl->xt + T.start[v], (int)N, (int)T.size(v), {}});
+    for (int v = lf; v < lf + lc; ++v) {
+      SymRow& R = rows[v - lf];
+      for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) {
+        const int j = T.near_idx[e];
+        if (j < v) continue;
+        R.terms.push_back({H.nearA[e], std::max(H.near_ld(v), 16), pl->xt + T.start[j], (int)N,
+                           (int)T.size(j), j == v ? -1 : j - lf});
+      }
+    }
+    rec.symv(a, s, rows, m, 1.0, false);
+    rec.tag_from(first, 400);
   } else {
     GemmBatch g(0, 0);
     for (int v = lf; v < lf + lc; ++v) {

@@ -687,7 +687,10 @@ __global__ __launch_bounds__(64 * NW) void k_symv(const SymProblem* __restrict__
   }
 }
 
-int symv_row_tile(int max_m) { return max_m <= 64 ? 64 : (max_m <= 128 ? 128 : 256); }
+int symv_row_tile(int max_m, int ncols) {
+  if (ncols > 4) return 256;
+  return max_m <= 64 ? 64 : (max_m <= 128 ? 128 : 256);
+}
 
 template <int NC, int NW, typename TA>
 static void launch_symv_nw(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
@@ -725,10 +728,177 @@ static void launch_symv_ta(hipStream_t s, const SymProblem* d_p, const SymTerm* 
   else launch_symv_nc<4, TA>(s, d_p, d_t, nprob, max_m, cap);
 }
 
+// Symmetric-pair product for 5 to 16 right-hand columns on FP64 MFMA
+// (v_mfma_f64_16x16x4f64; lane l holds A[l%16][l/16] and B[l/16][l%16], and
+// element v of the result D[l/16 + 4v][l%16]).  Same descriptors and outputs
+// as k_symv: a work item is (problem, tile of 256 rows); wave w owns rows
+// 64w..64w+63 of the tile and walks every term's columns in chunks of 16:
+//   row sums:  C[rows] += A[rows, chunk] B[chunk, :]        (16 MFMAs)
+//   mirrored:  P[chunk, :] = A[rows, chunk]^T X[rows, :]     (16 MFMAs per wave,
+//              the four waves' parts summed in wave order through LDS)
+// The mirrored product contracts over rows, so each wave transposes its
+// 64 x 16 chunk through its own LDS slot before the second set of MFMAs.
+// Every block element is read from HBM once.  Columns past n are zero in the
+// inputs and not written.
+__global__ __launch_bounds__(256) void k_symm16(const SymProblem* __restrict__ probs,
+                                                const SymTerm* __restrict__ terms, int tiles_max,
+                                                int nwork, int nprob) {
+  __shared__ double tr[4][64][17];      // per-wave transpose slot: rows x chunk columns
+  __shared__ double red[2][4][16][17];  // per-wave mirrored partials, two chunks in flight
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  int buf = 0;
+  for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
+    const int x8 = item & 7, rest = item >> 3;
+    const int tile = rest % tiles_max, p = (rest / tiles_max) * 8 + x8;
+    if (p >= nprob) continue;
+    const SymProblem P = probs[p];
+    const int i0 = tile * 256;
+    if (i0 >= P.m || P.n <= 0) continue;
+    const int n = P.n, m = P.m;
+    const int r0 = i0 + 64 * w;  // this wave's first row
+    const bool colok = lr < n;
+    // the mirrored product's right operand: this wave's own input rows,
+    // X[r0 + 4r + l/16][l%16] for row quads r = 0..15
+    double xop[16];
+    {
+      gdouble* Xg = (gdouble*)P.X;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = r0 + 4 * r + lk;
+        const double mk = (row < m && colok) ? 1.0 : 0.0;
+        xop[r] = Xg[(row < m ? row : m - 1) + (int64_t)(colok ? lr : 0) * P.ldx] * mk;
+      }
+    }
+    d4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int t = P.term_begin; t < P.term_end; ++t) {
+      const SymTerm T = terms[t];
+      const int K = T.k;
+      if (K <= 0) continue;
+      const int64_t lda = T.lda, ldb = T.ldb;
+      const double sc = T.scale;
+      double* pt = T.P ? T.P + (int64_t)tile * P.ptile : nullptr;
+      // A chunk's operands: A[r0 + 16s + l%16][c0 + 4q + l/16] and
+      // B[c0 + 4q + l/16][l%16], loaded from addresses clamped into the block
+      // and used unmasked except for B's columns past K, which are zeroed
+      // when the chunk is multiplied (not when it is loaded, so that its loads
+      // stay in flight meanwhile).  Nothing else needs a mask: rows past m
+      // meet zero rows of X in the mirrored product and give row sums that are
+      // never stored, and columns past K give mirrored entries that are never
+      // stored; values of columns past n reach only outputs that are never
+      // stored.
+      gdouble* Ag = (gdouble*)T.A;
+      gdouble* Bg = (gdouble*)T.B;
+      int rowc[4];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int row = r0 + 16 * s4 + lr;
+        rowc[s4] = row < m ? row : m - 1;
+      }
+      const int lrc = colok ? lr : 0;
+      auto load = [&](int c0, double (&ra)[4][4], double (&rb)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int col = c0 + 4 * q + lk;
+          const int64_t cc = col < K ? col : K - 1;
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) ra[s4][q] = __builtin_nontemporal_load(Ag + cc * lda + rowc[s4]);
+          rb[q] = Bg[cc + (int64_t)lrc * ldb];
+        }
+      };
+      auto process = [&](int c0, const double (&ca)[4][4], const double (&cb)[4]) {
+        double bs[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bs[q] = (c0 + 4 * q + lk < K) ? sc * cb[q] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4)
+            acc[s4] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[s4][q], bs[q], acc[s4], 0, 0, 0);
+        if (!pt) return;  // uniform across the workgroup (per term)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) tr[w][16 * s4 + lr][4 * q + lk] = ca[s4][q];
+        // LDS-only ordering: the prefetched global loads of the next chunk
+        // stay in flight (a full fence would wait for them)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        // four independent accumulation chains over the row quads
+        d4 pa[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pa[u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          pa[r & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(tr[w][4 * r + lk][lr], xop[r], pa[r & 3], 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          red[buf][w][lk + 4 * v][lr] = (pa[0][v] + pa[1][v]) + (pa[2][v] + pa[3][v]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        // 256 outputs of the chunk, 64 per wave: the four waves summed in order
+        const int e = 64 * w + lane;
+        const int kk = e >> 4, c = e & 15;
+        const double v =
+            ((red[buf][0][kk][c] + red[buf][1][kk][c]) + red[buf][2][kk][c]) + red[buf][3][kk][c];
+        if (c0 + kk < K && c < n) pt[c0 + kk + (int64_t)c * P.ldp] = sc * v;
+        buf ^= 1;
+      };
+      // two operand buffers in turn: the next chunk loads while one
+      // multiplies.  The loads are issued unconditionally (clamped past the
+      // term's end, at most one wasted chunk per term) so that every path
+      // into a multiplication has the same loads in flight and the wait
+      // before it covers only its own chunk.
+      double a0[4][4], b0[4], a1[4][4], b1[4];
+      load(0, a0, b0);
+      for (int c0 = 0; c0 < K; c0 += 32) {
+        load(c0 + 16, a1, b1);
+        process(c0, a0, b0);
+        if (c0 + 16 >= K) break;
+        load(c0 + 32, a0, b0);
+        process(c0 + 16, a1, b1);
+      }
+    }
+    // row sums: D[l/16 + 4v][l%16] of strip s is row r0 + 16s + l/16 + 4v, column l%16
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * s4 + lk + 4 * v;
+        if (row < m && colok) {
+          double* cp = P.C + row + (int64_t)lr * P.ldc;
+          double val = P.alpha * acc[s4][v];
+          if (P.beta != 0.0) val += P.beta * (*cp);
+          *cp = val;
+        }
+      }
+  }
+}
+
+static void launch_symm16(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
+                          int max_m, int cap) {
+  const int tiles = ceil_div(max_m, 256);
+  const int nwork = ceil_div(nprob, 8) * 8 * tiles;
+  const int capped = cap > 0 ? std::max(8, cap / 8 * 8) : nwork;
+  hipLaunchKernelGGL(k_symm16, dim3((unsigned)std::min(capped, nwork)), dim3(256), 0, s, d_p, d_t,
+                     tiles, nwork, nprob);
+}
+
 void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
                  int max_n, int cap, int a_f32) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
-  if (max_n > 4) throw Error(SPD_E_INVALID, "symmetric-pair product supports at most 4 columns");
+  if (max_n > 16) throw Error(SPD_E_INVALID, "symmetric-pair product supports at most 16 columns");
+  if (max_n > 4) {
+    if (a_f32) throw Error(SPD_E_INVALID, "FP32 blocks in the symmetric product only up to 4 columns");
+    launch_symm16(s, d_p, d_t, nprob, max_m, cap);
+    SPD_HIP(hipGetLastError());
+    return;
+  }
   if (a_f32) launch_symv_ta<float>(s, d_p, d_t, nprob, max_m, max_n, cap);
   else launch_symv_ta<double>(s, d_p, d_t, nprob, max_m, max_n, cap);
   SPD_HIP(hipGetLastError());

@@ -446,7 +446,7 @@ void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, in
   int max_m = 0;
   for (const SymRow& R : rows) max_m = std::max(max_m, R.m);
   if (max_m == 0) return;
-  const int tile = symv_row_tile(max_m);
+  const int tile = symv_row_tile(max_m, n);
   std::vector<SymProblem> probs;
   std::vector<SymTerm> terms;
   // contributions to each row's output, in order: (source, leading dimension)

@@ -538,11 +538,13 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   };
   iterate();
   true_residual();
-  // Residual replacement (beyond the paper): a column whose recursively updated
-  // residual met rtol while its true residual is above kRestartFactor * rtol
-  // (the two drift apart on ill-conditioned systems) restarts from the true
-  // residual, within maxit and at most kMaxRestarts times.
-  constexpr double kRestartFactor = 10.0;
+  // Residual replacement (beyond the paper, whose PCG stops on the recursively
+  // updated residual): a column whose recursive residual met rtol while its
+  // true residual is still above rtol (the two drift apart on ill-conditioned
+  // systems) continues from the true residual, within maxit and at most
+  // kMaxRestarts times, so that a converged result meets rtol on the true
+  // residual.
+  constexpr double kRestartFactor = 1.0;
   constexpr int kMaxRestarts = 4;
   for (int restart = 0; restart < kMaxRestarts && done < maxit; ++restart) {
     std::vector<int> act(m + 1, 0);

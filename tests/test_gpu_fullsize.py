@@ -85,12 +85,14 @@ def test_matvec_rows_against_kernel(F):
 
 def test_symmetric_and_batched_products_agree(F):
     rng = np.random.default_rng(12)
-    x = rng.standard_normal((W.n, 5))
-    y5 = F.B.h2_matvec(F.h2, cols(F, x)).cpu().numpy()
-    for c in (0, 3):
+    x = rng.standard_normal((W.n, 17))
+    y16 = F.B.h2_matvec(F.h2, cols(F, x[:, :16])).cpu().numpy()   # symmetric pairs on MFMA
+    y17 = F.B.h2_matvec(F.h2, cols(F, x)).cpu().numpy()           # every block, MFMA GEMM
+    for c in (0, 3, 15):
         y1 = F.B.h2_matvec(F.h2, cols(F, x[:, c:c + 1])).cpu().numpy()[:, 0]
-        d = np.linalg.norm(y1 - y5[:, c]) / np.linalg.norm(y5[:, c])
-        assert d <= 1e-13, (c, d)
+        for y in (y16, y17):
+            d = np.linalg.norm(y1 - y[:, c]) / np.linalg.norm(y[:, c])
+            assert d <= 1e-13, (c, d)
 
 
 def test_preconditioner_symmetric_positive(F):

@@ -138,8 +138,8 @@ def test_h2_skeletons_exact(P):
 
 
 # 1-4 columns take the symmetric-pair streaming product (1, 2 and 4-column
-# kernels), 5 the batched MFMA product
-@pytest.mark.parametrize("nrhs", [1, 2, 3, 5])
+# kernels), 5 and 16 the symmetric-pair MFMA product
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 5, 16])
 def test_h2_matvec(P, nrhs):
     rng = np.random.default_rng(1)
     x = rng.standard_normal((P.w.n, nrhs))
@@ -200,6 +200,20 @@ def test_pcg_fixed_iterations(P):
         assert rel(x.cpu().numpy(), xo) <= TOL
 
 
+def test_pcg_fixed_iterations_16_columns(P):
+    """16 right-hand sides (the N = 1M workload's width): the MFMA symmetric-pair
+    product, the MFMA apply and the per-column recurrences against the oracle
+    at fixed iteration counts."""
+    b = workloads.gaussian_matrix(P.w.n, 16, 2016)
+    bg = P.B.cols_like(P.w.n, 16, "cuda").copy_(torch.from_numpy(b))
+    x, it, _ = P.B.pcg_solve(P.g_h2, P.g_ulv, bg, rtol=0.0, maxit=4, raise_on_nonconvergence=False)
+    xo_t, ito, _ = opcg(P.o_h2.matvec, P.o_hss.solve, b[P.T.perm], 0.0, 4)
+    xo = np.empty_like(b)
+    xo[P.T.perm] = xo_t
+    assert it.tolist() == ito.tolist()
+    assert rel(x.cpu().numpy(), xo) <= TOL
+
+
 def test_pcg_converges_like_oracle(P):
     """Same stopping behaviour as the oracle: equal iteration counts (within one
     for rounding at the threshold) and, when the oracle converges, a true
@@ -210,7 +224,13 @@ def test_pcg_converges_like_oracle(P):
     x, it, res = P.B.pcg_solve(P.g_h2, P.g_ulv, bg, rtol=P.w.pcg_tol, maxit=maxit,
                                raise_on_nonconvergence=False)
     _, ito, reso = opcg(P.o_h2.matvec, P.o_hss.solve, b[P.T.perm], P.w.pcg_tol, maxit)
-    assert np.abs(it - ito).max() <= 1
+    # the oracle stops on the recursive residual (the paper's PCG); the library
+    # then also requires the true residual to meet rtol and otherwise continues
+    # from it, so where the oracle's true residual is above rtol the library
+    # may take more iterations
+    strict = reso <= P.w.pcg_tol
+    assert np.abs(it - ito)[strict].max(initial=0) <= 1
+    assert (it >= ito - 1).all()
     if (ito < maxit).all():
         assert (res <= 2 * P.w.pcg_tol).all()
     print(f"[parity] iterations gpu={it.tolist()} oracle={ito.tolist()} relres={res.tolist()} "
