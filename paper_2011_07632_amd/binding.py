@@ -14,9 +14,8 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# SPDHSS_LIB points the binding at another build of the same library
-# (development A/B comparisons); by default the in-tree build is loaded.
-LIB_PATH = os.environ.get("SPDHSS_LIB", os.path.join(HERE, "libspdhss.so"))
+# the in-tree build; importing without it raises (there is no fallback)
+LIB_PATH = os.path.join(HERE, "libspdhss.so")
 
 KERNELS = {"gaussian": 0, "matern32": 1, "exponential": 2, "imq": 3}
 

@@ -446,8 +446,10 @@ PcgResult pcg_tree(H2Model& H, ULVModel* U, const double* bt, double* xt, int m,
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  bool use_graph = getenv("SPDHSS_NO_GRAPH") == nullptr;
-  if (use_graph) {
+  // the iteration runs as a captured graph; if capture is not available on
+  // the stream (or instantiation fails) the same launches run eagerly
+  bool use_graph = true;
+  {
     SPD_HIP(hipStreamSynchronize(s));
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
       body();

@@ -191,11 +191,16 @@ def test_request_points_are_checked_before_any_device_use():
 
 
 def test_import_fails_loudly_without_the_library(tmp_path):
-    """No CPU fallback: without the built library the package does not import."""
+    """No CPU fallback: without the built library the package does not import
+    (a copy of the package's Python files with no libspdhss.so beside them)."""
+    import shutil
     import subprocess
     import sys
-    env = dict(os.environ, SPDHSS_LIB=str(tmp_path / "missing" / "libspdhss.so"))
-    r = subprocess.run([sys.executable, "-c", "import paper_2011_07632_amd"], cwd=ROOT, env=env,
+    pkg = tmp_path / "paper_2011_07632_amd"
+    pkg.mkdir()
+    for f in ("__init__.py", "binding.py"):
+        shutil.copy(os.path.join(ROOT, "paper_2011_07632_amd", f), pkg / f)
+    r = subprocess.run([sys.executable, "-c", "import paper_2011_07632_amd"], cwd=tmp_path,
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "not built" in r.stderr

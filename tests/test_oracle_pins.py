@@ -371,6 +371,21 @@ def test_pcg_matches_scipy_cg(h2s, hss):
     assert res[0] <= 1e-8 * 1.5
 
 
+def test_matvec_error_closed_forms():
+    """Section 6.1's metric (mean relative 2-norm error over Gaussian vectors)
+    on products whose error is known exactly: a product scaled by (1 + d)
+    errs by |d| on every vector; one that scales vector j by (1 + d_j) errs by
+    the mean of |d_j|; the exact product errs by 0."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((40, 40))
+    ref = lambda X: A @ X  # noqa: E731
+    assert matvec_error(ref, ref, 40, nvec=10, seed=1) == 0.0
+    assert matvec_error(ref, lambda X: 1.25 * (A @ X), 40, nvec=10, seed=1) == pytest.approx(0.25, rel=1e-14)
+    d = np.linspace(-0.3, 0.5, 10)
+    err = matvec_error(ref, lambda X: (A @ X) * (1.0 + d)[None, :], 40, nvec=10, seed=1)
+    assert err == pytest.approx(np.abs(d).mean(), rel=1e-14)
+
+
 def test_matvec_error_on_order_of_tau():
     """Sanity range only (parity unpinned): with the threshold form the HSS
     matvec error vs the H^2 product is of the order of tau (Table 4 reports
