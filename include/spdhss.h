@@ -400,6 +400,16 @@ spd_status spd_h2_time_launches(spd_h2_t A, int32_t nrhs, int32_t reps, void* st
 spd_status spd_test_gemm(const double* A, const double* B, double* C, int32_t batch,
                          int32_t m, int32_t n, int32_t k, int32_t transA,
                          int32_t transB, double alpha, double beta, void* stream);
+/* Y = S X for the block-cyclic symmetric matrix S with nblk block rows of m
+ * rows: row i holds nterm blocks A_it (m x m, column-major, ld m, stored at
+ * A + (i*nterm + t)*m*m), S_ij = A_it and S_ji = A_it^T for j = (i+1+t) mod
+ * nblk, zero elsewhere (nblk >= 2*nterm+1, so no pair repeats).  X and Y are
+ * nblk*m x n (ld nblk*m), 1 <= n <= 16: the symmetric-pair product of the H^2
+ * matvec on a synthetic layout.  With reps >= 1 the product launch is then
+ * replayed reps times alone and *ms receives its average time. */
+spd_status spd_test_symm(const double* A, const double* X, double* Y, int32_t nblk,
+                         int32_t m, int32_t nterm, int32_t n, int32_t reps, void* stream,
+                         double* ms);
 /* in-place lower Cholesky of batch n x n matrices; fail[b] = 1 if not SPD */
 spd_status spd_test_chol(double* A, int32_t batch, int32_t n, int32_t* fail, void* stream);
 /* B_b <- op(L_b)^{-1} B_b (lower L; upper = 1 reads L as upper triangular) */

@@ -97,6 +97,7 @@ def _load():
         "spd_h2_time_near": [vp, i32, i32, vp, vp, vp],
         "spd_h2_time_launches": [vp, i32, i32, vp, vp, vp, vp, i32, vp],
         "spd_test_gemm": [vp, vp, vp, i32, i32, i32, i32, i32, i32, dbl, dbl, vp],
+        "spd_test_symm": [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp],
         "spd_test_chol": [vp, i32, i32, vp, vp],
         "spd_test_trsm": [vp, vp, i32, i32, i32, i32, i32, vp],
         "spd_test_cpqr": [vp, vp, vp, vp, vp, i32, i32, i32, i32, dbl, i32, vp],
@@ -470,6 +471,17 @@ def test_gemm(A, B, C_, transA=0, transB=0, alpha=1.0, beta=0.0):
     k = A.shape[1] if not transA else A.shape[2]
     _check(lib.spd_test_gemm(A.data_ptr(), B.data_ptr(), C_.data_ptr(), batch, m, n, k, transA, transB,
                              alpha, beta, _stream()))
+
+
+def test_symm(A, X, Y, nblk, m, nterm, reps=0):
+    """Y = S X for the block-cyclic symmetric layout of spd_test_symm (A holds
+    nblk * nterm blocks of m x m, X and Y are (ncols, nblk * m)); with reps
+    >= 1 returns the product launch's average time in ms."""
+    n = X.shape[0]
+    ms = C.c_double(0.0)
+    _check(lib.spd_test_symm(A.data_ptr(), X.data_ptr(), Y.data_ptr(), int(nblk), int(m), int(nterm), n,
+                             int(reps), _stream(), C.byref(ms) if reps > 0 else None))
+    return ms.value
 
 
 def test_chol(A, fail):

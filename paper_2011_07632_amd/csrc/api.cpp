@@ -378,6 +378,48 @@ spd_status spd_test_gemm(const double* A, const double* B, double* C, int32_t ba
   SPD_API_END
 }
 
+spd_status spd_test_symm(const double* A, const double* X, double* Y, int32_t nblk, int32_t m,
+                         int32_t nterm, int32_t n, int32_t reps, void* stream, double* ms) {
+  SPD_API_BEGIN
+  SPD_REQUIRE(A && X && Y && nblk >= 1 && m >= 1 && nterm >= 0 && n >= 1 && n <= 16 && reps >= 0,
+              SPD_E_INVALID, "bad args");
+  SPD_REQUIRE(nblk >= 2 * nterm + 1, SPD_E_INVALID, "nblk must be at least 2 nterm + 1");
+  SPD_REQUIRE((int64_t)nblk * m <= (1ll << 30), SPD_E_INVALID, "nblk m above 2^30 rows");
+  SPD_REQUIRE(reps == 0 || ms, SPD_E_INVALID, "null time output");
+  hipStream_t s = as_stream(stream);
+  const int ld = nblk * m;
+  std::vector<SymRow> rows(nblk);
+  for (int i = 0; i < nblk; ++i) {
+    rows[i] = SymRow{Y + (size_t)i * m, ld, X + (size_t)i * m, ld, m, {}};
+    for (int t = 0; t < nterm; ++t) {
+      const int j = (i + 1 + t) % nblk;
+      rows[i].terms.push_back({A + ((size_t)i * nterm + t) * m * m, m, X + (size_t)j * m, ld, m, j});
+    }
+  }
+  Arena a;
+  Recorder rec;
+  rec.symv(a, s, rows, n, 0.0, false);
+  rec.replay(s);
+  if (reps > 0 && !rec.recs.empty()) {
+    Recorder one;
+    one.recs.push_back(rec.recs[0]);
+    hipEvent_t e0, e1;
+    SPD_HIP(hipEventCreate(&e0));
+    SPD_HIP(hipEventCreate(&e1));
+    SPD_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) one.replay(s);
+    SPD_HIP(hipEventRecord(e1, s));
+    SPD_HIP(hipEventSynchronize(e1));
+    float t = 0;
+    SPD_HIP(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t / reps;
+  }
+  SPD_HIP(hipStreamSynchronize(s));
+  SPD_API_END
+}
+
 spd_status spd_test_chol(double* A, int32_t batch, int32_t n, int32_t* fail, void* stream) {
   SPD_API_BEGIN
   SPD_REQUIRE(A && fail && batch >= 1 && n >= 1 && n <= 1024, SPD_E_INVALID, "bad args");

@@ -731,19 +731,72 @@ static void launch_symv_ta(hipStream_t s, const SymProblem* d_p, const SymTerm* 
 // Symmetric-pair product for 5 to 16 right-hand columns on FP64 MFMA
 // (v_mfma_f64_16x16x4f64; lane l holds A[l%16][l/16] and B[l/16][l%16], and
 // element v of the result D[l/16 + 4v][l%16]).  Same descriptors and outputs
-// as k_symv: a work item is (problem, tile of 256 rows); wave w owns rows
-// 64w..64w+63 of the tile and walks every term's columns in chunks of 16:
+// as k_symv: a work item is (problem, tile of up to 256 rows).  The tile's
+// rows are cut into R strips of 64 (R = 1, 2 or 4, the fewest that cover
+// them) and the four waves into R x G with G = 4 / R: wave (s, g) takes strip
+// s and every G-th chunk of 16 columns starting at chunk g, so that short
+// tiles keep all four waves on rows that exist.  Per chunk:
 //   row sums:  C[rows] += A[rows, chunk] B[chunk, :]        (16 MFMAs)
 //   mirrored:  P[chunk, :] = A[rows, chunk]^T X[rows, :]     (16 MFMAs per wave,
-//              the four waves' parts summed in wave order through LDS)
+//              the R strips' parts summed in strip order through LDS)
 // The mirrored product contracts over rows, so each wave transposes its
-// 64 x 16 chunk through its own LDS slot before the second set of MFMAs.
+// 64 x 16 chunk through its own LDS slot before the second set of MFMAs.  The
+// G groups' row sums are added in group order at the end of the item.
 // Every block element is read from HBM once.  Columns past n are zero in the
 // inputs and not written.
-__global__ __launch_bounds__(256) void k_symm16(const SymProblem* __restrict__ probs,
+//
+// A wave walks its chunks of all the item's terms as one sequence and loads
+// the next chunk (of the same or the next term) while it multiplies the
+// current one.  It waits for the current chunk's loads before it issues the
+// next ones: the mirrored results are stored inside the loop, and with stores
+// and loads both outstanding the wait for the older loads is a wait for
+// everything, which would otherwise include the loads just issued.
+// Descriptors read through the constant address space: uniform scalar loads
+// (a generic pointer to memory that stores may reach gives vector loads).
+// Buffer resource word 3 for raw (unswizzled, unformatted) buffer loads on
+// gfx9-family parts, the nontemporal cache policy bit of a buffer load, and
+// the s_waitcnt operand that waits for vmcnt = 0 only (expcnt 7, lgkmcnt 15).
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kBufNT = 2;
+constexpr int kWaitVm0 = 0x0F70;
+typedef const __attribute__((address_space(4))) SymProblem cSymProblem;
+typedef const __attribute__((address_space(4))) SymTerm cSymTerm;
+static __device__ inline SymProblem sym_problem(const SymProblem* p, int i) {
+  const cSymProblem* c = (const cSymProblem*)p + i;
+  SymProblem P;
+  P.C = c->C;
+  P.X = c->X;
+  P.ptile = c->ptile;
+  P.m = c->m;
+  P.n = c->n;
+  P.ldc = c->ldc;
+  P.ldx = c->ldx;
+  P.ldp = c->ldp;
+  P.term_begin = c->term_begin;
+  P.term_end = c->term_end;
+  P.pad = 0;
+  P.alpha = c->alpha;
+  P.beta = c->beta;
+  return P;
+}
+static __device__ inline SymTerm sym_term(const SymTerm* t, int i) {
+  const cSymTerm* c = (const cSymTerm*)t + i;
+  SymTerm T;
+  T.A = c->A;
+  T.B = c->B;
+  T.P = c->P;
+  T.scale = c->scale;
+  T.k = c->k;
+  T.lda = c->lda;
+  T.ldb = c->ldb;
+  T.pad = 0;
+  return T;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_symm16(const SymProblem* __restrict__ probs,
                                                 const SymTerm* __restrict__ terms, int tiles_max,
                                                 int nwork, int nprob) {
-  __shared__ double tr[4][64][17];      // per-wave transpose slot: rows x chunk columns
+  __shared__ double tr[4][64][17];      // per-wave transpose slot; row-sum exchange between groups
   __shared__ double red[2][4][16][17];  // per-wave mirrored partials, two chunks in flight
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -753,11 +806,15 @@ __global__ __launch_bounds__(256) void k_symm16(const SymProblem* __restrict__ p
     const int x8 = item & 7, rest = item >> 3;
     const int tile = rest % tiles_max, p = (rest / tiles_max) * 8 + x8;
     if (p >= nprob) continue;
-    const SymProblem P = probs[p];
+    const SymProblem P = sym_problem(probs, p);
     const int i0 = tile * 256;
     if (i0 >= P.m || P.n <= 0) continue;
     const int n = P.n, m = P.m;
-    const int r0 = i0 + 64 * w;  // this wave's first row
+    const int mt = min(256, m - i0);
+    const int lgR = mt <= 64 ? 0 : (mt <= 128 ? 1 : 2);  // R = 1 << lgR strips
+    const int R = 1 << lgR, G = 4 >> lgR;
+    const int st = w & (R - 1), g = w >> lgR;
+    const int r0 = i0 + 64 * st;  // this wave's first row
     const bool colok = lr < n;
     // the mirrored product's right operand: this wave's own input rows,
     // X[r0 + 4r + l/16][l%16] for row quads r = 0..15
@@ -771,112 +828,224 @@ __global__ __launch_bounds__(256) void k_symm16(const SymProblem* __restrict__ p
         xop[r] = Xg[(row < m ? row : m - 1) + (int64_t)(colok ? lr : 0) * P.ldx] * mk;
       }
     }
+    const int lrc = colok ? lr : 0;
     d4 acc[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int t = P.term_begin; t < P.term_end; ++t) {
-      const SymTerm T = terms[t];
-      const int K = T.k;
-      if (K <= 0) continue;
-      const int64_t lda = T.lda, ldb = T.ldb;
-      const double sc = T.scale;
-      double* pt = T.P ? T.P + (int64_t)tile * P.ptile : nullptr;
-      // A chunk's operands: A[r0 + 16s + l%16][c0 + 4q + l/16] and
-      // B[c0 + 4q + l/16][l%16], loaded from addresses clamped into the block
-      // and used unmasked except for B's columns past K, which are zeroed
-      // when the chunk is multiplied (not when it is loaded, so that its loads
-      // stay in flight meanwhile).  Nothing else needs a mask: rows past m
-      // meet zero rows of X in the mirrored product and give row sums that are
-      // never stored, and columns past K give mirrored entries that are never
-      // stored; values of columns past n reach only outputs that are never
-      // stored.
-      gdouble* Ag = (gdouble*)T.A;
-      gdouble* Bg = (gdouble*)T.B;
-      int rowc[4];
+    // pending mirrored result of the last chunk: ov (per lane), its block,
+    // first column and column count (uniform)
+    double ov[4];
+    bool pend = false;
+    double* ppt = nullptr;
+    int pc0 = 0, pK = 0;
+    // the chunk sequence: term t, chunk c0 = 16 (it G + g), it < niter(t)
+    struct Cur {
+      const double* A;
+      const double* B;
+      double* pt;
+      int lda8, bext;  // A's column stride and B's extent from its first row, in bytes
+      double sc;
+      int K, niter, t, it;
+      uint32_t va[4], vb;  // this lane's byte offsets in a chunk's first column
+    };
+    auto open = [&](int t, Cur& c) {  // first nonempty term at or after t; false at the end
+      for (; t < P.term_end; ++t) {
+        const SymTerm T = sym_term(terms, t);
+        if (T.k <= 0) continue;
+        c.A = T.A;
+        c.B = T.B;
+        c.pt = T.P ? T.P + (int64_t)tile * P.ptile : nullptr;
+        c.lda8 = 8 * T.lda;
+        c.bext = 8 * ((n - 1) * T.ldb + T.k);
+        c.sc = T.scale;
+        c.K = T.k;
+        c.niter = (((T.k + 15) >> 4) + G - 1) >> (2 - lgR);
+        c.t = t;
+        c.it = 0;
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const int row = r0 + 16 * s4 + lr;
-        rowc[s4] = row < m ? row : m - 1;
+        for (int s4 = 0; s4 < 4; ++s4) c.va[s4] = 8u * (uint32_t)(lk * T.lda + r0 + 16 * s4 + lr);
+        c.vb = 8u * (uint32_t)(lk + lrc * T.ldb);
+        return true;
       }
-      const int lrc = colok ? lr : 0;
-      auto load = [&](int c0, double (&ra)[4][4], double (&rb)[4]) {
+      return false;
+    };
+    // A chunk's operands: A[r0 + 16s + l%16][c0 + 4q + l/16] and
+    // B[c0 + 4q + l/16][l%16], as buffer loads from the chunk's column c0 + 4q
+    // whose range ends at the term's last column: the columns past K read
+    // zeros (so do rows past the block's last element).  B's columns past K
+    // are still zeroed when the chunk is multiplied, since the rows of B past
+    // K belong to other data.  Nothing else needs a mask: rows past m meet
+    // zero rows of X in the mirrored product and give row sums that are never
+    // stored, and columns past K give mirrored entries that are never stored;
+    // values of columns past n reach only outputs that are never stored.
+    auto load = [&](const Cur& c, double (&ra)[4][4], double (&rb)[4]) {
+      const int c0 = 16 * (c.it * G + g);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int col = c0 + 4 * q + lk;
-          const int64_t cc = col < K ? col : K - 1;
+      for (int q = 0; q < 4; ++q) {
+        const int col0 = c0 + 4 * q, rem = c.K - col0;
+        const __amdgpu_buffer_rsrc_t sa = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(c.A + (int64_t)col0 * (c.lda8 >> 3)), (short)0, rem > 0 ? rem * c.lda8 : 0, kBufWord3);
+        const __amdgpu_buffer_rsrc_t sb = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(c.B + col0), (short)0, rem > 0 ? c.bext - 8 * col0 : 0, kBufWord3);
 #pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) ra[s4][q] = __builtin_nontemporal_load(Ag + cc * lda + rowc[s4]);
-          rb[q] = Bg[cc + (int64_t)lrc * ldb];
+        for (int s4 = 0; s4 < 4; ++s4)
+          ra[s4][q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sa, c.va[s4], 0, kBufNT));
+        rb[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sb, c.vb, 0, 0));
+      }
+    };
+    // wait for every load issued so far (the current chunk's), before the
+    // next chunk's loads are issued
+    auto ready = [&]() {
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    auto process = [&](const Cur& c, const double (&ca)[4][4], const double (&cb)[4]) {
+      const int c0 = 16 * (c.it * G + g);
+      double bs[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bs[q] = (c0 + 4 * q + lk < c.K) ? c.sc * cb[q] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+          acc[s4] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[s4][q], bs[q], acc[s4], 0, 0, 0);
+      if (!c.pt) return;  // uniform across the workgroup (per term)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) tr[w][16 * s4 + lr][4 * q + lk] = ca[s4][q];
+      // LDS-only ordering: the prefetched global loads of the next chunk
+      // stay in flight (a full fence would wait for them)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+      // four independent accumulation chains over the row quads
+      d4 pa[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pa[u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        pa[r & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(tr[w][4 * r + lk][lr], xop[r], pa[r & 3], 0, 0, 0);
+      // the chunk's mirrored result is stored after the next chunk's wait
+      // (so that waiting for a chunk's loads never waits for a store just issued)
+      pend = true;
+      ppt = c.pt;
+      pc0 = c0;
+      pK = c.K;
+      if (R == 1) {
+        // one strip: the wave's own sums are the chunk's mirrored result
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ov[v] = c.sc * ((pa[0][v] + pa[1][v]) + (pa[2][v] + pa[3][v]));
+        return;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        red[buf][w][lk + 4 * v][lr] = (pa[0][v] + pa[1][v]) + (pa[2][v] + pa[3][v]);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+      // the group's 256 outputs, G = 256 / (64 R) per lane: output i is entry
+      // e = 64 (st + R i) + lane, the R strips summed in order
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (i >= G) break;
+        const int e = 64 * (st + R * i) + lane;
+        const int kk = e >> 4, cc = e & 15;
+        double v = red[buf][g << lgR][kk][cc];
+        for (int s = 1; s < R; ++s) v += red[buf][(g << lgR) + s][kk][cc];
+        ov[i] = c.sc * v;
+      }
+      buf ^= 1;
+    };
+    // store the pending mirrored result (lanes and entries past K or n skip)
+    auto flush = [&]() {
+      if (!pend) return;  // uniform
+      pend = false;
+      if (R == 1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int kk = lk + 4 * v;
+          if (pc0 + kk < pK && colok) ppt[pc0 + kk + (int64_t)lr * P.ldp] = ov[v];
         }
-      };
-      auto process = [&](int c0, const double (&ca)[4][4], const double (&cb)[4]) {
-        double bs[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bs[q] = (c0 + 4 * q + lk < K) ? sc * cb[q] : 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4)
-            acc[s4] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[s4][q], bs[q], acc[s4], 0, 0, 0);
-        if (!pt) return;  // uniform across the workgroup (per term)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) tr[w][16 * s4 + lr][4 * q + lk] = ca[s4][q];
-        // LDS-only ordering: the prefetched global loads of the next chunk
-        // stay in flight (a full fence would wait for them)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-        // four independent accumulation chains over the row quads
-        d4 pa[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) pa[u] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-          pa[r & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(tr[w][4 * r + lk][lr], xop[r], pa[r & 3], 0, 0, 0);
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          red[buf][w][lk + 4 * v][lr] = (pa[0][v] + pa[1][v]) + (pa[2][v] + pa[3][v]);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-        __builtin_amdgcn_s_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-        // 256 outputs of the chunk, 64 per wave: the four waves summed in order
-        const int e = 64 * w + lane;
-        const int kk = e >> 4, c = e & 15;
-        const double v =
-            ((red[buf][0][kk][c] + red[buf][1][kk][c]) + red[buf][2][kk][c]) + red[buf][3][kk][c];
-        if (c0 + kk < K && c < n) pt[c0 + kk + (int64_t)c * P.ldp] = sc * v;
-        buf ^= 1;
-      };
-      // two operand buffers in turn: the next chunk loads while one
-      // multiplies.  The loads are issued unconditionally (clamped past the
-      // term's end, at most one wasted chunk per term) so that every path
-      // into a multiplication has the same loads in flight and the wait
-      // before it covers only its own chunk.
-      double a0[4][4], b0[4], a1[4][4], b1[4];
-      load(0, a0, b0);
-      for (int c0 = 0; c0 < K; c0 += 32) {
-        load(c0 + 16, a1, b1);
-        process(c0, a0, b0);
-        if (c0 + 16 >= K) break;
-        load(c0 + 32, a0, b0);
-        process(c0 + 16, a1, b1);
+        return;
       }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (i >= G) break;
+        const int e = 64 * (st + R * i) + lane;
+        const int kk = e >> 4, cc = e & 15;
+        if (pc0 + kk < pK && cc < n) ppt[pc0 + kk + (int64_t)cc * P.ldp] = ov[i];
+      }
+    };
+    // advance to the next chunk in the sequence; false at the end
+    auto next = [&](const Cur& c, Cur& nx) {
+      if (c.it + 1 < c.niter) {
+        nx = c;
+        nx.it = c.it + 1;
+        return true;
+      }
+      return open(c.t + 1, nx);
+    };
+    // two operand buffers in turn
+    double a0[4][4], b0[4], a1[4][4], b1[4];
+    Cur c0s, c1s;
+    if (open(P.term_begin, c0s)) {
+      load(c0s, a0, b0);
+      while (true) {
+        ready();
+        flush();
+        const bool more0 = next(c0s, c1s);
+        if (more0) load(c1s, a1, b1);
+        process(c0s, a0, b0);
+        if (!more0) break;
+        ready();
+        flush();
+        const bool more1 = next(c1s, c0s);
+        if (more1) load(c0s, a0, b0);
+        process(c1s, a1, b1);
+        if (!more1) break;
+      }
+      flush();
     }
-    // row sums: D[l/16 + 4v][l%16] of strip s is row r0 + 16s + l/16 + 4v, column l%16
+    // row sums: D[l/16 + 4v][l%16] of strip s is row r0 + 16s + l/16 + 4v,
+    // column l%16; with G > 1 the groups' sums are added in group order
+    if (G > 1) {
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4)
+      for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = r0 + 16 * s4 + lk + 4 * v;
-        if (row < m && colok) {
-          double* cp = P.C + row + (int64_t)lr * P.ldc;
-          double val = P.alpha * acc[s4][v];
-          if (P.beta != 0.0) val += P.beta * (*cp);
-          *cp = val;
-        }
+        for (int v = 0; v < 4; ++v) tr[w][16 * s4 + lk + 4 * v][lr] = acc[s4][v];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+      if (g == 0) {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double sum = acc[s4][v];
+            for (int h = 1; h < G; ++h) sum += tr[st + (h << lgR)][16 * s4 + lk + 4 * v][lr];
+            acc[s4][v] = sum;
+          }
       }
+      // the slots are written again by the next item's transposes
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = r0 + 16 * s4 + lk + 4 * v;
+          if (row < m && colok) {
+            double* cp = P.C + row + (int64_t)lr * P.ldc;
+            double val = P.alpha * acc[s4][v];
+            if (P.beta != 0.0) val += P.beta * (*cp);
+            *cp = val;
+          }
+        }
+    }
   }
 }
 

@@ -521,6 +521,10 @@ void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, in
       while (want > 0) {
         const MT& g = mt[q];
         const int64_t take = std::min<int64_t>(want, g.k - off);
+        // the 5-16 column kernel addresses a term through 32-bit buffer ranges
+        SPD_REQUIRE(n <= 4 || (8 * (int64_t)g.lda * take < (1ll << 31) &&
+                               8 * ((int64_t)(n - 1) * g.ldb + take) < (1ll << 31)),
+                    SPD_E_INVALID, "symmetric-pair term above 2 GiB of addressed bytes");
         SymTerm t{};
         t.A = a_at(g.A, (int64_t)g.lda * off);
         t.B = g.B + off;

@@ -146,3 +146,31 @@ def test_cpqr(B, m, n, which):
         if which == 0:
             Qg = Q[b, :r].cpu().numpy().T
             np.testing.assert_allclose(Qg, f.q(), rtol=0, atol=1e-10)
+
+
+# The symmetric-pair product on a block-cyclic symmetric matrix: every block
+# A_it is read once for S_ij x_j and S_ji x_i = A_it^T x_i.  Up to 4 columns
+# take the streaming kernel, 5-16 the FP64 MFMA kernel; rows span partial
+# waves (37), several waves (100), exactly one tile (256), a ragged second tile
+# (300) and the 1 MiB split of long rows (m = 512, 4 terms).
+@pytest.mark.parametrize("nblk,m,nterm", [(3, 37, 1), (7, 100, 3), (5, 256, 2), (9, 300, 4), (9, 512, 4),
+                                          (4, 16, 0)])
+@pytest.mark.parametrize("n", [1, 3, 5, 16])
+def test_symmetric_pair_product(B, nblk, m, nterm, n):
+    rng = np.random.default_rng(nblk * 1000 + m + 7 * nterm + n)
+    A = rng.standard_normal((nblk * max(nterm, 1), m, m))  # block (i, t): A[i * nterm + t] (row-major view)
+    X = rng.standard_normal((n, nblk * m))
+    Y = np.full((n, nblk * m), np.nan)
+    dA, dX, dY = dev(A), dev(X), dev(Y)
+    B.test_symm(dA, dX, dY, nblk, m, nterm)
+    out = dY.cpu().numpy()
+    ref = np.zeros((nblk * m, n))
+    xc = X.T
+    for i in range(nblk):
+        for t in range(nterm):
+            j = (i + 1 + t) % nblk
+            blk = A[i * nterm + t].T  # the stored column-major m x m block
+            ref[i * m:(i + 1) * m] += blk @ xc[j * m:(j + 1) * m]
+            ref[j * m:(j + 1) * m] += blk.T @ xc[i * m:(i + 1) * m]
+    scale = max(np.abs(ref).max(), 1.0)
+    np.testing.assert_allclose(out.T, ref, rtol=0, atol=1e-13 * scale * m * max(nterm, 1))
