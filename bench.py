@@ -43,17 +43,18 @@ def source_hash() -> str:
 
 
 def recorded_traffic(workload: str, pass_name: str):
-    """HBM bytes per launch of the dominant pass measured with rocprofv3 counters
-    (profiles/hbm_traffic_<workload>.json), or None when the kernel sources
-    changed since the counters were taken."""
+    """HBM bytes per launch of a pass of the product measured with rocprofv3
+    counters (profiles/hbm_traffic_<workload>.json, one entry per pass), or
+    None when the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_sha") != source_hash() or rec.get("pass") != pass_name:
+    p = rec.get("passes", {}).get(pass_name)
+    if rec.get("source_sha") != source_hash() or p is None:
         return None
-    return round(rec["fetch_bytes"] + rec["write_bytes"], 1)
+    return round(p["fetch_bytes"] + p["write_bytes"], 1)
 
 
 def h2_sampled_error(P, h2, w, Xg, nrows: int = 200) -> float:

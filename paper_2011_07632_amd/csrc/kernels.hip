@@ -899,21 +899,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       __builtin_amdgcn_s_waitcnt(kWaitVm0);
       __builtin_amdgcn_sched_barrier(0);
     };
-    auto process = [&](const Cur& c, const double (&ca)[4][4], const double (&cb)[4]) {
+    // one step: the loads of chunk c have arrived in (ca, cb); the loads of
+    // the next chunk nx go out between the row-sum MFMAs of c, and so do the
+    // LDS transposes of c
+    auto process = [&](const Cur& c, const double (&ca)[4][4], const double (&cb)[4], const Cur& nx,
+                       double (&na)[4][4], double (&nb)[4], bool more) {
       const int c0 = 16 * (c.it * G + g);
       double bs[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) bs[q] = (c0 + 4 * q + lk < c.K) ? c.sc * cb[q] : 0.0;
+      const int n0 = 16 * (nx.it * G + g);
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 4; ++q) {
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4)
           acc[s4] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[s4][q], bs[q], acc[s4], 0, 0, 0);
-      if (!c.pt) return;  // uniform across the workgroup (per term)
+        if (more) {
+          const int col0 = n0 + 4 * q, rem = nx.K - col0;
+          const __amdgpu_buffer_rsrc_t sa = __builtin_amdgcn_make_buffer_rsrc(
+              (void*)(nx.A + (int64_t)col0 * (nx.lda8 >> 3)), (short)0, rem > 0 ? rem * nx.lda8 : 0, kBufWord3);
+          const __amdgpu_buffer_rsrc_t sb = __builtin_amdgcn_make_buffer_rsrc(
+              (void*)(nx.B + col0), (short)0, rem > 0 ? nx.bext - 8 * col0 : 0, kBufWord3);
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+          for (int s4 = 0; s4 < 4; ++s4)
+            na[s4][q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sa, nx.va[s4], 0, kBufNT));
+          nb[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sb, nx.vb, 0, 0));
+        }
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) tr[w][16 * s4 + lr][4 * q + lk] = ca[s4][q];
+      }
+      // issue order per column quad: MFMAs alternating with the buffer loads
+      // and LDS writes (scheduling-group masks: 0x008 MFMA, 0x020 vector
+      // memory read, 0x200 LDS write)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+      }
+      if (!c.pt) return;  // uniform across the workgroup (per term)
       // LDS-only ordering: the prefetched global loads of the next chunk
       // stay in flight (a full fence would wait for them)
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
@@ -995,14 +1025,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         ready();
         flush();
         const bool more0 = next(c0s, c1s);
-        if (more0) load(c1s, a1, b1);
-        process(c0s, a0, b0);
+        process(c0s, a0, b0, c1s, a1, b1, more0);
         if (!more0) break;
         ready();
         flush();
         const bool more1 = next(c1s, c0s);
-        if (more1) load(c0s, a0, b0);
-        process(c1s, a1, b1);
+        process(c1s, a1, b1, c0s, a0, b0, more1);
         if (!more1) break;
       }
       flush();

@@ -126,6 +126,8 @@ struct SymRow {
 struct Recorder {
   std::vector<LaunchRec> recs;
   void gemm(Arena& a, hipStream_t s, const GemmBatch& b);
+  // the same product on the symmetric-pair kernel (row sums only)
+  void gemm_symm(Arena& a, hipStream_t s, const GemmBatch& b, double bytes);
   // symmetric product of n <= 4 columns over rows (one product launch and one
   // launch that sums each row's partial results in a fixed order into
   // y = beta * y + sum)

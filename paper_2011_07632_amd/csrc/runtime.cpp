@@ -359,6 +359,68 @@ static double batch_bytes(const GemmBatch& b) {
   return bytes;
 }
 
+// A product of 5-16 right-hand columns that streams its A operands (not
+// transposed, no gathered rows) runs on the symmetric-pair kernel with no
+// mirrored terms: the row sums alone are C = alpha sum_t scale_t A_t B_t +
+// beta C, with every A read once per 256-row tile.  Launches of fewer than
+// kSymmMinWork tiles stay on the tiled GEMM, which splits them finer.
+static constexpr int64_t kSymmMinWork = 1024;
+
+static bool symm_form(const GemmBatch& b) {
+  if (b.transA || b.transB || b.indexed || b.a_f32 || b.max_n < 5 || b.max_n > 16) return false;
+  int64_t work = 0;
+  for (const GemmProblem& p : b.probs) {
+    if (p.cidx || p.D || p.didx) return false;
+    work += (p.m + 255) / 256;
+    for (int q = p.term_begin; q < p.term_end; ++q) {
+      const GemmTerm& t = b.terms[q];
+      if (t.bidx || 8 * (int64_t)t.lda * t.k >= (1ll << 31) ||
+          8 * ((int64_t)(p.n - 1) * t.ldb + t.k) >= (1ll << 31))
+        return false;
+    }
+  }
+  return work >= kSymmMinWork;
+}
+
+void Recorder::gemm_symm(Arena& a, hipStream_t s, const GemmBatch& b, double bytes) {
+  std::vector<SymProblem> probs;
+  std::vector<SymTerm> terms;
+  probs.reserve(b.probs.size());
+  for (const GemmProblem& g : b.probs) {
+    SymProblem P{};
+    P.C = g.C;
+    P.X = g.C;  // never multiplied (no mirrored terms); any rows of the right size
+    P.ptile = 0;
+    P.m = g.m;
+    P.n = g.n;
+    P.ldc = g.ldc;
+    P.ldx = g.ldc;
+    P.ldp = 1;
+    P.alpha = g.alpha;
+    P.beta = g.beta;
+    P.term_begin = (int)terms.size();
+    for (int q = g.term_begin; q < g.term_end; ++q) {
+      const GemmTerm& t = b.terms[q];
+      if (t.k <= 0) continue;
+      SymTerm u{};
+      u.A = t.A;
+      u.B = t.B;
+      u.P = nullptr;
+      u.scale = t.scale;
+      u.k = t.k;
+      u.lda = t.lda;
+      u.ldb = t.ldb;
+      terms.push_back(u);
+    }
+    P.term_end = (int)terms.size();
+    probs.push_back(P);
+  }
+  if (terms.empty()) terms.push_back(SymTerm{});
+  LaunchRec r{3, keep(a, s, probs), keep(a, s, terms), (int)probs.size(), b.max_m, b.max_n, 0, 0, bytes,
+              -1};
+  recs.push_back(r);
+}
+
 void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
   if (b.probs.empty() || b.max_m == 0 || b.max_n == 0) return;
   const double bytes = batch_bytes(b);
@@ -372,6 +434,10 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
   if (b.max_n <= 16 && !b.indexed && !b.a_f32)
     for (const GemmProblem& p : b.probs)
       if (8.0 * p.m * width(p) > kSplitBytes && width(p) > 1) { split = true; break; }
+  if (!split && symm_form(b)) {
+    gemm_symm(a, s, b, bytes);
+    return;
+  }
   if (!split) {
     std::vector<GemmTerm> t = b.terms;
     if (t.empty()) t.push_back(GemmTerm{});
@@ -423,9 +489,13 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
       red.term(dst, p.m, p.alpha);
     }
   }
-  recs.push_back({0, keep(a, s, parts.probs), keep(a, s, parts.terms), (int)parts.probs.size(),
-                  parts.max_m, parts.max_n, parts.transA, parts.transB, bytes, -1});
-  recs.back().max_k = std::max(b.max_k, 1);
+  if (symm_form(parts)) {
+    gemm_symm(a, s, parts, bytes);
+  } else {
+    recs.push_back({0, keep(a, s, parts.probs), keep(a, s, parts.terms), (int)parts.probs.size(),
+                    parts.max_m, parts.max_n, parts.transA, parts.transB, bytes, -1});
+    recs.back().max_k = std::max(b.max_k, 1);
+  }
   block(a, s, red);
 }
 

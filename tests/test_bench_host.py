@@ -47,8 +47,8 @@ def test_traffic_only_for_the_recorded_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(t))
     w = "some-workload"
     assert bench.recorded_traffic(w, "coupling") is None  # no record
-    rec = {"workload": w, "pass": "coupling", "source_sha": bench.source_hash(),
-           "fetch_bytes": 1000.25, "write_bytes": 24.5}
+    rec = {"workload": w, "source_sha": bench.source_hash(),
+           "passes": {"coupling": {"fetch_bytes": 1000.25, "write_bytes": 24.5}}}
     path = t / "profiles" / f"hbm_traffic_{w}.json"
     path.write_text(json.dumps(rec))
     assert bench.recorded_traffic(w, "coupling") == 1024.8  # rounded to 0.1 byte
