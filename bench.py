@@ -231,9 +231,9 @@ def run_serve(args, torch, P):
     completion minus arrival."""
     from paper_2011_07632_amd.binding import cols_like
     dev = "cuda"
-    trace = workloads.serve_requests(args.serve)
+    trace = workloads.serve_requests(args.serve, n_hi=args.serve_nmax, repeat=args.serve_repeat)
     reqs = []
-    for _, w in trace:
+    for _, w, _ in trace:
         reqs.append(dict(points=torch.from_numpy(w.points()).to(dev), kernel=w.kernel, ell=w.ell,
                          shift=w.shift, leaf=w.leaf, h2_tol=w.h2_tol, hss_tol=w.hss_tol, max_rank=w.max_rank,
                          oversample=w.oversample, b=cols_like(w.n, w.nrhs, dev).copy_(torch.from_numpy(w.rhs())),
@@ -242,21 +242,30 @@ def run_serve(args, torch, P):
     S = P.binding.Server(workers=args.workers, hbm_budget_bytes=200 << 30)
     t0 = time.perf_counter()
     tickets = []
-    for (arr, w), r in zip(trace, reqs):
+    for (arr, w, key), r in zip(trace, reqs):
         dt = arr - (time.perf_counter() - t0)
         if dt > 0:
             time.sleep(dt)
-        tickets.append(S.submit(r))
+        # every request names its matrix, so a later request on the same
+        # matrix solves on the device-resident state
+        tickets.append(S.submit(r, key=key))
     done = {}
+    phase = {}
     while len(done) < len(tickets):
         for k, t in enumerate(tickets):
             if k in done:
                 continue
+            p = S.phase(t)
+            if p != phase.get(k) and p in ("building", "solving"):
+                log(f"[bench] {trace[k][1].name}: {p} at {time.perf_counter() - t0:.1f} s")
+            phase[k] = p
             r = S.wait(t, block=False)
             if r is not None:
                 done[k] = r
                 log(f"[bench] served {len(done)}/{len(tickets)}: {trace[k][1].name} {r['status']} "
-                    f"latency {r['seconds_total']:.2f} s")
+                    f"latency {r['seconds_total']:.2f} s (h2 {r['seconds_h2']:.1f} s, build "
+                    f"{r['seconds_build']:.1f} s, solve {r['seconds_solve']:.1f} s, "
+                    f"{int(r['iters'].max())} iterations)")
         time.sleep(0.05)
     res = [done[k] for k in range(len(tickets))]
     span = time.perf_counter() - t0
@@ -269,15 +278,21 @@ def run_serve(args, torch, P):
     line = {"metric": "served p50 latency, s (request loop)", "value": round(float(np.percentile(lat, 50)), 3),
             "unit": "s", "p99_s": round(float(np.percentile(lat, 99)), 3), "higher_is_better": False,
             "solves_per_s": round(len(res) / span, 3), "n_gpus": 1, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": f"serve-{len(res)}-poisson20-N10k-100k", "requests": len(res),
-                       "arrival_rate_per_s": 20.0, "n_range": [10000, 100000], "leaf": 400,
-                       "workers": args.workers, "hbm_budget_bytes": 200 << 30},
+            "config": {"workload": f"serve-{len(res)}-poisson20-N10k-{args.serve_nmax // 1000}k"
+                                   f"-repeat{args.serve_repeat:g}", "requests": len(res),
+                       "arrival_rate_per_s": 20.0, "n_range": [10000, args.serve_nmax], "leaf": 400,
+                       "repeat_fraction": args.serve_repeat, "workers": args.workers,
+                       "hbm_budget_bytes": 200 << 30},
             "seconds_makespan": round(span, 3), "status_counts": status,
             "queued_p50_s": round(float(np.percentile([r["seconds_queued"] for r in res], 50)), 3),
             "relres_max_converged": float(max([float(r["relres"].max()) for r in ok], default=0.0)),
-            "requests": [{"name": w.name, "arrival_s": round(a, 3), "latency_s": round(r["seconds_total"], 3),
-                          "queued_s": round(r["seconds_queued"], 3), "iters": int(r["iters"].max()),
-                          "status": r["status"]} for (a, w), r in zip(trace, res)]}
+            "reused_state": sum(1 for r in res if r["seconds_h2"] == 0.0 and r["seconds_solve"] > 0.0),
+            "requests": [{"name": w.name, "n": w.n, "nrhs": w.nrhs, "key": key, "arrival_s": round(a, 3),
+                          "latency_s": round(r["seconds_total"], 3), "queued_s": round(r["seconds_queued"], 3),
+                          "h2_s": round(r["seconds_h2"], 3), "build_s": round(r["seconds_build"], 3),
+                          "solve_s": round(r["seconds_solve"], 3), "iters": int(r["iters"].max()),
+                          "relres": float(r["relres"].max()), "status": r["status"]}
+                         for (a, w, key), r in zip(trace, res)]}
     print(json.dumps(line), flush=True)
 
 
@@ -298,6 +313,10 @@ def main():
     ap.add_argument("--serve", type=int, default=0, metavar="COUNT",
                     help="served mode: a seeded trace of COUNT requests with Poisson arrivals (20/s) "
                          "through the request loop; prints p50/p99 latency and solves/s")
+    ap.add_argument("--serve-nmax", type=int, default=1_000_000,
+                    help="largest N of the served trace (log-uniform from 10,000)")
+    ap.add_argument("--serve-repeat", type=float, default=0.25,
+                    help="fraction of served requests on an earlier request's matrix")
     ap.add_argument("--counters-build", action="store_true",
                     help="build the H^2 matrix, then one SPD-HSS build + ULV factor, and exit (for counter runs)")
     ap.add_argument("--counters", action="store_true",

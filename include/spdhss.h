@@ -301,6 +301,22 @@ spd_status spd_server_create(int32_t workers, int64_t hbm_budget_bytes, spd_serv
 /* Queue a request; *ticket identifies it for spd_server_wait. */
 spd_status spd_server_submit(spd_server_t S, const spd_instance* request, int64_t* ticket);
 
+/* Queue a request whose matrix is named by key (nonzero).  Requests with the
+ * same key must have the same points (contents), n, kernel, h2 and hss
+ * options and solve precision; their right-hand sides, tolerances and
+ * iteration limits may differ.  The first of them builds the H^2, HSS and
+ * factor state and leaves it on the device; the later ones run only
+ * pcg_solve on it (their results report seconds_h2 = seconds_build = 0) and
+ * equal the same request run alone.  Requests with one key run one at a
+ * time; one that waits for its state does not hold up the requests behind
+ * it.  A resident state counts against hbm_budget_bytes with its footprint
+ * estimate less the PCG vectors; idle states are released, least recently
+ * used first, when a request cannot be admitted otherwise, and all of them at
+ * spd_server_destroy.  A failed build leaves nothing resident.
+ * SPD_E_INVALID for a zero key or null arguments. */
+spd_status spd_server_submit_keyed(spd_server_t S, const spd_instance* request, uint64_t key,
+                                   int64_t* ticket);
+
 /* block != 0: wait until the request has finished.  Returns SPD_PENDING
  * (block == 0, not finished) or SPD_OK with *result filled and, if not NULL,
  * the seconds from submission to admission (*seconds_queued) and to
@@ -310,6 +326,11 @@ spd_status spd_server_submit(spd_server_t S, const spd_instance* request, int64_
 spd_status spd_server_wait(spd_server_t S, int64_t ticket, int32_t block,
                            spd_instance_result* result, double* seconds_queued,
                            double* seconds_total);
+
+/* Where a submitted, not yet collected request is: *phase = 0 queued,
+ * 1 building its state, 2 solving, 3 finished.  SPD_E_INVALID for unknown or
+ * collected tickets.  Thread-safe. */
+spd_status spd_server_phase(spd_server_t S, int64_t ticket, int32_t* phase);
 
 /* Estimated device bytes of a request (the admission estimate). */
 int64_t spd_request_footprint(const spd_instance* request);

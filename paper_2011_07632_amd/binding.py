@@ -104,6 +104,8 @@ def _load():
         "spd_solve_batch": [C.POINTER(_Instance), i32, i32, C.POINTER(_InstanceResult)],
         "spd_server_create": [i32, i64, C.POINTER(vp)],
         "spd_server_submit": [vp, C.POINTER(_Instance), C.POINTER(i64)],
+        "spd_server_submit_keyed": [vp, C.POINTER(_Instance), C.c_uint64, C.POINTER(i64)],
+        "spd_server_phase": [vp, i64, C.POINTER(i32)],
         "spd_server_wait": [vp, i64, i32, C.POINTER(_InstanceResult), C.POINTER(dbl), C.POINTER(dbl)],
     }
     for name, args in sig.items():
@@ -530,8 +532,9 @@ def _fill_instance(I: _Instance, d: dict):
 
 class Server:
     """Request loop (spd_server_*): submit() queues a request dict (as for
-    solve_batch) and returns a ticket; wait(ticket) returns its result with
-    the queueing and total latency in seconds."""
+    solve_batch), optionally with a matrix key, and returns a ticket;
+    wait(ticket) returns its result with the queueing and total latency in
+    seconds."""
 
     def __init__(self, workers: int = 8, hbm_budget_bytes: int = 200 << 30):
         h = C.c_void_p()
@@ -544,14 +547,27 @@ class Server:
         keep = _fill_instance(I, d)  # noqa: F841
         return int(lib.spd_request_footprint(C.byref(I)))
 
-    def submit(self, d: dict) -> int:
+    def submit(self, d: dict, key: int = 0) -> int:
+        """key != 0 names the request's matrix: requests with the same key
+        share device-resident H^2 / HSS / factor state (spd_server_submit_keyed)."""
         I = _Instance()
         keep = _fill_instance(I, d)
         torch.cuda.current_stream().synchronize()
         t = C.c_int64()
-        _check(lib.spd_server_submit(self._h, C.byref(I), C.byref(t)))
+        if key:
+            _check(lib.spd_server_submit_keyed(self._h, C.byref(I), C.c_uint64(int(key)), C.byref(t)))
+        else:
+            _check(lib.spd_server_submit(self._h, C.byref(I), C.byref(t)))
         self._pending[t.value] = (I, keep)
         return t.value
+
+    PHASES = ("queued", "building", "solving", "finished")
+
+    def phase(self, ticket: int) -> str:
+        """Where a request not yet collected is (spd_server_phase)."""
+        p = C.c_int32()
+        _check(lib.spd_server_phase(self._h, int(ticket), C.byref(p)))
+        return self.PHASES[p.value]
 
     def wait(self, ticket: int, block: bool = True):
         r = _InstanceResult()

@@ -23,36 +23,59 @@ double seconds_since(std::chrono::steady_clock::time_point t0) {
 }  // namespace
 
 namespace spd {
-void run_instance(const spd_instance& I, hipStream_t s, spd_instance_result& R) {
-  R = spd_instance_result{};
+// h2_build, spdhss_build and ulv_factor_ex of one instance; on failure the
+// handles made so far are destroyed and left null
+spd_status build_state(const spd_instance& I, hipStream_t s, spd_instance_result& R, spd_h2_t* A,
+                       spd_hss_t* M, spd_ulv_t* F) {
+  *A = nullptr;
+  *M = nullptr;
+  *F = nullptr;
   auto t0 = std::chrono::steady_clock::now();
-  spd_h2_t A = nullptr;
-  spd_hss_t M = nullptr;
-  spd_ulv_t F = nullptr;
-  spd_status st = h2_build(I.points, I.n, I.kernel, &I.h2, s, &A);
+  spd_status st = h2_build(I.points, I.n, I.kernel, &I.h2, s, A);
   R.seconds_h2 = seconds_since(t0);
   if (st == SPD_OK) {
     t0 = std::chrono::steady_clock::now();
-    st = spdhss_build(A, &I.hss, s, &M);
-    if (st == SPD_OK) st = ulv_factor_ex(M, I.solve_precision, s, &F);
+    st = spdhss_build(*A, &I.hss, s, M);
+    if (st == SPD_OK) st = ulv_factor_ex(*M, I.solve_precision, s, F);
     R.seconds_build = seconds_since(t0);
   }
-  if (st == SPD_OK) {
-    std::vector<int32_t> it(std::max(I.nrhs, 1));
-    std::vector<double> rr(std::max(I.nrhs, 1));
-    t0 = std::chrono::steady_clock::now();
-    st = pcg_solve(A, F, I.b, I.x, I.nrhs, I.n, I.rtol, I.maxit, s, it.data(), rr.data());
-    R.seconds_solve = seconds_since(t0);
-    if (st == SPD_OK || st == SPD_E_NOT_CONVERGED) {
-      for (int c = 0; c < I.nrhs; ++c) {
-        R.iters_max = std::max(R.iters_max, it[c]);
-        R.relres_max = std::max(R.relres_max, rr[c]);
-        if (I.iters) I.iters[c] = it[c];
-        if (I.relres) I.relres[c] = rr[c];
-      }
+  if (st != SPD_OK) {
+    if (*F) ulv_destroy(*F);
+    if (*M) spdhss_destroy(*M);
+    if (*A) h2_destroy(*A);
+    *A = nullptr;
+    *M = nullptr;
+    *F = nullptr;
+  }
+  return st;
+}
+
+// pcg_solve of the instance's right-hand sides on built state
+void solve_state(const spd_instance& I, spd_h2_t A, spd_ulv_t F, hipStream_t s, spd_instance_result& R) {
+  std::vector<int32_t> it(std::max(I.nrhs, 1));
+  std::vector<double> rr(std::max(I.nrhs, 1));
+  const auto t0 = std::chrono::steady_clock::now();
+  const spd_status st = pcg_solve(A, F, I.b, I.x, I.nrhs, I.n, I.rtol, I.maxit, s, it.data(), rr.data());
+  R.seconds_solve = seconds_since(t0);
+  if (st == SPD_OK || st == SPD_E_NOT_CONVERGED) {
+    for (int c = 0; c < I.nrhs; ++c) {
+      R.iters_max = std::max(R.iters_max, it[c]);
+      R.relres_max = std::max(R.relres_max, rr[c]);
+      if (I.iters) I.iters[c] = it[c];
+      if (I.relres) I.relres[c] = rr[c];
     }
   }
   R.status = st;
+}
+
+void run_instance(const spd_instance& I, hipStream_t s, spd_instance_result& R) {
+  R = spd_instance_result{};
+  spd_h2_t A = nullptr;
+  spd_hss_t M = nullptr;
+  spd_ulv_t F = nullptr;
+  const spd_status st = build_state(I, s, R, &A, &M, &F);
+  if (st == SPD_OK) solve_state(I, A, F, s, R);
+  else R.status = st;
   if (F) ulv_destroy(F);
   if (M) spdhss_destroy(M);
   if (A) h2_destroy(A);

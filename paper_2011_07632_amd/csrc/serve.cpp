@@ -1,5 +1,6 @@
 // Request loop: FIFO queue, worker threads with their own streams, admission
-// by the estimated device footprint of the admitted requests.
+// by the estimated device footprint of the admitted requests, and resident
+// H^2 / HSS / factor state for requests that name the same matrix by a key.
 #include "model.h"
 
 #include <algorithm>
@@ -12,23 +13,45 @@
 #include <vector>
 
 namespace spd {
-void run_instance(const spd_instance& I, hipStream_t s, spd_instance_result& R);
+spd_status build_state(const spd_instance& I, hipStream_t s, spd_instance_result& R, spd_h2_t* A,
+                       spd_hss_t* M, spd_ulv_t* F);
+void solve_state(const spd_instance& I, spd_h2_t A, spd_ulv_t F, hipStream_t s, spd_instance_result& R);
 }
 
 using Clock = std::chrono::steady_clock;
 
+// Device bytes of a request's PCG vectors (the part of the footprint that a
+// request solving on resident state still needs).
+static int64_t pcg_bytes(const spd_instance* q) {
+  return (int64_t)(8.0 * (double)q->n * 8.0 * std::max(q->nrhs, 1));
+}
+
 struct spd_server {
   struct Request {
     spd_instance inst{};
-    int64_t bytes = 0;
+    uint64_t key = 0;
+    int64_t bytes = 0;  // footprint estimate: state + PCG vectors
+    int64_t held = 0;   // bytes counted in in_use while it runs
+    int32_t phase = 0;  // 0 queued, 1 building, 2 solving, 3 finished
     bool done = false;
     spd_instance_result res{};
     Clock::time_point t_submit, t_admit, t_done;
+  };
+  // state of a keyed matrix kept on the device between its requests
+  struct Resident {
+    spd_h2_t A = nullptr;
+    spd_hss_t M = nullptr;
+    spd_ulv_t F = nullptr;
+    int64_t bytes = 0;  // counted in in_use while resident
+    bool ready = false; // built (false while its first request builds it)
+    bool busy = false;  // a request is using it (one at a time)
+    Clock::time_point last;
   };
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<int64_t> queue;
   std::map<int64_t, Request> reqs;
+  std::map<uint64_t, Resident> resident;
   int64_t next_ticket = 1;
   int64_t budget = 0, in_use = 0;
   int running = 0;
@@ -36,9 +59,84 @@ struct spd_server {
   int dev = 0;
   std::vector<std::thread> workers;
 
+  // Bytes request r needs to start: the PCG vectors on a built resident state,
+  // the whole footprint otherwise.
+  int64_t need(const Request& r) const {
+    if (r.key) {
+      auto it = resident.find(r.key);
+      if (it != resident.end() && it->second.ready) return pcg_bytes(&r.inst);
+    }
+    return r.bytes;
+  }
+  // Resident states that are idle and not r's, least recently used first,
+  // released until r fits; their handles are handed back to be destroyed
+  // outside the lock.
+  bool make_room(const Request& r, int64_t want, std::vector<Resident>& freed) {
+    auto idle = [&](const std::pair<const uint64_t, Resident>& kv) {
+      return kv.first != r.key && kv.second.ready && !kv.second.busy;
+    };
+    int64_t can = 0;
+    for (const auto& kv : resident)
+      if (idle(kv)) can += kv.second.bytes;
+    if (in_use - can + want > budget) return false;  // evicting everything idle would not do
+    while (in_use + want > budget) {
+      auto victim = resident.end();
+      for (auto it = resident.begin(); it != resident.end(); ++it)
+        if (idle(*it) && (victim == resident.end() || it->second.last < victim->second.last)) victim = it;
+      in_use -= victim->second.bytes;
+      freed.push_back(victim->second);
+      resident.erase(victim);
+    }
+    return true;
+  }
+  // The request to admit next, or 0.  First come first served, except that a
+  // request whose matrix state is in use (or being built) by another request
+  // waits without holding up the requests behind it.  The first request that
+  // may run is admitted once it fits, after idle resident states are
+  // released, or when nothing else runs (a request above the budget then runs
+  // alone).
+  int64_t pick(std::vector<Resident>& freed) {
+    for (auto qi = queue.begin(); qi != queue.end(); ++qi) {
+      Request& r = reqs[*qi];
+      if (r.key) {
+        auto it = resident.find(r.key);
+        if (it != resident.end() && (it->second.busy || !it->second.ready)) continue;
+      }
+      const int64_t want = need(r);
+      bool go = in_use + want <= budget || make_room(r, want, freed);
+      if (!go && running == 0) {
+        // above the budget: it runs alone, with every idle resident state released
+        for (auto it = resident.begin(); it != resident.end();) {
+          if (it->first != r.key && it->second.ready && !it->second.busy) {
+            in_use -= it->second.bytes;
+            freed.push_back(it->second);
+            it = resident.erase(it);
+          } else {
+            ++it;
+          }
+        }
+        go = true;
+      }
+      if (go) {
+        const int64_t t = *qi;
+        queue.erase(qi);
+        return t;
+      }
+      return 0;
+    }
+    return 0;
+  }
+
+  static void release(Resident& z) {
+    if (z.F) ulv_destroy(z.F);
+    if (z.M) spdhss_destroy(z.M);
+    if (z.A) h2_destroy(z.A);
+    z = Resident{};
+  }
+
   void work() {
     // a worker that cannot set the device or make a stream still drains the
-    // queue (run_instance then reports the device error per request, or runs
+    // queue (the instance then reports the device error per request, or runs
     // on the null stream), so that no request waits forever
     (void)hipSetDevice(dev);
     hipStream_t s = nullptr;
@@ -49,34 +147,94 @@ struct spd_server {
     for (;;) {
       int64_t t = 0;
       spd_instance inst{};
+      uint64_t key = 0;
+      Resident use{};
+      bool reuse = false;
+      std::vector<Resident> freed;
       {
         std::unique_lock<std::mutex> lk(mu);
-        // first come first served: the head is admitted once it fits, or when
-        // nothing else runs (a request above the budget then runs alone)
         cv_work.wait(lk, [&] {
           if (queue.empty()) return stop;
-          const Request& h = reqs[queue.front()];
-          return running == 0 || in_use + h.bytes <= budget;
+          t = pick(freed);
+          return t != 0;
         });
-        if (queue.empty()) break;
-        t = queue.front();
-        queue.pop_front();
+        if (t == 0) break;  // stopping with an empty queue
         Request& r = reqs[t];
         r.t_admit = Clock::now();
-        in_use += r.bytes;
+        key = r.key;
+        if (key) {
+          auto it = resident.find(key);
+          if (it != resident.end()) {  // built and idle (pick checked)
+            it->second.busy = true;
+            use = it->second;
+            reuse = true;
+          } else {
+            Resident& z = resident[key];  // placeholder while this request builds it
+            z.busy = true;
+            z.bytes = r.bytes - pcg_bytes(&r.inst);
+          }
+        }
+        r.held = reuse ? pcg_bytes(&r.inst) : r.bytes;
+        r.phase = reuse ? 2 : 1;
+        in_use += r.held;
         ++running;
         inst = r.inst;
       }
+      auto solving = [&]() {
+        std::lock_guard<std::mutex> lk(mu);
+        reqs[t].phase = 2;
+      };
+      for (Resident& z : freed) release(z);
       spd_instance_result res{};
-      spd::run_instance(inst, s, res);
+      if (reuse) {
+        spd::solve_state(inst, use.A, use.F, s, res);
+      } else {
+        const spd_status st = spd::build_state(inst, s, res, &use.A, &use.M, &use.F);
+        if (st == SPD_OK) {
+          solving();
+          spd::solve_state(inst, use.A, use.F, s, res);
+        } else {
+          res.status = st;
+        }
+        if (!key) {  // nothing stays resident
+          if (use.F) ulv_destroy(use.F);
+          if (use.M) spdhss_destroy(use.M);
+          if (use.A) h2_destroy(use.A);
+          use = Resident{};
+        }
+      }
       {
         std::lock_guard<std::mutex> lk(mu);
         Request& r = reqs[t];
         r.res = res;
         r.t_done = Clock::now();
         r.done = true;
-        in_use -= r.bytes;
+        r.phase = 3;
         --running;
+        if (!key) {
+          in_use -= r.held;
+        } else {
+          Resident& z = resident[key];
+          if (!reuse) {
+            if (use.A && use.F) {  // built: keep it resident, counted in in_use
+              z.A = use.A;
+              z.M = use.M;
+              z.F = use.F;
+              z.ready = true;
+              in_use -= pcg_bytes(&r.inst);
+            } else {  // the build failed: nothing stays
+              in_use -= r.held;
+              resident.erase(key);
+            }
+          } else {
+            in_use -= r.held;
+          }
+          auto it = resident.find(key);
+          if (it != resident.end()) {
+            it->second.busy = false;
+            it->second.last = Clock::now();
+          }
+        }
       }
       cv_done.notify_all();
       cv_work.notify_all();
@@ -120,7 +278,7 @@ spd_status spd_server_create(int32_t workers, int64_t hbm_budget_bytes, spd_serv
   return SPD_OK;
 }
 
-spd_status spd_server_submit(spd_server_t S, const spd_instance* q, int64_t* ticket) {
+static spd_status submit(spd_server_t S, const spd_instance* q, uint64_t key, int64_t* ticket) {
   if (!S || !q || !ticket) {
     spd::set_last_error("null argument");
     return SPD_E_INVALID;
@@ -134,6 +292,7 @@ spd_status spd_server_submit(spd_server_t S, const spd_instance* q, int64_t* tic
     const int64_t t = S->next_ticket++;
     spd_server::Request& r = S->reqs[t];
     r.inst = *q;
+    r.key = key;
     r.bytes = spd_request_footprint(q);
     r.t_submit = Clock::now();
     S->queue.push_back(t);
@@ -141,6 +300,18 @@ spd_status spd_server_submit(spd_server_t S, const spd_instance* q, int64_t* tic
   }
   S->cv_work.notify_all();
   return SPD_OK;
+}
+
+spd_status spd_server_submit(spd_server_t S, const spd_instance* q, int64_t* ticket) {
+  return submit(S, q, 0, ticket);
+}
+
+spd_status spd_server_submit_keyed(spd_server_t S, const spd_instance* q, uint64_t key, int64_t* ticket) {
+  if (key == 0) {
+    spd::set_last_error("key must be nonzero");
+    return SPD_E_INVALID;
+  }
+  return submit(S, q, key, ticket);
 }
 
 spd_status spd_server_wait(spd_server_t S, int64_t ticket, int32_t block, spd_instance_result* result,
@@ -176,6 +347,21 @@ spd_status spd_server_wait(spd_server_t S, int64_t ticket, int32_t block, spd_in
   return SPD_OK;
 }
 
+spd_status spd_server_phase(spd_server_t S, int64_t ticket, int32_t* phase) {
+  if (!S || !phase) {
+    spd::set_last_error("null argument");
+    return SPD_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) {
+    spd::set_last_error("unknown or already collected ticket");
+    return SPD_E_INVALID;
+  }
+  *phase = it->second.phase;
+  return SPD_OK;
+}
+
 void spd_server_destroy(spd_server_t S) {
   if (!S) return;
   {
@@ -184,6 +370,7 @@ void spd_server_destroy(spd_server_t S) {
   }
   S->cv_work.notify_all();
   for (auto& t : S->workers) t.join();
+  for (auto& kv : S->resident) spd_server::release(kv.second);
   delete S;
 }
 

@@ -110,3 +110,81 @@ def test_two_waiters_on_one_ticket(B):
     assert len(got) == 2
     assert sum(1 for v in got if v == B.SPD_E_INVALID) == 1
     assert sum(1 for v in got if v in ("SPD_OK", "SPD_E_NOT_CONVERGED", "SPD_E_NOT_SPD")) == 1
+
+
+def test_keyed_requests_reuse_resident_state(B):
+    # two requests on one matrix (different right-hand sides) and one on another
+    w1, w3 = workloads.batch_instances(count=2, seed=79, n_lo=2000, n_hi=4000)
+    r1 = request(B, w1)
+    r2 = dict(r1, b=B.cols_like(w1.n, 3, "cuda").copy_(
+        torch.from_numpy(workloads.gaussian_matrix(w1.n, 3, 555))))
+    r3 = request(B, w3)
+    ref = [alone(B, r) for r in (r1, r2, r3)]
+    S = B.Server(workers=2)
+    t1 = S.submit(r1, key=7)
+    t2 = S.submit(r2, key=7)
+    t3 = S.submit(r3, key=9)
+    got = [S.wait(t) for t in (t1, t2, t3)]
+    S.close()
+    for (x, it), g, name in zip(ref, got, ("first", "reuse", "other")):
+        print(f"[serve keyed] {name}: h2 {g['seconds_h2']:.3f} s build {g['seconds_build']:.3f} s "
+              f"solve {g['seconds_solve']:.3f} s {g['status']}", flush=True)
+        assert g["status"] == "SPD_OK", name
+        assert g["iters"].tolist() == it.tolist(), name
+        assert np.array_equal(g["x"].cpu().numpy(), x), name
+    assert got[0]["seconds_h2"] > 0 and got[2]["seconds_h2"] > 0
+    assert got[1]["seconds_h2"] == 0.0 and got[1]["seconds_build"] == 0.0  # solved on the resident state
+
+
+def test_resident_state_released_for_admission(B):
+    # a budget that holds one resident state: the second matrix evicts the
+    # first, whose next request then builds it again; results are unchanged
+    w1, w3 = workloads.batch_instances(count=2, seed=80, n_lo=2000, n_hi=3000)
+    r1, r3 = request(B, w1), request(B, w3)
+    ref1, ref3 = alone(B, r1), alone(B, r3)
+    S0 = B.Server(workers=1)
+    budget = max(S0.footprint(r1), S0.footprint(r3)) + 1
+    S0.close()
+    S = B.Server(workers=1, hbm_budget_bytes=budget)
+    g1 = S.wait(S.submit(r1, key=1))
+    g3 = S.wait(S.submit(r3, key=3))
+    g1b = S.wait(S.submit(r1, key=1))
+    S.close()
+    for g, (x, it) in ((g1, ref1), (g3, ref3), (g1b, ref1)):
+        assert g["status"] == "SPD_OK"
+        assert np.array_equal(g["x"].cpu().numpy(), x)
+    assert g1b["seconds_h2"] > 0  # rebuilt: its state had been released for the other matrix
+
+
+def test_keyed_submit_rejects_zero_key(B):
+    w = workloads.batch_instances(count=1, seed=81, n_lo=1500, n_hi=1600)[0]
+    S = B.Server(workers=1)
+    r = request(B, w)
+    import ctypes
+    I = B._Instance()
+    keep = B._fill_instance(I, r)  # noqa: F841
+    t = ctypes.c_int64()
+    assert B.lib.spd_server_submit_keyed(S._h, ctypes.byref(I), ctypes.c_uint64(0), ctypes.byref(t)) != 0
+    S.close()
+
+
+def test_phase_reports_progress(B):
+    w = workloads.batch_instances(count=1, seed=82, n_lo=3000, n_hi=3100)[0]
+    S = B.Server(workers=1)
+    t = S.submit(request(B, w))
+    seen = set()
+    while True:
+        p = S.phase(t)
+        seen.add(p)
+        if p == "finished":
+            break
+        time.sleep(0.001)
+    g = S.wait(t)
+    S.close()
+    assert g["status"] == "SPD_OK" and "finished" in seen
+    with pytest.raises(B.SpdError):
+        S2 = B.Server(workers=1)
+        try:
+            S2.phase(12345)  # unknown ticket
+        finally:
+            S2.close()

@@ -60,13 +60,34 @@ def test_batch_recipe():
 def test_serve_recipe():
     reqs = workloads.serve_requests()
     assert len(reqs) == 64
-    t = np.array([a for a, _ in reqs])
+    t = np.array([a for a, _, _ in reqs])
     assert np.all(np.diff(t) > 0)
     # Poisson arrivals at 20/s: 64 exponential gaps with mean 0.05 s
     gaps = np.diff(np.concatenate([[0.0], t]))
     assert 0.03 < gaps.mean() < 0.07 and gaps.std() / gaps.mean() > 0.6
-    ws = [w for _, w in reqs]
+    ws = [w for _, w, _ in reqs]
+    assert [k for _, _, k in reqs] == list(range(1, 65))  # no repeats: every request its own matrix
     assert all(10_000 <= w.n <= 100_000 and w.point_set == "cube" for w in ws)
     assert {w.kernel for w in ws} == set(workloads.SERVE_KERNELS)
     assert all(0.05 <= w.ell <= 0.5 and 1 <= w.nrhs <= 32 for w in ws)
     assert all((w.shift, w.leaf, w.pcg_tol) == (1e-3, 400, 1e-8) for w in ws)
+
+
+def test_serve_recipe_with_repeats():
+    # the served trace over the full size range, a quarter of the requests on
+    # an earlier request's matrix with new right-hand sides
+    reqs = workloads.serve_requests(count=256, n_hi=1_000_000, repeat=0.25)
+    ws = {k: w for _, w, k in reqs if w.rhs_seed is None}
+    reps = [(w, k) for _, w, k in reqs if w.rhs_seed is not None]
+    assert 30 < len(reps) < 100
+    assert all(10_000 <= w.n <= 1_000_000 for _, w, _ in reqs)
+    assert max(w.n for _, w, _ in reqs) > 300_000
+    for w, k in reps:
+        base = ws[k]  # the matrix of the request it names
+        assert (w.n, w.kernel, w.ell, w.seed_base, w.point_set) == (base.n, base.kernel, base.ell, base.seed_base,
+                                                                    base.point_set)
+        assert np.array_equal(w.points()[:5], base.points()[:5])
+        assert not np.array_equal(w.rhs()[:5, 0], base.rhs()[:5, 0]) or w.nrhs != base.nrhs
+    # without repeats the trace is the one above
+    assert [w.name for _, w, _ in workloads.serve_requests()] == \
+        [w.name for _, w, _ in workloads.serve_requests(repeat=0.0)]

@@ -67,6 +67,7 @@ class Workload:
     pcg_tol: float
     eta: float = 1.0
     seed_base: int = 0
+    rhs_seed: int | None = None  # right-hand sides of a request on another request's matrix
 
     @property
     def s(self) -> int:
@@ -76,7 +77,7 @@ class Workload:
         return points(self.point_set, self.n, 1000 + self.seed_base)
 
     def rhs(self) -> np.ndarray:
-        return gaussian_matrix(self.n, self.nrhs, 2000 + self.seed_base)
+        return gaussian_matrix(self.n, self.nrhs, 2000 + (self.seed_base if self.rhs_seed is None else self.rhs_seed))
 
     def omega(self) -> np.ndarray:
         return gaussian_matrix(self.n, self.s, 3000 + self.seed_base)
@@ -152,19 +153,32 @@ SERVE_SEED = 100 * 1004
 
 
 def serve_requests(count: int = 64, rate: float = 20.0, seed: int = 4004, n_lo: int = 10_000,
-                   n_hi: int = 100_000) -> list:
-    """[(arrival seconds, Workload)] sorted by arrival."""
+                   n_hi: int = 100_000, repeat: float = 0.0) -> list:
+    """[(arrival seconds, Workload, key)] sorted by arrival.  With probability
+    `repeat` a request (after the first) solves new right-hand sides on the
+    matrix of an earlier non-repeated request, drawn uniformly; `key` names
+    the matrix (the index of its first request, plus one)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
+    firsts = []
     for j in range(count):
         t += float(rng.exponential(1.0 / rate))
         n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
         kern = SERVE_KERNELS[int(rng.integers(len(SERVE_KERNELS)))]
         ell = float(rng.uniform(0.05, 0.5))
         nrhs = int(rng.integers(1, 33))
+        again = bool(rng.random() < repeat) if repeat > 0 else False
+        if again and firsts:
+            k = firsts[int(rng.integers(len(firsts)))]
+            base = out[k][1]
+            w = dataclasses.replace(base, name=f"req{j}-on-req{k}-r{nrhs}", nrhs=nrhs,
+                                    rhs_seed=SERVE_SEED + 100_000 + j)
+            out.append((t, w, k + 1))
+            continue
+        firsts.append(j)
         out.append((t, Workload(name=f"req{j}-{kern}-l{ell:.3f}-N{n}-r{nrhs}", n=n, point_set="cube",
                                 kernel=kern, ell=ell, shift=1e-3, leaf=400, h2_tol=1e-8, hss_tol=1e-2,
                                 max_rank=100, oversample=10, nrhs=nrhs, pcg_tol=1e-8,
-                                seed_base=SERVE_SEED + j)))
+                                seed_base=SERVE_SEED + j), j + 1))
     return out
