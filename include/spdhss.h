@@ -154,7 +154,7 @@ typedef enum {
  * SPD and close to A, so its operators can be rounded to FP32; the H^2
  * operator, the residuals and the dot products of PCG stay FP64, so the
  * attainable residual is unchanged).  SPD_SOLVE_F32 halves the bytes of each
- * apply with at most 4 right-hand sides (more columns use the FP64
+ * apply with at most 16 right-hand sides (more columns use the FP64
  * operators); ulv_apply then differs from the FP64 apply by about the FP32
  * rounding of the operators, and pcg_solve switches to the flexible
  * (Polak-Ribiere) beta, which tolerates that inexactness.
@@ -193,13 +193,13 @@ spd_status h2_matvec(spd_h2_t A, const double* x, double* y, int32_t nrhs,
                      int64_t ld, void* stream);
 
 /* h2_matvec with a choice of precision for the stored blocks.  SPD_SOLVE_F32
- * (at most 4 columns) streams FP32 copies of the near-field and coupling
+ * (at most 16 columns) streams FP32 copies of the near-field and coupling
  * blocks (made on first use and kept with the handle, about half the bytes of
  * the FP64 blocks the product reads) and accumulates in FP64; the
  * interpolation, vectors and sums stay FP64.  This is a different operator
  * from the FP64 one: each block entry is rounded to FP32 (relative 6e-8).
  * Argument errors as for h2_matvec; an unknown precision, or SPD_SOLVE_F32
- * with more than 4 columns, gives SPD_E_INVALID. */
+ * with more than 16 columns, gives SPD_E_INVALID. */
 spd_status h2_matvec_ex(spd_h2_t A, const double* x, double* y, int32_t nrhs,
                         int64_t ld, int32_t precision, void* stream);
 
@@ -220,7 +220,7 @@ spd_status pcg_solve(spd_h2_t A, spd_ulv_t M, const double* b, double* x,
                      void* stream, int32_t* iters, double* relres);
 
 /* pcg_solve with a choice of precision for the product inside the iteration
- * (mixed-precision PCG, beyond the paper).  With SPD_SOLVE_F32 (at most 4
+ * (mixed-precision PCG, beyond the paper).  With SPD_SOLVE_F32 (at most 16
  * columns) every iteration applies the FP32-block product of h2_matvec_ex,
  * and the residual is kept honest with the FP64 product: whenever an active
  * column's recursively updated residual has halved since the last
@@ -232,7 +232,7 @@ spd_status pcg_solve(spd_h2_t A, spd_ulv_t M, const double* b, double* x,
  * stopping test, the reported true residuals and the final restarts use the
  * FP64 product, so the result meets rtol against the FP64 operator.
  * op_precision SPD_SOLVE_F64 is pcg_solve.  Errors as for pcg_solve; an
- * unknown precision, or SPD_SOLVE_F32 with more than 4 columns, gives
+ * unknown precision, or SPD_SOLVE_F32 with more than 16 columns, gives
  * SPD_E_INVALID. */
 spd_status pcg_solve_ex(spd_h2_t A, spd_ulv_t M, const double* b, double* x,
                         int32_t nrhs, int64_t ld, double rtol, int32_t maxit,

@@ -405,7 +405,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 def h2_matvec(A: H2Matrix, x: torch.Tensor, out: torch.Tensor | None = None, stream=None,
               precision: str = "f64") -> torch.Tensor:
     """y = A x; precision "f32" streams FP32 copies of the near and coupling
-    blocks (at most 4 columns, FP64 accumulation)."""
+    blocks (at most 16 columns, FP64 accumulation)."""
     x, nc, ld = _as_cols(x, A.n)
     if out is None:
         out = _out_like(x, A.n, nc, ld)
@@ -420,7 +420,7 @@ def pcg_solve(A: H2Matrix, M: ULVFactor | None, b: torch.Tensor, rtol: float = 1
               op_precision: str = "f64"):
     """Returns (x, iterations per column, true relative residual per column).
     op_precision "f32": the iterations use the FP32-block product, with
-    residual replacement by the FP64 product (at most 4 columns)."""
+    residual replacement by the FP64 product (at most 16 columns)."""
     b, nc, ld = _as_cols(b, A.n)
     if out is None:
         out = _out_like(b, A.n, nc, ld)

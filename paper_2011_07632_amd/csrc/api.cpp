@@ -158,8 +158,8 @@ spd_status h2_matvec_ex(spd_h2_t A, const double* x, double* y, int32_t nrhs, in
   SPD_REQUIRE(x != y, SPD_E_INVALID, "x and y must not alias");
   SPD_REQUIRE(precision == SPD_SOLVE_F64 || precision == SPD_SOLVE_F32, SPD_E_INVALID,
               "unknown precision");
-  SPD_REQUIRE(precision == SPD_SOLVE_F64 || nrhs <= 4, SPD_E_INVALID,
-              "the FP32 product takes at most 4 columns");
+  SPD_REQUIRE(precision == SPD_SOLVE_F64 || nrhs <= 16, SPD_E_INVALID,
+              "the FP32 product takes at most 16 columns");
   hipStream_t s = as_stream(stream);
   A->m.s = s;
   double* xt = h2_plan_x(A->m, nrhs);
@@ -192,8 +192,8 @@ spd_status pcg_solve_ex(spd_h2_t A, spd_ulv_t M, const double* b, double* x, int
   SPD_REQUIRE(rtol >= 0 && maxit >= 0, SPD_E_INVALID, "bad rtol or maxit");
   SPD_REQUIRE(op_precision == SPD_SOLVE_F64 || op_precision == SPD_SOLVE_F32, SPD_E_INVALID,
               "unknown precision");
-  SPD_REQUIRE(op_precision == SPD_SOLVE_F64 || nrhs <= 4, SPD_E_INVALID,
-              "the FP32 product takes at most 4 columns");
+  SPD_REQUIRE(op_precision == SPD_SOLVE_F64 || nrhs <= 16, SPD_E_INVALID,
+              "the FP32 product takes at most 16 columns");
   if (M) SPD_REQUIRE(M->m.f->T.N == N, SPD_E_INVALID, "preconditioner size mismatch");
   hipStream_t s = as_stream(stream);
   A->m.s = s;

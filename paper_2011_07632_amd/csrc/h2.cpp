@@ -470,8 +470,8 @@ static void build_plan(H2Model& H, int m, bool f32 = false) {
   hipStream_t s = H.s;
   Arena& a = pl->arena;
   if (f32) {
-    SPD_REQUIRE(m <= 4 && H.plan && H.plan->ncols == m, SPD_E_INVALID,
-                "the FP32 product needs at most 4 columns");
+    SPD_REQUIRE(m <= 16 && H.plan && H.plan->ncols == m, SPD_E_INVALID,
+                "the FP32 product needs at most 16 columns");
     make_f32_blocks(H);
     pl->xt = H.plan->xt;
     pl->yt = H.plan->yt;
@@ -643,11 +643,11 @@ static void build_plan(H2Model& H, int m, bool f32 = false) {
       for (int64_t e = T.near_ptr[v]; e < T.near_ptr[v + 1]; ++e) {
         const int j = T.near_idx[e];
         if (j < v) continue;
-        R.terms.push_back({H.nearA[e], std::max(H.near_ld(v), 16), pl->xt + T.start[j], (int)N,
+        R.terms.push_back({blk(H.nearA, H.nearA32, e), std::max(H.near_ld(v), 16), pl->xt + T.start[j], (int)N,
                            (int)T.size(j), j == v ? -1 : j - lf});
       }
     }
-    rec.symv(a, s, rows, m, 1.0, false);
+    rec.symv(a, s, rows, m, 1.0, f32);
     rec.tag_from(first, 400);
   } else {
     GemmBatch g(0, 0);

@@ -741,7 +741,9 @@ static void launch_symv_ta(hipStream_t s, const SymProblem* d_p, const SymTerm* 
 //              the R strips' parts summed in strip order through LDS)
 // The mirrored product contracts over rows, so each wave transposes its
 // 64 x 16 chunk through its own LDS slot before the second set of MFMAs.  The
-// G groups' row sums are added in group order at the end of the item.
+// G groups' row sums are added in group order at the end of the item.  A
+// operands are FP64, or FP32 copies (TA = float) widened to FP64 as they are
+// loaded; B, X and all arithmetic stay FP64.
 // Every block element is read from HBM once.  Columns past n are zero in the
 // inputs and not written.
 //
@@ -793,9 +795,10 @@ static __device__ inline SymTerm sym_term(const SymTerm* t, int i) {
   return T;
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_symm16(const SymProblem* __restrict__ probs,
-                                                const SymTerm* __restrict__ terms, int tiles_max,
-                                                int nwork, int nprob) {
+template <typename TA>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_symm16(
+    const SymProblem* __restrict__ probs, const SymTerm* __restrict__ terms, int tiles_max, int nwork, int nprob) {
+  constexpr int ES = (int)sizeof(TA);  // bytes of an A element (FP64, or FP32 copies widened on load)
   __shared__ double tr[4][64][17];      // per-wave transpose slot; row-sum exchange between groups
   __shared__ double red[2][4][16][17];  // per-wave mirrored partials, two chunks in flight
   const int lane = threadIdx.x & 63;
@@ -840,10 +843,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     int pc0 = 0, pK = 0;
     // the chunk sequence: term t, chunk c0 = 16 (it G + g), it < niter(t)
     struct Cur {
-      const double* A;
+      const TA* A;
       const double* B;
       double* pt;
-      int lda8, bext;  // A's column stride and B's extent from its first row, in bytes
+      int ldab, bext;  // A's column stride and B's extent from its first row, in bytes
       double sc;
       int K, niter, t, it;
       uint32_t va[4], vb;  // this lane's byte offsets in a chunk's first column
@@ -852,10 +855,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       for (; t < P.term_end; ++t) {
         const SymTerm T = sym_term(terms, t);
         if (T.k <= 0) continue;
-        c.A = T.A;
+        c.A = (const TA*)T.A;
         c.B = T.B;
         c.pt = T.P ? T.P + (int64_t)tile * P.ptile : nullptr;
-        c.lda8 = 8 * T.lda;
+        c.ldab = ES * T.lda;
         c.bext = 8 * ((n - 1) * T.ldb + T.k);
         c.sc = T.scale;
         c.K = T.k;
@@ -863,7 +866,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         c.t = t;
         c.it = 0;
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) c.va[s4] = 8u * (uint32_t)(lk * T.lda + r0 + 16 * s4 + lr);
+        for (int s4 = 0; s4 < 4; ++s4) c.va[s4] = (uint32_t)ES * (uint32_t)(lk * T.lda + r0 + 16 * s4 + lr);
         c.vb = 8u * (uint32_t)(lk + lrc * T.ldb);
         return true;
       }
@@ -878,20 +881,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // zero rows of X in the mirrored product and give row sums that are never
     // stored, and columns past K give mirrored entries that are never stored;
     // values of columns past n reach only outputs that are never stored.
-    auto load = [&](const Cur& c, double (&ra)[4][4], double (&rb)[4]) {
-      const int c0 = 16 * (c.it * G + g);
+    auto issue = [&](const Cur& c, int q, double (&ra)[4][4], double (&rb)[4]) {
+      const int col0 = 16 * (c.it * G + g) + 4 * q, rem = c.K - col0;
+      const __amdgpu_buffer_rsrc_t sa = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(c.A + (int64_t)col0 * (c.ldab / ES)), (short)0, rem > 0 ? rem * c.ldab : 0, kBufWord3);
+      const __amdgpu_buffer_rsrc_t sb = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(c.B + col0), (short)0, rem > 0 ? c.bext - 8 * col0 : 0, kBufWord3);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int col0 = c0 + 4 * q, rem = c.K - col0;
-        const __amdgpu_buffer_rsrc_t sa = __builtin_amdgcn_make_buffer_rsrc(
-            (void*)(c.A + (int64_t)col0 * (c.lda8 >> 3)), (short)0, rem > 0 ? rem * c.lda8 : 0, kBufWord3);
-        const __amdgpu_buffer_rsrc_t sb = __builtin_amdgcn_make_buffer_rsrc(
-            (void*)(c.B + col0), (short)0, rem > 0 ? c.bext - 8 * col0 : 0, kBufWord3);
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
+      for (int s4 = 0; s4 < 4; ++s4) {
+        if constexpr (ES == 8)
           ra[s4][q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sa, c.va[s4], 0, kBufNT));
-        rb[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sb, c.vb, 0, 0));
+        else
+          ra[s4][q] = (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sa, c.va[s4], 0, kBufNT));
       }
+      rb[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sb, c.vb, 0, 0));
+    };
+    auto load = [&](const Cur& c, double (&ra)[4][4], double (&rb)[4]) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) issue(c, q, ra, rb);
     };
     // wait for every load issued so far (the current chunk's), before the
     // next chunk's loads are issued
@@ -908,23 +915,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       double bs[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) bs[q] = (c0 + 4 * q + lk < c.K) ? c.sc * cb[q] : 0.0;
-      const int n0 = 16 * (nx.it * G + g);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4)
           acc[s4] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[s4][q], bs[q], acc[s4], 0, 0, 0);
-        if (more) {
-          const int col0 = n0 + 4 * q, rem = nx.K - col0;
-          const __amdgpu_buffer_rsrc_t sa = __builtin_amdgcn_make_buffer_rsrc(
-              (void*)(nx.A + (int64_t)col0 * (nx.lda8 >> 3)), (short)0, rem > 0 ? rem * nx.lda8 : 0, kBufWord3);
-          const __amdgpu_buffer_rsrc_t sb = __builtin_amdgcn_make_buffer_rsrc(
-              (void*)(nx.B + col0), (short)0, rem > 0 ? nx.bext - 8 * col0 : 0, kBufWord3);
-#pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4)
-            na[s4][q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sa, nx.va[s4], 0, kBufNT));
-          nb[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sb, nx.vb, 0, 0));
-        }
+        if (more) issue(nx, q, na, nb);
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) tr[w][16 * s4 + lr][4 * q + lk] = ca[s4][q];
       }
@@ -1078,12 +1074,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 }
 
 static void launch_symm16(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
-                          int max_m, int cap) {
+                          int max_m, int cap, int a_f32) {
   const int tiles = ceil_div(max_m, 256);
   const int nwork = ceil_div(nprob, 8) * 8 * tiles;
   const int capped = cap > 0 ? std::max(8, cap / 8 * 8) : nwork;
-  hipLaunchKernelGGL(k_symm16, dim3((unsigned)std::min(capped, nwork)), dim3(256), 0, s, d_p, d_t,
-                     tiles, nwork, nprob);
+  const dim3 grid((unsigned)std::min(capped, nwork));
+  if (a_f32)
+    hipLaunchKernelGGL(k_symm16<float>, grid, dim3(256), 0, s, d_p, d_t, tiles, nwork, nprob);
+  else
+    hipLaunchKernelGGL(k_symm16<double>, grid, dim3(256), 0, s, d_p, d_t, tiles, nwork, nprob);
 }
 
 void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
@@ -1091,8 +1090,7 @@ void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int n
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
   if (max_n > 16) throw Error(SPD_E_INVALID, "symmetric-pair product supports at most 16 columns");
   if (max_n > 4) {
-    if (a_f32) throw Error(SPD_E_INVALID, "FP32 blocks in the symmetric product only up to 4 columns");
-    launch_symm16(s, d_p, d_t, nprob, max_m, cap);
+    launch_symm16(s, d_p, d_t, nprob, max_m, cap, a_f32);
     SPD_HIP(hipGetLastError());
     return;
   }

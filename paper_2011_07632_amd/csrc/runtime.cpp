@@ -363,23 +363,25 @@ static double batch_bytes(const GemmBatch& b) {
 // transposed, no gathered rows) runs on the symmetric-pair kernel with no
 // mirrored terms: the row sums alone are C = alpha sum_t scale_t A_t B_t +
 // beta C, with every A read once per 256-row tile.  Launches of fewer than
-// kSymmMinWork tiles stay on the tiled GEMM, which splits them finer.
+// kSymmMinWork tiles stay on the tiled GEMM, which splits them finer, unless
+// their A operands are FP32 copies, which only this kernel reads.
 static constexpr int64_t kSymmMinWork = 1024;
 
 static bool symm_form(const GemmBatch& b) {
-  if (b.transA || b.transB || b.indexed || b.a_f32 || b.max_n < 5 || b.max_n > 16) return false;
+  if (b.transA || b.transB || b.indexed || b.max_n < 5 || b.max_n > 16) return false;
+  const int64_t esz = b.a_f32 ? 4 : 8;
   int64_t work = 0;
   for (const GemmProblem& p : b.probs) {
     if (p.cidx || p.D || p.didx) return false;
     work += (p.m + 255) / 256;
     for (int q = p.term_begin; q < p.term_end; ++q) {
       const GemmTerm& t = b.terms[q];
-      if (t.bidx || 8 * (int64_t)t.lda * t.k >= (1ll << 31) ||
+      if (t.bidx || esz * (int64_t)t.lda * t.k >= (1ll << 31) ||
           8 * ((int64_t)(p.n - 1) * t.ldb + t.k) >= (1ll << 31))
         return false;
     }
   }
-  return work >= kSymmMinWork;
+  return b.a_f32 || work >= kSymmMinWork;
 }
 
 void Recorder::gemm_symm(Arena& a, hipStream_t s, const GemmBatch& b, double bytes) {
@@ -418,6 +420,7 @@ void Recorder::gemm_symm(Arena& a, hipStream_t s, const GemmBatch& b, double byt
   if (terms.empty()) terms.push_back(SymTerm{});
   LaunchRec r{3, keep(a, s, probs), keep(a, s, terms), (int)probs.size(), b.max_m, b.max_n, 0, 0, bytes,
               -1};
+  r.a_f32 = b.a_f32;
   recs.push_back(r);
 }
 
@@ -592,7 +595,7 @@ void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, in
         const MT& g = mt[q];
         const int64_t take = std::min<int64_t>(want, g.k - off);
         // the 5-16 column kernel addresses a term through 32-bit buffer ranges
-        SPD_REQUIRE(n <= 4 || (8 * (int64_t)g.lda * take < (1ll << 31) &&
+        SPD_REQUIRE(n <= 4 || (esz * (int64_t)g.lda * take < (1ll << 31) &&
                                8 * ((int64_t)(n - 1) * g.ldb + take) < (1ll << 31)),
                     SPD_E_INVALID, "symmetric-pair term above 2 GiB of addressed bytes");
         SymTerm t{};

@@ -192,8 +192,9 @@ static std::unique_ptr<ULVModel::ApplyPlan> make_apply_plan(ULVModel& U, int m, 
   const int lf = T.first_at(1), lc = T.count_at(1);
   const int Ni = (int)N;
   const int tA = m <= 4 ? 1 : 0;
-  // mixed precision: FP32 operators in the dot-form products (<= 4 columns)
-  const bool f32 = tA && U.precision == 1;
+  // mixed precision: FP32 operators, read by the dot-form products (<= 4
+  // columns) or by the symmetric-pair kernel's row sums (5-16 columns)
+  const bool f32 = U.precision == 1 && m <= 16;
   auto op = [&](const std::vector<double*>& d, const std::vector<float*>& f, int v) -> const double* {
     return f32 ? (const double*)f[v] : d[v];
   };
@@ -220,7 +221,7 @@ static std::unique_ptr<ULVModel::ApplyPlan> make_apply_plan(ULVModel& U, int m, 
       if (F.r[v] == 0) continue;
       g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
       if (tA) g.term(op(F.Zs, F.Zs32, v), F.rho[v], pl->in + T.start[v], Ni, F.rho[v]);
-      else g.term(F.ZsT[v], F.r[v], pl->in + T.start[v], Ni, F.rho[v]);
+      else g.term(op(F.ZsT, F.ZsT32, v), F.r[v], pl->in + T.start[v], Ni, F.rho[v]);
     }
     rec.gemm(a, s, g);
   }
@@ -231,7 +232,7 @@ static std::unique_ptr<ULVModel::ApplyPlan> make_apply_plan(ULVModel& U, int m, 
       if (F.r[v] == 0 || F.rho[v] == 0) continue;
       g.add(F.blk(pl->ts, v, m), F.r[v], m, F.blk_ld(v));
       if (tA) g.term(op(F.Zs, F.Zs32, v), F.rho[v], pl->ts + F.par_off[v] * m, F.rho[v], F.rho[v]);
-      else g.term(F.ZsT[v], F.r[v], pl->ts + F.par_off[v] * m, F.rho[v], F.rho[v]);
+      else g.term(op(F.ZsT, F.ZsT32, v), F.r[v], pl->ts + F.par_off[v] * m, F.rho[v], F.rho[v]);
     }
     rec.gemm(a, s, g);
   }
@@ -253,7 +254,7 @@ static std::unique_ptr<ULVModel::ApplyPlan> make_apply_plan(ULVModel& U, int m, 
       g.term(op(F.Dm, F.Dm32, v), rv, pl->ts + F.par_off[v] * m, rv, rv);
       if (F.r[v] > 0) {
         if (tA) g.term(op(F.ZsT, F.ZsT32, v), F.r[v], F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
-        else g.term(F.Zs[v], rv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
+        else g.term(op(F.Zs, F.Zs32, v), rv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
       }
     }
     rec.gemm(a, s, g);
@@ -267,7 +268,7 @@ static std::unique_ptr<ULVModel::ApplyPlan> make_apply_plan(ULVModel& U, int m, 
       g.term(op(F.Dm, F.Dm32, v), nv, pl->in + T.start[v], Ni, nv);
       if (F.r[v] > 0) {
         if (tA) g.term(op(F.ZsT, F.ZsT32, v), F.r[v], F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
-        else g.term(F.Zs[v], nv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
+        else g.term(op(F.Zs, F.Zs32, v), nv, F.blk(pl->ds, v, m), F.blk_ld(v), F.r[v]);
       }
     }
     rec.gemm(a, s, g);

@@ -35,7 +35,9 @@ def cols(B, a):
     return B.cols_like(a.shape[0], a.shape[1], "cuda").copy_(torch.from_numpy(np.ascontiguousarray(a)))
 
 
-@pytest.mark.parametrize("nrhs", [1, 3])
+# 1-4 columns: the dot-form products with FP32 operators; 5-16: the
+# symmetric-pair kernel's row sums with FP32 A operands
+@pytest.mark.parametrize("nrhs", [1, 3, 5, 16])
 def test_f32_apply_against_oracle(S, nrhs):
     B, perm = S["B"], S["o_h2"].tree.perm
     b = workloads.gaussian_matrix(W.n, nrhs, 31)
@@ -63,16 +65,16 @@ def test_f32_pcg_reaches_fp64_tolerance(S):
     assert abs(int(it32[0]) - int(ito[0])) <= 3
 
 
-def test_more_than_four_columns_use_fp64_operators(S):
+def test_more_than_sixteen_columns_use_fp64_operators(S):
     B, perm = S["B"], S["o_h2"].tree.perm
-    b = workloads.gaussian_matrix(W.n, 5, 41)
+    b = workloads.gaussian_matrix(W.n, 17, 41)
     xo = np.empty_like(b)
     xo[perm] = S["o_hss"].solve(b[perm])
     x32 = B.ulv_apply(S["u32"], cols(B, b)).cpu().numpy()
     assert np.linalg.norm(x32 - xo) / np.linalg.norm(xo) <= 1e-10
 
 
-@pytest.mark.parametrize("nrhs", [1, 2, 4])
+@pytest.mark.parametrize("nrhs", [1, 2, 4, 5, 16])
 def test_f32_product_against_oracle(S, nrhs):
     B, perm = S["B"], S["o_h2"].tree.perm
     x = workloads.gaussian_matrix(W.n, nrhs, 51)
@@ -88,10 +90,10 @@ def test_f32_product_against_oracle(S, nrhs):
     assert e32 > e64
 
 
-@pytest.mark.parametrize("pre", ["f64", "f32"])
-def test_f32_operator_pcg_reaches_fp64_tolerance(S, pre):
+@pytest.mark.parametrize("pre,ncols", [("f64", 3), ("f32", 3), ("f32", 16)])
+def test_f32_operator_pcg_reaches_fp64_tolerance(S, pre, ncols):
     B = S["B"]
-    b = workloads.gaussian_matrix(W.n, 3, 61)
+    b = workloads.gaussian_matrix(W.n, ncols, 61)
     M = S["u64"] if pre == "f64" else S["u32"]
     x, it, res = B.pcg_solve(S["h2"], M, cols(B, b), rtol=W.pcg_tol, maxit=500, op_precision="f32")
     _, it64, _ = B.pcg_solve(S["h2"], M, cols(B, b), rtol=W.pcg_tol, maxit=500)
@@ -108,7 +110,7 @@ def test_f32_operator_pcg_reaches_fp64_tolerance(S, pre):
 def test_f32_product_argument_errors(S):
     B = S["B"]
     with pytest.raises(B.SpdError):
-        B.h2_matvec(S["h2"], cols(B, workloads.gaussian_matrix(W.n, 5, 1)), precision="f32")
+        B.h2_matvec(S["h2"], cols(B, workloads.gaussian_matrix(W.n, 17, 1)), precision="f32")
     import ctypes as C
     x = cols(B, workloads.gaussian_matrix(W.n, 1, 1))
     y = torch.empty_like(x)
