@@ -63,12 +63,22 @@ typedef enum {
  *   MATERN32     (1 + sqrt(3) r / ell) exp(-sqrt(3) r / ell)
  *   EXPONENTIAL  exp(-r / ell)
  *   IMQ          1 / sqrt(r^2 + ell^2)
+ *   RPY          the Rotne-Prager-Yamakawa 3 x 3 tensor with particle radius
+ *                a = ell (Section 6; self term I / a, and for r = x - y,
+ *                rr = r r^T / |r|^2: 3/(4|r|)(I + rr) + 3a^2/(2|r|^3)(I/3 - rr)
+ *                for |r| >= 2a, (1/a)(1 - 9|r|/(32a)) I + 3|r|/(32a^2) rr
+ *                below).  The matrix has 3N rows, row 3p + c being component
+ *                c of point p: every vector of the handle (b, x, y) has 3N
+ *                rows, and N in the sizes and leading dimensions below means
+ *                3N.  The proxy spheres of its ID hold twice proxy_per_shell
+ *                points each (capped at proxy_per_shell_max), 3 columns a point.
  * The matrix is shift * I + K(X, X) (Section 6 kernels, Section 6.2 shift). */
 typedef enum {
   SPD_K_GAUSSIAN = 0,
   SPD_K_MATERN32 = 1,
   SPD_K_EXPONENTIAL = 2,
-  SPD_K_IMQ = 3
+  SPD_K_IMQ = 3,
+  SPD_K_RPY = 4
 } spd_kernel_kind;
 
 typedef struct {
@@ -244,7 +254,8 @@ spd_status pcg_solve_ex(spd_h2_t A, spd_ulv_t M, const double* b, double* x,
  * spdhss_build, then pcg_solve of b (nrhs columns) preconditioned by the
  * factored HSS matrix with the given solve precision.  All arrays are DEVICE
  * except iters/relres (HOST, nrhs entries each, may be NULL).  b and x are
- * N x nrhs with ld = N, original point order. */
+ * N x nrhs with ld = N, original point order (3N rows, row 3p + c, for the
+ * RPY tensor). */
 typedef struct {
   const double* points;     /* DEVICE n x 3 row-major */
   int64_t n;

@@ -84,7 +84,11 @@ class H2:
     def __init__(self, X, kind, ell, shift, leaf, tol, eta=1.0,
                  shells=8, per_shell=128, per_shell_max=2048, density=90.0,
                  sketch_seed=SKETCH_SEED, tree: Tree | None = None):
-        self.X = np.ascontiguousarray(X, dtype=np.float64)
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        # a tensor kernel acts on 3 rows per point: row 3p + c is point p's
+        # component c, and the tree partitions the rows (3 coincident entries a point)
+        self.comp = np.tile(np.arange(3), X.shape[0]) if kind in kernels.TENSOR else None
+        self.X = np.repeat(X, 3, axis=0) if self.comp is not None else X
         self.kind, self.ell, self.shift, self.tol = kind, float(ell), float(shift), float(tol)
         self.shells, self.per_shell = int(shells), int(per_shell)
         self.per_shell_max, self.density = max(int(per_shell_max), int(per_shell)), float(density)
@@ -109,6 +113,8 @@ class H2:
                 self.near_blocks[(i, j)] = blk
 
     def K(self, ia, ib) -> np.ndarray:
+        if self.comp is not None:
+            return kernels.evaluate(self.kind, self.ell, self.X[ia], self.X[ib], self.comp[ia], self.comp[ib])
         return kernels.evaluate(self.kind, self.ell, self.X[ia], self.X[ib])
 
     # -- construction --------------------------------------------------------
@@ -126,7 +132,13 @@ class H2:
         rout = float(np.sqrt(dc[:, 0] * dc[:, 0] + dc[:, 1] * dc[:, 1] + dc[:, 2] * dc[:, 2]).max())
         rout = max(rout, rin)
         Q = self.shells
-        P = proxy_count(rin, self.ell, self.per_shell, self.per_shell_max, self.density)
+        # a tensor kernel's ell is the particle radius, not a length scale of
+        # its far field (which decays like 1/r): the per-sphere count is fixed
+        # at twice per_shell (each proxy point then gives 3 columns)
+        if self.comp is not None:
+            P = min(2 * self.per_shell, self.per_shell_max)
+        else:
+            P = proxy_count(rin, self.ell, self.per_shell, self.per_shell_max, self.density)
         self.proxy_n[v] = P
         unit = fibonacci_sphere(P)
         pts = []
@@ -152,7 +164,12 @@ class H2:
                     self.skel[v] = cand[:0]
                     self.W[v] = np.zeros((len(cand), 0))
                     continue
-                G = kernels.evaluate(self.kind, self.ell, self.X[cand], P)
+                if self.comp is not None:
+                    # every proxy point carries the 3 components: column 3q + c
+                    G = kernels.evaluate(self.kind, self.ell, self.X[cand], np.repeat(P, 3, axis=0),
+                                         self.comp[cand], np.tile(np.arange(3), len(P)))
+                else:
+                    G = kernels.evaluate(self.kind, self.ell, self.X[cand], P)
                 c, M = G.shape
                 l = sketch_rows(c)
                 self.sketched[v] = M > l

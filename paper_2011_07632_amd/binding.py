@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # the in-tree build; importing without it raises (there is no fallback)
 LIB_PATH = os.path.join(HERE, "libspdhss.so")
 
-KERNELS = {"gaussian": 0, "matern32": 1, "exponential": 2, "imq": 3}
+KERNELS = {"gaussian": 0, "matern32": 1, "exponential": 2, "imq": 3, "rpy": 4}
 
 SPD_OK, SPD_E_INVALID, SPD_E_NOMEM, SPD_E_NOT_SPD, SPD_E_NOT_CONVERGED, SPD_E_DEVICE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {1: "SPD_PENDING", 0: "SPD_OK", -1: "SPD_E_INVALID", -2: "SPD_E_NOMEM", -3: "SPD_E_NOT_SPD",
@@ -349,7 +349,9 @@ def h2_build(points: torch.Tensor, kernel: str, ell: float, shift: float, leaf: 
                                       proxy_density=proxy_density, sketch_seed=sketch_seed))
     out = C.c_void_p()
     _check(lib.h2_build(points.data_ptr(), points.shape[0], k, C.byref(o), _stream(stream), C.byref(out)))
-    return H2Matrix(out.value, points.shape[0], points.device)
+    # rows of the matrix: one per point, three for the RPY tensor
+    rows = 3 * points.shape[0] if kernel == "rpy" else points.shape[0]
+    return H2Matrix(out.value, rows, points.device)
 
 
 def spdhss_build(A: H2Matrix, tol: float, max_rank: int = 100, oversample: int = 10, seed: int = 0,
@@ -507,15 +509,16 @@ def _fill_instance(I: _Instance, d: dict):
     if not P.is_cuda or P.dtype != torch.float64 or P.dim() != 2 or P.shape[1] != 3:
         raise ValueError("points must be an (N, 3) float64 device tensor")
     P = P.contiguous()
-    b, nc, ld = _as_cols(d["b"], P.shape[0])
-    if ld != P.shape[0]:
-        raise ValueError("b must have ld = N")
-    x = cols_like(P.shape[0], nc, P.device)
+    rows = 3 * P.shape[0] if d["kernel"] == "rpy" else P.shape[0]  # 3 rows a particle for the tensor
+    b, nc, ld = _as_cols(d["b"], rows)
+    if ld != rows:
+        raise ValueError("b must have ld = N (3N for the RPY tensor)")
+    x = cols_like(rows, nc, P.device)
     om = d.get("omega")
     if om is not None:
-        om, nco, ldo = _as_cols(om, P.shape[0])
-        if nco != int(d["max_rank"]) + int(d["oversample"]) or ldo != P.shape[0]:
-            raise ValueError("omega must be (N, max_rank + oversample) with ld = N")
+        om, nco, ldo = _as_cols(om, rows)
+        if nco != int(d["max_rank"]) + int(d["oversample"]) or ldo != rows:
+            raise ValueError("omega must be (rows, max_rank + oversample) with ld = rows")
     it = np.zeros(nc, dtype=np.int32)
     rr = np.zeros(nc, dtype=np.float64)
     I.points, I.n = P.data_ptr(), P.shape[0]

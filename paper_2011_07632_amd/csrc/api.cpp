@@ -62,7 +62,7 @@ spd_status h2_build(const double* points, int64_t n, spd_kernel kernel, const sp
   SPD_REQUIRE(points && out && opts, SPD_E_INVALID, "null argument");
   SPD_REQUIRE(n >= 1, SPD_E_INVALID, "n must be positive");
   SPD_REQUIRE(n < (int64_t(1) << 31), SPD_E_INVALID, "n must be below 2^31");
-  SPD_REQUIRE(kernel.kind >= 0 && kernel.kind <= 3, SPD_E_INVALID, "unknown kernel kind");
+  SPD_REQUIRE(kernel.kind >= 0 && kernel.kind <= 4, SPD_E_INVALID, "unknown kernel kind");
   SPD_REQUIRE(kernel.ell > 0 && std::isfinite(kernel.ell), SPD_E_INVALID, "ell must be positive");
   SPD_REQUIRE(std::isfinite(kernel.shift), SPD_E_INVALID, "shift must be finite");
   SPD_REQUIRE(opts->leaf_size >= 1 && opts->leaf_size <= 512, SPD_E_INVALID,

@@ -55,7 +55,8 @@ void solve_state(const spd_instance& I, spd_h2_t A, spd_ulv_t F, hipStream_t s, 
   std::vector<int32_t> it(std::max(I.nrhs, 1));
   std::vector<double> rr(std::max(I.nrhs, 1));
   const auto t0 = std::chrono::steady_clock::now();
-  const spd_status st = pcg_solve(A, F, I.b, I.x, I.nrhs, I.n, I.rtol, I.maxit, s, it.data(), rr.data());
+  const int64_t rows = I.kernel.kind == SPD_K_RPY ? 3 * I.n : I.n;  // 3 rows a particle for the tensor
+  const spd_status st = pcg_solve(A, F, I.b, I.x, I.nrhs, rows, I.rtol, I.maxit, s, it.data(), rr.data());
   R.seconds_solve = seconds_since(t0);
   if (st == SPD_OK || st == SPD_E_NOT_CONVERGED) {
     for (int c = 0; c < I.nrhs; ++c) {

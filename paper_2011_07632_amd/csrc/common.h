@@ -173,9 +173,11 @@ void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int
                  int max_m, int max_n, int transA, int transB, int max_k = 1 << 30, int a_f32 = 0);
 void launch_block(hipStream_t s, const BlockProblem* d_p, const BlockTerm* d_t,
                   int nprob, int max_m, int max_n);
+// perm: tree position -> original index (for the RPY tensor, whose rows are
+// point components: component = original index mod 3); may be null otherwise
 void launch_kblock(hipStream_t s, const KBlockProblem* d_p, int nprob, int max_m,
                    int max_n, const double* px, int64_t stride, int kind,
-                   double ell, double shift);
+                   double ell, double shift, const int64_t* perm);
 void launch_chol(hipStream_t s, const CholProblem* d_p, int nprob, int max_n,
                  int* d_fail);
 void launch_trsm(hipStream_t s, const TrsmProblem* d_p, int nprob, int max_n,

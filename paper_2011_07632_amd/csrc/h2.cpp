@@ -91,19 +91,39 @@ static void upper_solve_blocked(hipStream_t s, Stage& st, const std::vector<Uppe
   }
 }
 
-void h2_build_impl(H2Model& H, const double* points, int64_t n) {
+void h2_build_impl(H2Model& H, const double* points, int64_t npts) {
   hipStream_t s = H.s;
   const double t0 = now_seconds();
-  std::vector<double> hp((size_t)3 * n);
-  SPD_HIP(hipMemcpyAsync(hp.data(), points, (size_t)3 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<double> hp((size_t)3 * npts);
+  SPD_HIP(hipMemcpyAsync(hp.data(), points, (size_t)3 * npts * sizeof(double), hipMemcpyDeviceToHost, s));
   SPD_HIP(hipStreamSynchronize(s));
   for (double x : hp) SPD_REQUIRE(std::isfinite(x), SPD_E_INVALID, "non-finite point coordinate");
+  // The RPY tensor acts on 3 rows per particle (row 3p + c is component c of
+  // particle p): the tree, lists and IDs work on these rows, each placed at
+  // its particle, and the kernel blocks read a row's component from its
+  // original index.
+  const bool tensor = H.kern.kind == SPD_K_RPY;
+  const int64_t n = tensor ? 3 * npts : npts;
+  if (tensor) {
+    std::vector<double> h3((size_t)3 * n);
+    for (int64_t p = 0; p < npts; ++p)
+      for (int c = 0; c < 3; ++c)
+        for (int k = 0; k < 3; ++k) h3[(size_t)3 * (3 * p + c) + k] = hp[(size_t)3 * p + k];
+    hp.swap(h3);
+  }
   TreeHost& T = H.T;
   T.build(hp.data(), n, H.opts.leaf_size, H.opts.eta);
   const int nn = T.nnodes, L = T.L;
   H.perm_d = upload(H.arena, s, T.perm);
   H.pts = H.arena.get_n<double>((size_t)3 * n);
-  launch_soa_points(s, points, H.perm_d, n, H.pts);
+  if (tensor) {
+    double* rows = H.arena.get_n<double>((size_t)3 * n);
+    SPD_HIP(hipMemcpyAsync(rows, hp.data(), (size_t)3 * n * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_soa_points(s, rows, H.perm_d, n, H.pts);
+    SPD_HIP(hipStreamSynchronize(s));
+  } else {
+    launch_soa_points(s, points, H.perm_d, n, H.pts);
+  }
   const double t1 = now_seconds();
 
   H.k.assign(nn, 0);
@@ -147,9 +167,13 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
       jb.v = v;
       jb.rin = rin;
       jb.rout = rout;
-      jb.per = proxy_count(rin, H.kern.ell, H.opts.proxy_per_shell, H.opts.proxy_per_shell_max,
-                           H.opts.proxy_density);
-      jb.M = Q * jb.per;
+      // the RPY tensor: its ell is the particle radius, not a length scale of
+      // a far field that decays like 1/r, so the count per sphere is fixed at
+      // twice proxy_per_shell, and every proxy point gives 3 columns
+      jb.per = tensor ? std::min(2 * H.opts.proxy_per_shell, H.opts.proxy_per_shell_max)
+                      : proxy_count(rin, H.kern.ell, H.opts.proxy_per_shell, H.opts.proxy_per_shell_max,
+                                    H.opts.proxy_density);
+      jb.M = Q * jb.per * (tensor ? 3 : 1);
       jb.c = H.cand[v];
       const int l = std::max(2 * jb.c, jb.c + 16);
       jb.sk = jb.M > l;
@@ -238,7 +262,7 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
         cp.nrm = tmp.get_n<double>(c);
       }
       auto* dkb = (const KBlockProblem*)st.push(s, kb.data(), kb.size() * sizeof(KBlockProblem));
-      launch_kblock(s, dkb, nj, maxM, maxc, H.pts, n, H.kern.kind, H.kern.ell, H.kern.shift);
+      launch_kblock(s, dkb, nj, maxM, maxc, H.pts, n, H.kern.kind, H.kern.ell, H.kern.shift, H.perm_d);
       if (!sketch.empty()) {
         launch_sketch_fill(s, Om, om_rows, (int)om_cols, om_rows, H.opts.sketch_seed);
         sketch.run(s, st);
@@ -386,7 +410,7 @@ void h2_build_impl(H2Model& H, const double* points, int64_t n) {
     for (size_t a = 0; a < kb.size(); a += chunk) {
       const size_t b = std::min(kb.size(), a + chunk);
       auto* d = (const KBlockProblem*)st.push(s, kb.data() + a, (b - a) * sizeof(KBlockProblem));
-      launch_kblock(s, d, (int)(b - a), mm, mn, H.pts, n, H.kern.kind, H.kern.ell, H.kern.shift);
+      launch_kblock(s, d, (int)(b - a), mm, mn, H.pts, n, H.kern.kind, H.kern.ell, H.kern.shift, H.perm_d);
     }
     SPD_HIP(hipStreamSynchronize(s));
     st.reset();

@@ -1215,11 +1215,33 @@ __device__ __forceinline__ void proxy_point(const KBlockProblem& P, int t, doubl
   z = P.cz + rad * zz;
 }
 
+// Entry [ca][cb] of the RPY tensor with particle radius a at r = (dx, dy, dz)
+// (Section 6, normalized so that the self term is I / a):
+//   |r| >= 2a:  3/(4|r|) (I + rr) + 3a^2/(2|r|^3) (I/3 - rr)
+//   |r| <  2a:  (1/a)(1 - 9|r|/(32a)) I + 3|r|/(32a^2) rr,   rr = r r^T / |r|^2
+// (the two branches agree at |r| = 2a).
+__device__ __forceinline__ double rpy_entry(double a, double dx, double dy, double dz, int ca, int cb) {
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double eye = ca == cb ? 1.0 : 0.0;
+  if (r2 == 0.0) return eye / a;
+  const double d[3] = {dx, dy, dz};
+  const double r = sqrt(r2);
+  const double rr = d[ca] * d[cb] / r2;
+  if (r >= 2.0 * a) return 0.75 / r * (eye + rr) + 1.5 * a * a / (r2 * r) * (eye / 3.0 - rr);
+  return (1.0 - 9.0 * r / (32.0 * a)) / a * eye + 3.0 * r / (32.0 * a * a) * rr;
+}
+
+// Dense kernel blocks.  For the RPY tensor every row and column is a point's
+// component: a point's component is its original index mod 3 (row 3p + c is
+// component c of particle p), and proxy index t is component t mod 3 of proxy
+// point t / 3.
 __global__ __launch_bounds__(256) void k_kblock(const KBlockProblem* __restrict__ probs,
                                                 int tiles_max, const double* __restrict__ px,
                                                 int64_t stride, int kind, double ell,
-                                                double shift) {
+                                                double shift, const int64_t* __restrict__ perm) {
   __shared__ double ax[64], ay[64], az[64], bx[64], by[64], bz[64];
+  __shared__ int ac[64], bc[64];
+  const bool tensor = kind == SPD_K_RPY;
   const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
   const KBlockProblem P = probs[p];
   const int tm = (P.na + 63) / 64, tn = (P.nb + 63) / 64;
@@ -1230,17 +1252,21 @@ __global__ __launch_bounds__(256) void k_kblock(const KBlockProblem* __restrict_
     const int i = i0 + tid;
     if (i < P.na) {
       double x, y, z;
+      int c = 0;
       if (P.proxy) {
-        proxy_point(P, i, x, y, z);
+        proxy_point(P, tensor ? i / 3 : i, x, y, z);
+        c = tensor ? i % 3 : 0;
       } else {
         const int64_t g = P.ia ? (int64_t)P.ia[i] : P.offa + i;
         x = px[g];
         y = px[g + stride];
         z = px[g + 2 * stride];
+        c = tensor ? (int)(perm[g] % 3) : 0;
       }
       ax[tid] = x;
       ay[tid] = y;
       az[tid] = z;
+      ac[tid] = c;
     }
   } else if (tid < 128) {
     const int j = j0 + tid - 64;
@@ -1249,6 +1275,7 @@ __global__ __launch_bounds__(256) void k_kblock(const KBlockProblem* __restrict_
       bx[tid - 64] = px[g];
       by[tid - 64] = px[g + stride];
       bz[tid - 64] = px[g + 2 * stride];
+      bc[tid - 64] = tensor ? (int)(perm[g] % 3) : 0;
     }
   }
   __syncthreads();
@@ -1257,21 +1284,27 @@ __global__ __launch_bounds__(256) void k_kblock(const KBlockProblem* __restrict_
     const int i = i0 + il, j = j0 + jl;
     if (i >= P.na || j >= P.nb) continue;
     const double dx = ax[il] - bx[jl], dy = ay[il] - by[jl], dz = az[il] - bz[jl];
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    double v = kfun(kind, ell, r2);
+    double v;
+    if (tensor) {
+      v = rpy_entry(ell, dx, dy, dz, ac[il], bc[jl]);
+    } else {
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      v = kfun(kind, ell, r2);
+    }
     if (P.diag_shift && i == j) v += shift;
     P.out[i + (int64_t)j * P.ld] = v;
   }
 }
 
 void launch_kblock(hipStream_t s, const KBlockProblem* d_p, int nprob, int max_m, int max_n,
-                   const double* px, int64_t stride, int kind, double ell, double shift) {
+                   const double* px, int64_t stride, int kind, double ell, double shift,
+                   const int64_t* perm) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
   const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 64);
   const int per = probs_per_launch(tiles, 256);
   for (int p0 = 0; p0 < nprob; p0 += per)
     hipLaunchKernelGGL(k_kblock, dim3((unsigned)std::min(per, nprob - p0) * tiles), dim3(256), 0, s,
-                       d_p + p0, tiles, px, stride, kind, ell, shift);
+                       d_p + p0, tiles, px, stride, kind, ell, shift, perm);
   SPD_HIP(hipGetLastError());
 }
 

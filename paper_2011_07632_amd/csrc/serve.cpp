@@ -22,8 +22,10 @@ using Clock = std::chrono::steady_clock;
 
 // Device bytes of a request's PCG vectors (the part of the footprint that a
 // request solving on resident state still needs).
+static int64_t rows_of(const spd_instance* q) { return q->kernel.kind == SPD_K_RPY ? 3 * q->n : q->n; }
+
 static int64_t pcg_bytes(const spd_instance* q) {
-  return (int64_t)(8.0 * (double)q->n * 8.0 * std::max(q->nrhs, 1));
+  return (int64_t)(8.0 * (double)rows_of(q) * 8.0 * std::max(q->nrhs, 1));
 }
 
 struct spd_server {
@@ -250,7 +252,7 @@ extern "C" {
 
 int64_t spd_request_footprint(const spd_instance* q) {
   if (!q || q->n <= 0) return 0;
-  const double n = (double)q->n, leaf = std::max(q->h2.leaf_size, 1);
+  const double n = (double)rows_of(q), leaf = std::max(q->h2.leaf_size, 1);
   const double s = std::max(q->hss.max_rank + q->hss.oversample, 1);
   // points; near blocks (about 27 neighbours a leaf); coupling blocks (taken
   // as 60 leaf-sized blocks a leaf); samples and their level stacks; HSS

@@ -62,7 +62,7 @@ def _h2_args(**kw):
 @pytest.mark.parametrize("n,bad,msg", [
     (0, {}, b"n must be positive"),
     (1 << 31, {}, b"below 2^31"),
-    (100, {"kind": 4}, b"unknown kernel"),
+    (100, {"kind": 5}, b"unknown kernel"),
     (100, {"ell": 0.0}, b"ell"),
     (100, {"ell": float("nan")}, b"ell"),
     (100, {"shift": float("inf")}, b"shift"),

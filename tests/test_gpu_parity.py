@@ -69,6 +69,10 @@ CASES = {
     "r200": dict(w=workloads.SMALL.with_(name="exp-l0.1-N4096-r200", n=4096, kernel="exponential", ell=0.1,
                                          shift=1e-2, leaf=256, max_rank=200, hss_tol=0.0, seed_base=31),
                  shells=4, per_shell=64),
+    # the RPY tensor (3 rows per particle, no shift): 2,000 particles of radius
+    # 0.29 at unit density in a ball, 6,000 rows in leaves of 90 rows
+    "rpy2000": dict(w=workloads.RPY_SMALL.with_(name="rpy-a0.29-N2000-ball1", n=2000, leaf=90),
+                    shells=8, per_shell=128),
     # inverse multiquadric, fixed-rank form (tol = 0)
     "imq1200": dict(w=workloads.SMALL.with_(name="imq-c0.1-N1200", n=1200, kernel="imq", ell=0.1,
                                             shift=1e-3, leaf=30, max_rank=20, hss_tol=0.0, seed_base=9),
@@ -100,7 +104,7 @@ class Pair:
                                tol=w.h2_tol, eta=w.eta, proxy_shells=c["shells"],
                                proxy_per_shell=c["per_shell"])
         self.g_hss = B.spdhss_build(self.g_h2, w.hss_tol, w.max_rank, w.oversample,
-                                    omega=B.cols_like(w.n, w.s, "cuda").copy_(torch.from_numpy(om)))
+                                    omega=B.cols_like(w.rows, w.s, "cuda").copy_(torch.from_numpy(om)))
         self.g_ulv = B.ulv_factor(self.g_hss)
 
 
@@ -142,8 +146,8 @@ def test_h2_skeletons_exact(P):
 @pytest.mark.parametrize("nrhs", [1, 2, 3, 5, 16])
 def test_h2_matvec(P, nrhs):
     rng = np.random.default_rng(1)
-    x = rng.standard_normal((P.w.n, nrhs))
-    xg = P.B.cols_like(P.w.n, nrhs, "cuda").copy_(torch.from_numpy(x))
+    x = rng.standard_normal((P.w.rows, nrhs))
+    xg = P.B.cols_like(P.w.rows, nrhs, "cuda").copy_(torch.from_numpy(x))
     y = P.B.h2_matvec(P.g_h2, xg).cpu().numpy()
     yo = np.empty_like(x)
     yo[P.T.perm] = P.o_h2.matvec(x[P.T.perm])
@@ -180,8 +184,8 @@ def test_leaf_factors(P):
 
 
 def test_ulv_apply(P):
-    b = workloads.gaussian_matrix(P.w.n, 4, 77)
-    bg = P.B.cols_like(P.w.n, 4, "cuda").copy_(torch.from_numpy(b))
+    b = workloads.gaussian_matrix(P.w.rows, 4, 77)
+    bg = P.B.cols_like(P.w.rows, 4, "cuda").copy_(torch.from_numpy(b))
     x = P.B.ulv_apply(P.g_ulv, bg).cpu().numpy()
     xo = np.empty_like(b)
     xo[P.T.perm] = P.o_hss.solve(b[P.T.perm])
@@ -190,7 +194,7 @@ def test_ulv_apply(P):
 
 def test_pcg_fixed_iterations(P):
     b = P.w.rhs()
-    bg = P.B.cols_like(P.w.n, b.shape[1], "cuda").copy_(torch.from_numpy(b))
+    bg = P.B.cols_like(P.w.rows, b.shape[1], "cuda").copy_(torch.from_numpy(b))
     for k in (1, 5):
         x, it, _ = P.B.pcg_solve(P.g_h2, P.g_ulv, bg, rtol=0.0, maxit=k, raise_on_nonconvergence=False)
         xo_t, ito, _ = opcg(P.o_h2.matvec, P.o_hss.solve, b[P.T.perm], 0.0, k)
@@ -204,8 +208,8 @@ def test_pcg_fixed_iterations_16_columns(P):
     """16 right-hand sides (the N = 1M workload's width): the MFMA symmetric-pair
     product, the MFMA apply and the per-column recurrences against the oracle
     at fixed iteration counts."""
-    b = workloads.gaussian_matrix(P.w.n, 16, 2016)
-    bg = P.B.cols_like(P.w.n, 16, "cuda").copy_(torch.from_numpy(b))
+    b = workloads.gaussian_matrix(P.w.rows, 16, 2016)
+    bg = P.B.cols_like(P.w.rows, 16, "cuda").copy_(torch.from_numpy(b))
     x, it, _ = P.B.pcg_solve(P.g_h2, P.g_ulv, bg, rtol=0.0, maxit=4, raise_on_nonconvergence=False)
     xo_t, ito, _ = opcg(P.o_h2.matvec, P.o_hss.solve, b[P.T.perm], 0.0, 4)
     xo = np.empty_like(b)
@@ -219,7 +223,7 @@ def test_pcg_converges_like_oracle(P):
     for rounding at the threshold) and, when the oracle converges, a true
     residual at the tolerance."""
     b = P.w.rhs()
-    bg = P.B.cols_like(P.w.n, b.shape[1], "cuda").copy_(torch.from_numpy(b))
+    bg = P.B.cols_like(P.w.rows, b.shape[1], "cuda").copy_(torch.from_numpy(b))
     maxit = CASES[P.name].get("pcg_maxit", 500)
     x, it, res = P.B.pcg_solve(P.g_h2, P.g_ulv, bg, rtol=P.w.pcg_tol, maxit=maxit,
                                raise_on_nonconvergence=False)

@@ -61,6 +61,8 @@ def test_kernel_closed_forms():
     X = workloads.points("cube", 5, 1)
     Y = workloads.points("cube", 4, 2)
     for k in kernels.KINDS:
+        if k in kernels.TENSOR:  # tensor entries: their own pins in test_oracle_rpy.py
+            continue
         np.testing.assert_allclose(kernels.evaluate(k, ell, X, Y), kernels.evaluate(k, ell, Y, X).T, rtol=0, atol=0)
 
 

@@ -22,22 +22,25 @@ from __future__ import annotations
 import dataclasses
 import numpy as np
 
-KERNELS = ("gaussian", "matern32", "exponential", "imq")
+KERNELS = ("gaussian", "matern32", "exponential", "imq", "rpy")
 
 
 def points(kind: str, n: int, seed: int) -> np.ndarray:
     """Seeded point set: 'cube' = iid U[0,1)^3, 'sphere' = unit-sphere surface,
-    'ball' = uniform (constant density) in the unit ball."""
+    'ball' = uniform (constant density) in the unit ball, 'ball1' = uniform in
+    the ball of radius (3n / (4 pi))^(1/3), one point per unit volume."""
     rng = np.random.default_rng(seed)
     if kind == "cube":
         x = rng.random((n, 3))
     elif kind == "sphere":
         g = rng.standard_normal((n, 3))
         x = g / np.linalg.norm(g, axis=1, keepdims=True)
-    elif kind == "ball":
+    elif kind in ("ball", "ball1"):
         g = rng.standard_normal((n, 3))
         r = rng.random(n) ** (1.0 / 3.0)
         x = g / np.linalg.norm(g, axis=1, keepdims=True) * r[:, None]
+        if kind == "ball1":  # constant density 1: radius (3n / (4 pi))^(1/3)
+            x = x * (3.0 * n / (4.0 * np.pi)) ** (1.0 / 3.0)
     else:
         raise ValueError(f"unknown point set {kind!r}")
     return np.ascontiguousarray(x, dtype=np.float64)
@@ -76,11 +79,18 @@ class Workload:
     def points(self) -> np.ndarray:
         return points(self.point_set, self.n, 1000 + self.seed_base)
 
+    @property
+    def rows(self) -> int:
+        """Rows of the matrix: 3 per point for the tensor kernel (row 3p + c is
+        component c of point p), else one."""
+        return 3 * self.n if self.kernel == "rpy" else self.n
+
     def rhs(self) -> np.ndarray:
-        return gaussian_matrix(self.n, self.nrhs, 2000 + (self.seed_base if self.rhs_seed is None else self.rhs_seed))
+        return gaussian_matrix(self.rows, self.nrhs,
+                               2000 + (self.seed_base if self.rhs_seed is None else self.rhs_seed))
 
     def omega(self) -> np.ndarray:
-        return gaussian_matrix(self.n, self.s, 3000 + self.seed_base)
+        return gaussian_matrix(self.rows, self.s, 3000 + self.seed_base)
 
     def with_(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)
@@ -117,7 +127,17 @@ HEADLINE = LARGE.with_(name="gaussian-l0.2-N1M-cube-eps1e-8-tau1e-2-r200", h2_to
 # the smallest eigenvalue (used to compare the mixed-precision forms).
 MEDIUM_S2 = MEDIUM.with_(name="matern32-l0.1-s1e-2-N100k-cube", shift=1e-2)
 
-BY_NAME = {w.name: w for w in (SMALL, MEDIUM, LARGE, MEDIUM_S2, HEADLINE)}
+# The RPY tensor kernel of the paper's Section 6: particles of radius a = 0.29
+# (volume fraction about 0.1) in the ball of unit point density, no shift;
+# 3 rows per particle.
+RPY_SMALL = Workload(name="rpy-a0.29-N1200-ball1", n=1200, point_set="ball1", kernel="rpy", ell=0.29,
+                     shift=0.0, leaf=96, h2_tol=1e-8, hss_tol=1e-2, max_rank=60, oversample=10, nrhs=1,
+                     pcg_tol=1e-8, seed_base=20)
+RPY_LARGE = Workload(name="rpy-a0.29-N100k-ball1", n=100_000, point_set="ball1", kernel="rpy", ell=0.29,
+                     shift=0.0, leaf=400, h2_tol=1e-8, hss_tol=1e-2, max_rank=100, oversample=10, nrhs=16,
+                     pcg_tol=1e-8, seed_base=21)
+
+BY_NAME = {w.name: w for w in (SMALL, MEDIUM, LARGE, MEDIUM_S2, HEADLINE, RPY_LARGE)}
 
 
 # Batched case: independent instances of uneven sizes.  N is log-uniform in
