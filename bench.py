@@ -186,8 +186,8 @@ def run_batch(args, torch, P):
     for w in ws:
         reqs.append(dict(points=torch.from_numpy(w.points()).to(dev), kernel=w.kernel, ell=w.ell, shift=w.shift,
                          leaf=w.leaf, h2_tol=w.h2_tol, hss_tol=w.hss_tol, max_rank=w.max_rank,
-                         oversample=w.oversample, b=cols_like(w.n, w.nrhs, dev).copy_(torch.from_numpy(w.rhs())),
-                         omega=cols_like(w.n, w.s, dev).copy_(torch.from_numpy(w.omega())),
+                         oversample=w.oversample, b=cols_like(w.rows, w.nrhs, dev).copy_(torch.from_numpy(w.rhs())),
+                         omega=cols_like(w.rows, w.s, dev).copy_(torch.from_numpy(w.omega())),
                          rtol=w.pcg_tol, maxit=5000, precision="f32"))
     P.binding.solve_batch(reqs[:2], workers=2)  # warm-up
     torch.cuda.synchronize()
@@ -238,7 +238,7 @@ def run_serve(args, torch, P):
     for _, w, _ in trace:
         reqs.append(dict(points=torch.from_numpy(w.points()).to(dev), kernel=w.kernel, ell=w.ell,
                          shift=w.shift, leaf=w.leaf, h2_tol=w.h2_tol, hss_tol=w.hss_tol, max_rank=w.max_rank,
-                         oversample=w.oversample, b=cols_like(w.n, w.nrhs, dev).copy_(torch.from_numpy(w.rhs())),
+                         oversample=w.oversample, b=cols_like(w.rows, w.nrhs, dev).copy_(torch.from_numpy(w.rhs())),
                          rtol=w.pcg_tol, maxit=3000, seed=w.seed_base))
     torch.cuda.synchronize()
     S = P.binding.Server(workers=args.workers, hbm_budget_bytes=200 << 30)
@@ -345,9 +345,9 @@ def main():
     w = workloads.BY_NAME[args.workload]
     dev = "cuda"
     X = torch.from_numpy(w.points()).to(dev)
-    om = cols_like(w.n, w.s, dev).copy_(torch.from_numpy(w.omega()))
-    b = cols_like(w.n, w.nrhs, dev).copy_(torch.from_numpy(w.rhs()))
-    x = cols_like(w.n, w.nrhs, dev)
+    om = cols_like(w.rows, w.s, dev).copy_(torch.from_numpy(w.omega()))
+    b = cols_like(w.rows, w.nrhs, dev).copy_(torch.from_numpy(w.rhs()))
+    x = cols_like(w.rows, w.nrhs, dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     h2 = P.h2_build(X, w.kernel, w.ell, w.shift, leaf=w.leaf, tol=w.h2_tol, eta=w.eta)
@@ -420,7 +420,7 @@ def main():
     # the FP64 operator it replaces and the true residual reached (FP64 product)
     mixed = None
     if w.nrhs <= 16 and (args.mixed or (w.nrhs <= 4 and not args.no_mixed)):
-        v = cols_like(w.n, 1, dev).copy_(torch.from_numpy(workloads.gaussian_matrix(w.n, 1, 4242)))
+        v = cols_like(w.rows, 1, dev).copy_(torch.from_numpy(workloads.gaussian_matrix(w.rows, 1, 4242)))
         y64 = P.h2_matvec(h2, v)
         y32 = P.h2_matvec(h2, v, precision="f32")
         pdiff = float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64))
