@@ -325,6 +325,7 @@ static const void* keep(Arena& a, hipStream_t s, const std::vector<T>& v) {
 // (deterministic).  This balances the work over workgroups when per-problem
 // work is uneven (the coupling pass).
 static constexpr double kSplitBytes = 1.0 * (1 << 20);
+static constexpr int64_t kFillTiles = 1024;
 
 // Algorithmic bytes of a batch: every A operand once, C once (twice with
 // beta), and the union of the B ranges read (B operands of different terms
@@ -433,10 +434,25 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
     return k;
   };
   if (b.indexed && b.max_n > 4) throw Error(SPD_E_INVALID, "indexed products support at most 4 columns");
+  // Parts per problem: by bytes (about kSplitBytes of A each), and, for a
+  // 5-16 column launch of fewer than kFillTiles row tiles (the upper levels of
+  // the sweeps: a few large nodes, one workgroup each), by the inner dimension
+  // too, so that the launch fills the GPU (parts of at least 128 columns).
+  int64_t tiles = 0;
+  for (const GemmProblem& p : b.probs) tiles += (p.m + 63) / 64;
+  const int64_t fill =
+      (!b.transA && b.max_n > 4 && b.max_n <= 16 && tiles > 0 && tiles < kFillTiles) ? (kFillTiles + tiles - 1) / tiles : 1;
+  auto nparts_of = [&](const GemmProblem& p) -> int64_t {
+    const int64_t K = width(p);
+    if (K <= 1) return 1;
+    int64_t np = 8.0 * p.m * K > kSplitBytes ? (int64_t)std::ceil(8.0 * p.m * K / kSplitBytes) : 1;
+    np = std::max<int64_t>(np, std::min<int64_t>(fill, K / 128));
+    return std::max<int64_t>(1, std::min<int64_t>(np, K));
+  };
   bool split = false;
   if (b.max_n <= 16 && !b.indexed && !b.a_f32)
     for (const GemmProblem& p : b.probs)
-      if (8.0 * p.m * width(p) > kSplitBytes && width(p) > 1) { split = true; break; }
+      if (nparts_of(p) > 1) { split = true; break; }
   if (!split && symm_form(b)) {
     gemm_symm(a, s, b, bytes);
     return;
@@ -455,7 +471,8 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
   // partial results live in this recorder's arena for its lifetime
   for (const GemmProblem& p : b.probs) {
     const int64_t K = width(p);
-    if (8.0 * p.m * K <= kSplitBytes || K <= 1) {
+    const int64_t nparts = nparts_of(p);
+    if (nparts <= 1) {
       parts.probs.push_back(p);
       parts.probs.back().term_begin = (int)parts.terms.size();
       for (int q = p.term_begin; q < p.term_end; ++q) parts.terms.push_back(b.terms[q]);
@@ -464,7 +481,6 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
       parts.max_n = std::max(parts.max_n, p.n);
       continue;
     }
-    const int64_t nparts = std::min<int64_t>(K, (int64_t)std::ceil(8.0 * p.m * K / kSplitBytes));
     red.add(p.C, p.m, p.n, p.ldc, p.beta);
     int q = p.term_begin;
     int64_t off = 0;  // columns of term q already assigned
