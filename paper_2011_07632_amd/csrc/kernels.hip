@@ -2168,14 +2168,21 @@ __global__ __launch_bounds__(256) void k_pcg_xr_dot(double* __restrict__ x, doub
                                                     const double* __restrict__ zold,
                                                     double* __restrict__ rzop) {
   __shared__ double red[4], red2[4];
+  __shared__ double salpha;
   const int b = blockIdx.x, c = blockIdx.y;
-  if (!active[c]) return;
-  const double rz = chunk_sum(rzp, nblk, c);
-  const double alpha = rz / chunk_sum(pqp, nblk, c);
-  if (b == 0 && threadIdx.x == 0) {
-    if (iters) iters[c] += 1;
-    rzv[c] = rz;
+  if (!active[c]) return;  // uniform across the block
+  // the scalars once per block (the same sums in the same order as every
+  // other block), handed to its threads through LDS
+  if (threadIdx.x == 0) {
+    const double rz = chunk_sum(rzp, nblk, c);
+    salpha = rz / chunk_sum(pqp, nblk, c);
+    if (b == 0) {
+      if (iters) iters[c] += 1;
+      rzv[c] = rz;
+    }
   }
+  __syncthreads();
+  const double alpha = salpha;
   const int64_t lo = (int64_t)b * DOT_CHUNK, hi = min(n, lo + DOT_CHUNK);
   double sacc = 0.0, sz = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
@@ -2224,13 +2231,18 @@ __global__ void k_pcg_update_p_partial(double* __restrict__ p, const double* __r
                                        const double* __restrict__ rzv,
                                        const int* __restrict__ active, int64_t n, int64_t ld,
                                        const double* __restrict__ rzop) {
+  __shared__ double sbeta;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
-  if (!active[c] || i >= n) return;
-  double num = chunk_sum(rzp, nblk, c);
-  if (rzop) num -= chunk_sum(rzop, nblk, c);
-  const double beta = num / rzv[c];
-  p[i + c * ld] = z[i + c * ld] + beta * p[i + c * ld];
+  if (!active[c]) return;  // uniform across the block
+  if (threadIdx.x == 0) {  // beta once per block, handed over through LDS
+    double num = chunk_sum(rzp, nblk, c);
+    if (rzop) num -= chunk_sum(rzop, nblk, c);
+    sbeta = num / rzv[c];
+  }
+  __syncthreads();
+  if (i >= n) return;
+  p[i + c * ld] = z[i + c * ld] + sbeta * p[i + c * ld];
 }
 
 void launch_coldot_partial(hipStream_t s, const double* x, const double* y, int64_t n, int ncols,
