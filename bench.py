@@ -185,7 +185,7 @@ def run_batch(args, torch, P):
     reqs = []
     for w in ws:
         reqs.append(dict(points=torch.from_numpy(w.points()).to(dev), kernel=w.kernel, ell=w.ell, shift=w.shift,
-                         leaf=w.leaf, h2_tol=w.h2_tol, hss_tol=w.hss_tol, max_rank=w.max_rank,
+                         leaf=w.leaf, tree=w.tree, h2_tol=w.h2_tol, hss_tol=w.hss_tol, max_rank=w.max_rank,
                          oversample=w.oversample, b=cols_like(w.rows, w.nrhs, dev).copy_(torch.from_numpy(w.rhs())),
                          omega=cols_like(w.rows, w.s, dev).copy_(torch.from_numpy(w.omega())),
                          rtol=w.pcg_tol, maxit=5000, precision="f32"))
@@ -237,7 +237,8 @@ def run_serve(args, torch, P):
     reqs = []
     for _, w, _ in trace:
         reqs.append(dict(points=torch.from_numpy(w.points()).to(dev), kernel=w.kernel, ell=w.ell,
-                         shift=w.shift, leaf=w.leaf, h2_tol=w.h2_tol, hss_tol=w.hss_tol, max_rank=w.max_rank,
+                         shift=w.shift, leaf=w.leaf, tree=w.tree, h2_tol=w.h2_tol, hss_tol=w.hss_tol,
+                         max_rank=w.max_rank,
                          oversample=w.oversample, b=cols_like(w.rows, w.nrhs, dev).copy_(torch.from_numpy(w.rhs())),
                          rtol=w.pcg_tol, maxit=3000, seed=w.seed_base))
     torch.cuda.synchronize()
@@ -350,7 +351,7 @@ def main():
     x = cols_like(w.rows, w.nrhs, dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h2 = P.h2_build(X, w.kernel, w.ell, w.shift, leaf=w.leaf, tol=w.h2_tol, eta=w.eta)
+    h2 = P.h2_build(X, w.kernel, w.ell, w.shift, leaf=w.leaf, tol=w.h2_tol, eta=w.eta, tree=w.tree)
     torch.cuda.synchronize()
     t_h2 = time.perf_counter() - t0
     log(f"[bench] {w.name}: h2_build {t_h2:.3f} s, levels {h2.levels}")

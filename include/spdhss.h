@@ -89,6 +89,21 @@ typedef struct {
                    * spdhss_build reports as SPD_E_NOT_SPD) */
 } spd_kernel;
 
+/* Partition tree of the points (Section 2 assumes a perfect tree). */
+typedef enum {
+  SPD_TREE_KD = 0,  /* binary kd-tree: depth D is the smallest with
+                       N <= leaf_size * 2^D; a node is split on the axis of its
+                       largest extent into halves of floor(n/2) and the rest */
+  SPD_TREE_BOX = 1  /* the 2^d-ary box-bisection tree of Section 6 (d = 3) as
+                       a perfect binary tree with 3 levels per 2^d-ary level: a
+                       node at depth t is bisected along axis t mod 3 (x, y, z)
+                       at the midpoint of its points' extent, and D is the
+                       smallest multiple of 3 with at most leaf_size points in
+                       every node at depth D (at most 24).  Leaves are ragged.
+                       A node with no extent along its axis cannot be bisected:
+                       SPD_E_INVALID */
+} spd_tree_kind;
+
 /* H^2 construction options (Section 5.1; construction method: proxy-point
  * interpolative decomposition, this library's choice since the paper does not
  * describe one).
@@ -106,7 +121,7 @@ typedef struct {
  * the counter (t << 24) | j under sketch_seed, then Box-Muller), a randomized
  * interpolative decomposition.  c may not exceed 4000 (SPD_E_INVALID). */
 typedef struct {
-  int32_t leaf_size;            /* max points per leaf of the binary kd-tree */
+  int32_t leaf_size;            /* max points per leaf, in [1, 512] */
   double eta;                   /* admissibility: r_i + r_j <= eta * |c_i - c_j| */
   double tol;                   /* relative truncation of the ID (|R_tt| > tol |R_00|) */
   int32_t proxy_shells;         /* proxy spheres per node, in [1, 64] */
@@ -115,6 +130,7 @@ typedef struct {
                                    proxy_shells * maximum <= 65536) */
   double proxy_density;         /* >= 0, see above */
   uint64_t sketch_seed;         /* seed of the sketch's generator */
+  int32_t tree;                 /* spd_tree_kind (0, the kd-tree, when left zero) */
 } spd_h2_opts;
 
 /* SPD HSS construction options (Algorithm 5.3, Algorithm 5.1). */
@@ -136,7 +152,7 @@ typedef struct spd_ulv* spd_ulv_t;
 
 /* Build the H^2 representation of shift*I + K(X, X).
  * points: DEVICE, n x 3 row-major (x0 y0 z0 x1 ...), original order; n >= 1.
- * Builds the kd-tree, the near/coupling lists, the proxy-point ID bases and
+ * Builds the partition tree, the near/coupling lists, the proxy-point ID bases and
  * stores the dense near blocks and the coupling blocks on the device. */
 spd_status h2_build(const double* points, int64_t n, spd_kernel kernel,
                     const spd_h2_opts* opts, void* stream, spd_h2_t* out);

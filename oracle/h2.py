@@ -83,7 +83,7 @@ SKETCH_SEED = 0x5EEDF00D
 class H2:
     def __init__(self, X, kind, ell, shift, leaf, tol, eta=1.0,
                  shells=8, per_shell=128, per_shell_max=2048, density=90.0,
-                 sketch_seed=SKETCH_SEED, tree: Tree | None = None):
+                 sketch_seed=SKETCH_SEED, tree: Tree | None = None, tree_kind: str = "kd"):
         X = np.ascontiguousarray(X, dtype=np.float64)
         # a tensor kernel acts on 3 rows per point: row 3p + c is point p's
         # component c, and the tree partitions the rows (3 coincident entries a point)
@@ -95,7 +95,7 @@ class H2:
         self.sketch_seed = int(sketch_seed)
         self.proxy_n: dict[int, int] = {}   # points per sphere of each node
         self.sketched: dict[int, bool] = {}
-        self.tree = tree if tree is not None else Tree(self.X, leaf, eta)
+        self.tree = tree if tree is not None else Tree(self.X, leaf, eta, tree_kind)
         T = self.tree
         self.skel: dict[int, np.ndarray] = {}
         self.W: dict[int, np.ndarray] = {}   # U_i (leaf) or R_i (nonleaf)

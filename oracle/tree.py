@@ -7,13 +7,27 @@ points are well separated from those of i; Section 5.2.2 classes blocks as
 Type-1 (j not in F_i), Type-2 (inside a larger far block) and Type-3 (far, with
 inadmissible parents).
 
-Readings taken where the paper is silent (Section 6 uses a 2^d-ary box
-bisection; the workloads ask for a binary kd-tree):
+Two partition rules ("kind"):
 
-* depth D = smallest integer with N <= leaf * 2^D; L = D + 1 levels;
-* a node is split on the axis of largest tight-bounding-box extent (lowest
-  axis on ties), its points ordered by (coordinate, original index), and the
-  left child takes the first floor(n/2) of them;
+* "kd" (the binary kd-tree of the workloads; the paper is silent on it):
+  depth D = smallest integer with N <= leaf * 2^D; a node is split on the
+  axis of largest tight-bounding-box extent (lowest axis on ties), its points
+  ordered by (coordinate, original index), and the left child takes the first
+  floor(n/2) of them;
+* "box" (Section 6: the 2^d-ary tree that bisects every dimension of a box
+  enclosing the points until the finest boxes are small enough), realised as
+  a perfect binary tree with d = 3 binary levels per 2^d-ary level: a node at
+  depth t is bisected along axis t mod 3 at the midpoint of its points' tight
+  extent on that axis, points below the midpoint going left (ordered by
+  (coordinate, original index) as above), and D is the smallest multiple of 3
+  for which no node at depth D holds more than leaf points.  Readings: the
+  box of a node is the tight box of its points (so that no box is empty and
+  the tree stays perfect); the axes are taken in the order x, y, z; "small
+  enough" is at most leaf points.  A node that cannot be bisected (no extent
+  along the axis) is an error.
+
+Shared by both:
+
 * admissible(i, j)  <=>  i != j and r_i + r_j <= eta * |c_i - c_j|, with c the
   bounding-box centre and r its half diagonal;
 * near/coupling lists are built top-down: the children of every near node of
@@ -35,32 +49,60 @@ def depth_for(n: int, leaf: int) -> int:
     return d
 
 
+def box_split(P: np.ndarray, axis: int) -> int:
+    """Points of a node bisected at the midpoint of their extent along axis:
+    the number below it (P already ordered along the axis)."""
+    lo, hi = P[:, axis].min(), P[:, axis].max()
+    mid = 0.5 * (lo + hi)
+    m = int(np.count_nonzero(P[:, axis] < mid))
+    if m == 0 or m == P.shape[0]:
+        raise ValueError(f"box bisection: a node of {P.shape[0]} points has no extent along axis {axis}")
+    return m
+
+
 class Tree:
-    def __init__(self, X: np.ndarray, leaf: int, eta: float = 1.0):
+    def __init__(self, X: np.ndarray, leaf: int, eta: float = 1.0, kind: str = "kd"):
         X = np.asarray(X, dtype=np.float64)
         N = X.shape[0]
         if N < 1:
             raise ValueError("empty point set")
-        self.N, self.leaf, self.eta = N, int(leaf), float(eta)
-        self.D = depth_for(N, leaf)
-        self.L = self.D + 1
-        nn = (1 << (self.D + 1)) - 1
-        self.nnodes = nn
+        if kind not in ("kd", "box"):
+            raise ValueError(f"unknown tree kind {kind!r}")
+        self.N, self.leaf, self.eta, self.kind = N, int(leaf), float(eta), kind
         perm = np.arange(N)
-        start = np.zeros(nn, dtype=np.int64)
-        end = np.zeros(nn, dtype=np.int64)
-        start[0], end[0] = 0, N
-        for v in range((1 << self.D) - 1):  # every internal node, top-down
+        start, end = [0], [N]
+
+        def split(v: int, axis):
             s, e = start[v], end[v]
             idx = perm[s:e]
             P = X[idx]
-            ext = P.max(axis=0) - P.min(axis=0)
-            axis = int(np.argmax(ext))  # first maximum -> lowest axis on ties
+            if axis is None:
+                ext = P.max(axis=0) - P.min(axis=0)
+                axis = int(np.argmax(ext))  # first maximum -> lowest axis on ties
             order = np.lexsort((idx, P[:, axis]))  # primary: coordinate, then index
             perm[s:e] = idx[order]
-            half = (e - s) // 2
-            start[2 * v + 1], end[2 * v + 1] = s, s + half
-            start[2 * v + 2], end[2 * v + 2] = s + half, e
+            m = (e - s) // 2 if kind == "kd" else box_split(P[order], axis)
+            start.extend([s, s + m])
+            end.extend([s + m, e])
+
+        if kind == "kd":
+            self.D = depth_for(N, leaf)
+            for v in range((1 << self.D) - 1):  # every internal node, top-down
+                split(v, None)
+        else:
+            self.D = 0
+            while max(end[v] - start[v] for v in range((1 << self.D) - 1, (1 << (self.D + 1)) - 1)) > leaf:
+                if self.D + 3 > 24:
+                    raise ValueError("tree too deep")
+                for t in range(self.D, self.D + 3):  # bisect x, then y, then z
+                    for v in range((1 << t) - 1, (1 << (t + 1)) - 1):
+                        split(v, t % 3)
+                self.D += 3
+        self.L = self.D + 1
+        nn = (1 << (self.D + 1)) - 1
+        self.nnodes = nn
+        start = np.asarray(start, dtype=np.int64)
+        end = np.asarray(end, dtype=np.int64)
         self.perm = perm                  # tree position -> original index
         self.iperm = np.empty(N, dtype=np.int64)
         self.iperm[perm] = np.arange(N)   # original index -> tree position

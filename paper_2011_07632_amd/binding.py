@@ -44,19 +44,21 @@ class _H2Opts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("eta", C.c_double), ("tol", C.c_double),
                 ("proxy_shells", C.c_int32), ("proxy_per_shell", C.c_int32),
                 ("proxy_per_shell_max", C.c_int32), ("proxy_density", C.c_double),
-                ("sketch_seed", C.c_uint64)]
+                ("sketch_seed", C.c_uint64), ("tree", C.c_int32)]
 
 
 # defaults of the H^2 construction options (spd_h2_opts)
 H2_DEFAULTS = dict(proxy_shells=8, proxy_per_shell=128, proxy_per_shell_max=2048, proxy_density=90.0,
-                   sketch_seed=0x5EEDF00D)
+                   sketch_seed=0x5EEDF00D, tree="kd")
+TREES = {"kd": 0, "box": 1}  # spd_tree_kind
 
 
 def _h2_opts(leaf, eta, tol, d: dict) -> "_H2Opts":
     g = {k: d.get(k, v) for k, v in H2_DEFAULTS.items()}
     g["proxy_per_shell_max"] = max(int(g["proxy_per_shell_max"]), int(g["proxy_per_shell"]))
     return _H2Opts(int(leaf), float(eta), float(tol), int(g["proxy_shells"]), int(g["proxy_per_shell"]),
-                   int(g["proxy_per_shell_max"]), float(g["proxy_density"]), int(g["sketch_seed"]))
+                   int(g["proxy_per_shell_max"]), float(g["proxy_density"]), int(g["sketch_seed"]),
+                   TREES[g["tree"]])
 
 
 class _HSSOpts(C.Structure):
@@ -339,14 +341,14 @@ class ULVFactor:
 def h2_build(points: torch.Tensor, kernel: str, ell: float, shift: float, leaf: int = 64,
              tol: float = 1e-8, eta: float = 1.0, proxy_shells: int = 8, proxy_per_shell: int = 128,
              proxy_per_shell_max: int = 2048, proxy_density: float = 90.0, sketch_seed: int = 0x5EEDF00D,
-             stream=None) -> H2Matrix:
+             tree: str = "kd", stream=None) -> H2Matrix:
     if not points.is_cuda or points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 3:
         raise ValueError("points must be an (N, 3) float64 device tensor")
     points = points.contiguous()
     k = _Kernel(KERNELS[kernel], float(ell), float(shift))
     o = _h2_opts(leaf, eta, tol, dict(proxy_shells=proxy_shells, proxy_per_shell=proxy_per_shell,
                                       proxy_per_shell_max=proxy_per_shell_max,
-                                      proxy_density=proxy_density, sketch_seed=sketch_seed))
+                                      proxy_density=proxy_density, sketch_seed=sketch_seed, tree=tree))
     out = C.c_void_p()
     _check(lib.h2_build(points.data_ptr(), points.shape[0], k, C.byref(o), _stream(stream), C.byref(out)))
     # rows of the matrix: one per point, three for the RPY tensor

@@ -67,6 +67,8 @@ spd_status h2_build(const double* points, int64_t n, spd_kernel kernel, const sp
   SPD_REQUIRE(std::isfinite(kernel.shift), SPD_E_INVALID, "shift must be finite");
   SPD_REQUIRE(opts->leaf_size >= 1 && opts->leaf_size <= 512, SPD_E_INVALID,
               "leaf_size must be in [1, 512]");
+  SPD_REQUIRE(opts->tree == SPD_TREE_KD || opts->tree == SPD_TREE_BOX, SPD_E_INVALID,
+              "unknown tree kind");
   SPD_REQUIRE(opts->eta > 0, SPD_E_INVALID, "eta must be positive");
   SPD_REQUIRE(opts->tol >= 0 && opts->tol < 1, SPD_E_INVALID, "tol must be in [0, 1)");
   SPD_REQUIRE(opts->proxy_shells >= 1 && opts->proxy_shells <= 64 && opts->proxy_per_shell >= 4,

@@ -112,7 +112,7 @@ void h2_build_impl(H2Model& H, const double* points, int64_t npts) {
     hp.swap(h3);
   }
   TreeHost& T = H.T;
-  T.build(hp.data(), n, H.opts.leaf_size, H.opts.eta);
+  T.build(hp.data(), n, H.opts.leaf_size, H.opts.eta, H.opts.tree);
   const int nn = T.nnodes, L = T.L;
   H.perm_d = upload(H.arena, s, T.perm);
   H.pts = H.arena.get_n<double>((size_t)3 * n);

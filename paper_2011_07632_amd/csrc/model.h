@@ -11,14 +11,15 @@ namespace spd {
 // ------------------------------------------------------------------ tree --
 struct TreeHost {
   int64_t N = 0;
-  int leaf = 0, D = 0, L = 0, nnodes = 0;
+  int leaf = 0, D = 0, L = 0, nnodes = 0, kind = SPD_TREE_KD;
   double eta = 1.0;
   std::vector<int64_t> perm, start, end;
   std::vector<double> lo, hi, center, radius;
   std::vector<int64_t> near_ptr, coup_ptr;
   std::vector<int> near_idx, coup_idx;
 
-  void build(const double* pts_rowmajor, int64_t n, int leaf_size, double eta);
+  void build(const double* pts_rowmajor, int64_t n, int leaf_size, double eta, int kind);
+  void split(const double* pts, int v, int axis);
   bool admissible(int i, int j) const;
   void build_lists();
   int depth(int v) const { int d = 0; while ((1 << (d + 1)) - 1 <= v) ++d; return d; }

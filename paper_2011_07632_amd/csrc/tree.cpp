@@ -1,9 +1,17 @@
 // Partition tree and admissibility lists (host).
 //
-// Perfect binary kd-tree (Section 2 assumes a perfect tree): depth D is the
-// smallest integer with N <= leaf * 2^D; a node is split on the axis of its
-// largest bounding-box extent (lowest axis on ties), its points ordered by
-// (coordinate, original index), the left child taking floor(n/2) of them.
+// A perfect binary tree (Section 2 assumes a perfect tree) in heap order, of
+// one of two kinds:
+// * kd: depth D is the smallest integer with N <= leaf * 2^D; a node is split
+//   on the axis of its largest bounding-box extent (lowest axis on ties), its
+//   points ordered by (coordinate, original index), the left child taking
+//   floor(n/2) of them;
+// * box: the 2^d-ary box-bisection tree of Section 6 for d = 3, as three
+//   binary levels per 2^d-ary level: a node at depth t is bisected along axis
+//   t mod 3 at the midpoint of its points' extent on that axis (points below
+//   it go left, in the same order as above), and D is the smallest multiple of
+//   3 at which no node holds more than leaf points.  The box of a node is the
+//   tight box of its points, so no child is empty and the tree stays perfect.
 // Far-field sets (Section 5.1) use the admissibility rule
 // r_i + r_j <= eta * |c_i - c_j| on bounding-box centres c and half-diagonals
 // r; near (Type-1) and coupling (Type-3) lists are built top-down from the
@@ -27,46 +35,78 @@ static int depth_for(int64_t n, int leaf) {
   return d;
 }
 
-void TreeHost::build(const double* pts, int64_t n, int leaf_size, double eta_) {
-  SPD_REQUIRE(n >= 1, SPD_E_INVALID, "empty point set");
-  SPD_REQUIRE(leaf_size >= 1, SPD_E_INVALID, "leaf size must be positive");
-  N = n;
-  leaf = leaf_size;
-  eta = eta_;
-  D = depth_for(n, leaf);
-  SPD_REQUIRE(D <= 24, SPD_E_INVALID, "tree too deep");
-  L = D + 1;
-  nnodes = (1 << (D + 1)) - 1;
-  perm.resize(n);
-  std::iota(perm.begin(), perm.end(), (int64_t)0);
-  start.assign(nnodes, 0);
-  end.assign(nnodes, 0);
-  end[0] = n;
-  for (int v = 0; v < (1 << D) - 1; ++v) {
-    const int64_t s = start[v], e = end[v];
-    double lo3[3] = {INFINITY, INFINITY, INFINITY}, hi3[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t i = s; i < e; ++i)
-      for (int a = 0; a < 3; ++a) {
-        const double x = pts[3 * perm[i] + a];
-        lo3[a] = std::min(lo3[a], x);
-        hi3[a] = std::max(hi3[a], x);
-      }
-    int axis = 0;
+// Split node v into 2v+1 and 2v+2 (appended to start/end); axis < 0 takes the
+// axis of largest extent (kd), otherwise the node is bisected along axis (box).
+void TreeHost::split(const double* pts, int v, int axis) {
+  const int64_t s = start[v], e = end[v];
+  double lo3[3] = {INFINITY, INFINITY, INFINITY}, hi3[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = s; i < e; ++i)
+    for (int a = 0; a < 3; ++a) {
+      const double x = pts[3 * perm[i] + a];
+      lo3[a] = std::min(lo3[a], x);
+      hi3[a] = std::max(hi3[a], x);
+    }
+  const bool box = axis >= 0;
+  if (!box) {
+    axis = 0;
     if (e > s) {
       double best = hi3[0] - lo3[0];
       for (int a = 1; a < 3; ++a)
         if (hi3[a] - lo3[a] > best) { best = hi3[a] - lo3[a]; axis = a; }
     }
-    std::sort(perm.begin() + s, perm.begin() + e, [&](int64_t a, int64_t b) {
-      const double xa = pts[3 * a + axis], xb = pts[3 * b + axis];
-      return xa < xb || (xa == xb && a < b);
-    });
-    const int64_t half = (e - s) / 2;
-    start[2 * v + 1] = s;
-    end[2 * v + 1] = s + half;
-    start[2 * v + 2] = s + half;
-    end[2 * v + 2] = e;
   }
+  std::sort(perm.begin() + s, perm.begin() + e, [&](int64_t a, int64_t b) {
+    const double xa = pts[3 * a + axis], xb = pts[3 * b + axis];
+    return xa < xb || (xa == xb && a < b);
+  });
+  int64_t m = (e - s) / 2;
+  if (box) {
+    const double mid = 0.5 * (lo3[axis] + hi3[axis]);
+    m = std::partition_point(perm.begin() + s, perm.begin() + e,
+                             [&](int64_t a) { return pts[3 * a + axis] < mid; }) -
+        (perm.begin() + s);
+    SPD_REQUIRE(m > 0 && m < e - s, SPD_E_INVALID,
+                "box bisection: node " + std::to_string(v) + " (" + std::to_string(e - s) +
+                    " points) has no extent along axis " + std::to_string(axis));
+  }
+  start.push_back(s);
+  end.push_back(s + m);
+  start.push_back(s + m);
+  end.push_back(e);
+}
+
+void TreeHost::build(const double* pts, int64_t n, int leaf_size, double eta_, int kind_) {
+  SPD_REQUIRE(n >= 1, SPD_E_INVALID, "empty point set");
+  SPD_REQUIRE(leaf_size >= 1, SPD_E_INVALID, "leaf size must be positive");
+  N = n;
+  leaf = leaf_size;
+  eta = eta_;
+  kind = kind_;
+  perm.resize(n);
+  std::iota(perm.begin(), perm.end(), (int64_t)0);
+  start.assign(1, 0);
+  end.assign(1, n);
+  if (kind == SPD_TREE_KD) {
+    D = depth_for(n, leaf);
+    SPD_REQUIRE(D <= 24, SPD_E_INVALID, "tree too deep");
+    for (int v = 0; v < (1 << D) - 1; ++v) split(pts, v, -1);
+  } else {
+    SPD_REQUIRE(kind == SPD_TREE_BOX, SPD_E_INVALID, "unknown tree kind");
+    D = 0;
+    auto largest = [&]() {
+      int64_t m = 0;
+      for (int v = (1 << D) - 1; v < (1 << (D + 1)) - 1; ++v) m = std::max(m, end[v] - start[v]);
+      return m;
+    };
+    while (largest() > leaf) {
+      SPD_REQUIRE(D + 3 <= 24, SPD_E_INVALID, "tree too deep");
+      for (int t = D; t < D + 3; ++t)
+        for (int v = (1 << t) - 1; v < (1 << (t + 1)) - 1; ++v) split(pts, v, t % 3);
+      D += 3;
+    }
+  }
+  L = D + 1;
+  nnodes = (1 << (D + 1)) - 1;
   lo.assign(3 * nnodes, 0.0);
   hi.assign(3 * nnodes, 0.0);
   for (int v = nnodes - 1; v >= 0; --v) {

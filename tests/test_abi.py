@@ -69,6 +69,8 @@ def _h2_args(**kw):
     (100, {"leaf_size": 0}, b"leaf_size"),
     (100, {"leaf_size": 513}, b"leaf_size"),
     (100, {"eta": 0.0}, b"eta"),
+    (100, {"tree": 2}, b"unknown tree"),
+    (100, {"tree": -1}, b"unknown tree"),
     (100, {"tol": 1.0}, b"tol"),
     (100, {"proxy_shells": 0}, b"proxy"),
     (100, {"proxy_shells": 65}, b"proxy counts"),

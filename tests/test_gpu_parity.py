@@ -73,6 +73,17 @@ CASES = {
     # 0.29 at unit density in a ball, 6,000 rows in leaves of 90 rows
     "rpy2000": dict(w=workloads.RPY_SMALL.with_(name="rpy-a0.29-N2000-ball1", n=2000, leaf=90),
                     shells=8, per_shell=128),
+    # the 2^d-ary box-bisection tree (Section 6): 4,000 cube points, 64 boxes
+    # of 48-80 points (6 binary levels), Gaussian kernel
+    "box4000": dict(w=workloads.SMALL.with_(name="gaussian-l0.3-N4000-box", n=4000, ell=0.3, leaf=128,
+                                            max_rank=40, seed_base=12, tree="box"),
+                    shells=6, per_shell=96),
+    # box-bisection tree on the ball: ragged leaves at the surface (11 to 103
+    # points), Matern kernel
+    "boxball3000": dict(w=workloads.SMALL.with_(name="matern32-l0.2-N3000-ball-box", n=3000, point_set="ball",
+                                                kernel="matern32", ell=0.2, shift=1e-2, leaf=128, max_rank=40,
+                                                seed_base=13, tree="box"),
+                        shells=6, per_shell=96),
     # inverse multiquadric, fixed-rank form (tol = 0)
     "imq1200": dict(w=workloads.SMALL.with_(name="imq-c0.1-N1200", n=1200, kernel="imq", ell=0.1,
                                             shift=1e-3, leaf=30, max_rank=20, hss_tol=0.0, seed_base=9),
@@ -96,13 +107,13 @@ class Pair:
         X = w.points()
         self.X = X
         self.o_h2 = OH2(X, w.kernel, w.ell, w.shift, w.leaf, w.h2_tol, eta=w.eta,
-                        shells=c["shells"], per_shell=c["per_shell"])
+                        shells=c["shells"], per_shell=c["per_shell"], tree_kind=w.tree)
         self.T = self.o_h2.tree
         om = w.omega()
         self.o_hss = OHSS(self.o_h2, om[self.T.perm], w.hss_tol, w.max_rank, "chol")
         self.g_h2 = B.h2_build(torch.from_numpy(X).cuda(), w.kernel, w.ell, w.shift, leaf=w.leaf,
                                tol=w.h2_tol, eta=w.eta, proxy_shells=c["shells"],
-                               proxy_per_shell=c["per_shell"])
+                               proxy_per_shell=c["per_shell"], tree=w.tree)
         self.g_hss = B.spdhss_build(self.g_h2, w.hss_tol, w.max_rank, w.oversample,
                                     omega=B.cols_like(w.rows, w.s, "cuda").copy_(torch.from_numpy(om)))
         self.g_ulv = B.ulv_factor(self.g_hss)

@@ -88,6 +88,72 @@ def test_tree_properties(n, leaf):
         assert T.size(c1) == T.size(v) // 2
 
 
+def _lattice(m, seed, jitter):
+    """An m x m x m lattice of integer points (spacing 1) in a seeded random
+    order, each point moved by at most jitter along every axis."""
+    rng = np.random.default_rng(seed)
+    ijk = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"), -1).reshape(-1, 3)
+    ijk = ijk[rng.permutation(len(ijk))]
+    return ijk, ijk + rng.uniform(-jitter, jitter, ijk.shape)
+
+
+def _morton(ijk, bits):
+    """Z-order code with x the most significant bit of every triple."""
+    code = np.zeros(len(ijk), dtype=np.int64)
+    for b in range(bits - 1, -1, -1):
+        for a in range(3):
+            code = (code << 1) | ((ijk[:, a] >> b) & 1)
+    return code
+
+
+@pytest.mark.parametrize("jitter", [0.0, 0.2])
+@pytest.mark.parametrize("leaf,depth,group", [(1, 9, 0), (7, 9, 0), (8, 6, 1), (63, 6, 1), (64, 3, 2), (512, 0, 3)])
+def test_box_tree_on_a_lattice_is_the_octree(leaf, depth, group, jitter):
+    """On an 8 x 8 x 8 lattice the 2^d-ary box bisection is the octree of
+    the lattice cells: the leaves at depth 3k, in heap order, are the
+    2^(3-k)-cubes of points in Z-order (Morton order, x first), whatever the
+    input order and a jitter below a quarter of the spacing."""
+    ijk, X = _lattice(8, 5, jitter)
+    T = Tree(X, leaf, kind="box")
+    assert T.D == depth
+    leaves = T.leaves()
+    for a, v in enumerate(leaves):
+        members = T.perm[T.rng(v)]
+        assert len(members) == 8 ** group
+        assert (_morton(ijk[members] >> group, 3 - group) == a).all()
+
+
+@pytest.mark.parametrize("point_set,n,leaf", [("cube", 3000, 100), ("ball", 4000, 200), ("sphere", 2500, 100)])
+def test_box_tree_properties(point_set, n, leaf):
+    X = workloads.points(point_set, n, 4)
+    T = Tree(X, leaf, kind="box")
+    assert T.D % 3 == 0
+    assert sorted(T.perm.tolist()) == list(range(n))
+    sizes = [T.size(v) for v in T.leaves()]
+    assert min(sizes) >= 1 and max(sizes) <= leaf and sum(sizes) == n
+    up = T.nodes_at(4) if T.D >= 3 else []  # depth D - 3: some node exceeds leaf
+    assert T.D == 0 or max(T.size(v) for v in up) > leaf
+    for v in range((1 << T.D) - 1):
+        ax = T.depth(v) % 3
+        c1, c2 = T.children(v)
+        x = X[T.perm[T.rng(v)], ax]
+        mid = 0.5 * (x.min() + x.max())
+        assert (X[T.perm[T.rng(c1)], ax] < mid).all() and (X[T.perm[T.rng(c2)], ax] >= mid).all()
+
+
+def test_box_tree_rejects_a_node_without_extent():
+    X = workloads.points("cube", 400, 6)
+    X[:, 2] = 0.5  # a plane: the z bisection has nothing to split
+    with pytest.raises(ValueError, match="no extent"):
+        Tree(X, 50, kind="box")
+    # a perfect tree cannot hold a box that runs out of points above depth D:
+    # sparse boxes at the surface of a ball with small leaves
+    with pytest.raises(ValueError, match="a node of 1 points"):
+        Tree(workloads.points("ball", 4000, 4), 64, kind="box")
+    with pytest.raises(ValueError, match="unknown tree"):
+        Tree(X, 50, kind="oct")
+
+
 def test_lists_tile_the_matrix_exactly(h2s):
     """Every leaf pair is covered exactly once by a near leaf block or by one
     coupling block at some level (the H^2 block partition)."""

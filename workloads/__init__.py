@@ -71,6 +71,7 @@ class Workload:
     eta: float = 1.0
     seed_base: int = 0
     rhs_seed: int | None = None  # right-hand sides of a request on another request's matrix
+    tree: str = "kd"  # partition tree: "kd" or "box" (2^d-ary box bisection)
 
     @property
     def s(self) -> int:
@@ -122,6 +123,11 @@ LARGE = Workload(name="gaussian-l0.2-N1M-cube", n=1_000_000, point_set="cube",
 HEADLINE = LARGE.with_(name="gaussian-l0.2-N1M-cube-eps1e-8-tau1e-2-r200", h2_tol=1e-8, hss_tol=1e-2,
                        max_rank=200)
 
+# The same problem on the paper's 2^d-ary box-bisection tree (Section 6:
+# bisect every dimension until no box holds more than 400 points): 4,096 boxes
+# of 190 to 301 points at depth 12, the kd-tree's depth.
+HEADLINE_BOX = HEADLINE.with_(name="gaussian-l0.2-N1M-cube-eps1e-8-tau1e-2-r200-boxtree", tree="box")
+
 # The medium workload with a hundredfold larger shift (+ 1e-2 I): a better
 # conditioned system on which FP32 rounding of the stored blocks stays far below
 # the smallest eigenvalue (used to compare the mixed-precision forms).
@@ -137,7 +143,7 @@ RPY_LARGE = Workload(name="rpy-a0.29-N100k-ball1", n=100_000, point_set="ball1",
                      shift=0.0, leaf=400, h2_tol=1e-8, hss_tol=1e-2, max_rank=100, oversample=10, nrhs=16,
                      pcg_tol=1e-8, seed_base=21)
 
-BY_NAME = {w.name: w for w in (SMALL, MEDIUM, LARGE, MEDIUM_S2, HEADLINE, RPY_LARGE)}
+BY_NAME = {w.name: w for w in (SMALL, MEDIUM, LARGE, MEDIUM_S2, HEADLINE, HEADLINE_BOX, RPY_LARGE)}
 
 
 # Batched case: independent instances of uneven sizes.  N is log-uniform in
