@@ -93,6 +93,7 @@ struct BlockProblem {
   int term_begin, term_end;
   int add_eye;
   double beta;
+  int tile0;  // first workgroup of this problem in its launch's tile list
 };
 struct BlockTerm {
   const double* src;
@@ -171,8 +172,13 @@ int symv_row_tile(int max_m, int ncols);
 // a_f32: the A operands are FP32 (dot-form product only)
 void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int nprob,
                  int max_m, int max_n, int transA, int transB, int max_k = 1 << 30, int a_f32 = 0);
+// Block sums over a tile list: tile t belongs to problem tiles[t] (made by
+// block_tiles, which also sets BlockProblem::tile0); tiles of 64 rows x 16
+// columns when every problem has at most 16 columns (max_n <= 16), else 64 x 64.
+int block_tile_cols(int max_n);
+std::vector<int> block_tiles(std::vector<BlockProblem>& probs, int max_n);
 void launch_block(hipStream_t s, const BlockProblem* d_p, const BlockTerm* d_t,
-                  int nprob, int max_m, int max_n);
+                  const int* d_tiles, int ntiles, int max_n);
 // perm: tree position -> original index (for the RPY tensor, whose rows are
 // point components: component = original index mod 3); may be null otherwise
 void launch_kblock(hipStream_t s, const KBlockProblem* d_p, int nprob, int max_m,

@@ -1142,15 +1142,37 @@ void launch_gemm(hipStream_t s, const GemmProblem* d_p, const GemmTerm* d_t, int
 }
 
 // ---------------------------------------------------------- block updates --
+// dst = beta dst + sum_t alpha_t op(src_t) (+ I), per element in term order:
+// beta dst first, then the terms one by one.  Workgroups come from a tile
+// list, so problems of very different sizes launch no empty workgroups.
+int block_tile_cols(int max_n) { return max_n <= 16 ? 16 : 64; }
+
+std::vector<int> block_tiles(std::vector<BlockProblem>& probs, int max_n) {
+  const int bn = block_tile_cols(max_n);
+  std::vector<int> t;
+  for (size_t p = 0; p < probs.size(); ++p) {
+    probs[p].tile0 = (int)t.size();
+    const int64_t n = (int64_t)ceil_div(probs[p].m, 64) * ceil_div(probs[p].n, bn);
+    t.insert(t.end(), (size_t)n, (int)p);
+  }
+  return t;
+}
+
+__device__ __forceinline__ double block_src(const BlockTerm& T, int i, int j) {
+  return T.alpha * (T.trans ? T.src[j + (int64_t)i * T.lds] : T.src[i + (int64_t)j * T.lds]);
+}
+
+// 64 x BN tiles: element e of the tile is row e mod 64, column e / 64
+template <int BN>
 __global__ __launch_bounds__(256) void k_block(const BlockProblem* __restrict__ probs,
                                                const BlockTerm* __restrict__ terms,
-                                               int tiles_max) {
-  const int p = blockIdx.x / tiles_max, tile = blockIdx.x % tiles_max;
-  const BlockProblem P = probs[p];
-  const int tm = (P.m + 63) / 64, tn = (P.n + 63) / 64;
-  if (tile >= tm * tn) return;
-  const int i0 = (tile % tm) * 64, j0 = (tile / tm) * 64;
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+                                               const int* __restrict__ tiles, int tile_base) {
+  const int g = tile_base + blockIdx.x;
+  const BlockProblem P = probs[tiles[g]];
+  const int tile = g - P.tile0;
+  const int tm = (P.m + 63) / 64;
+  const int i0 = (tile % tm) * 64, j0 = (tile / tm) * BN;
+  for (int e = threadIdx.x; e < 64 * BN; e += 256) {
     const int i = i0 + (e & 63), j = j0 + (e >> 6);
     if (i >= P.m || j >= P.n) continue;
     double* d = P.dst + i + (int64_t)j * P.ldd;
@@ -1161,30 +1183,27 @@ __global__ __launch_bounds__(256) void k_block(const BlockProblem* __restrict__ 
     for (; t + 8 <= P.term_end; t += 8) {
       double x[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const BlockTerm T = terms[t + q];
-        x[q] = T.alpha * (T.trans ? T.src[j + (int64_t)i * T.lds] : T.src[i + (int64_t)j * T.lds]);
-      }
+      for (int q = 0; q < 8; ++q) x[q] = block_src(terms[t + q], i, j);
 #pragma unroll
       for (int q = 0; q < 8; ++q) v += x[q];
     }
-    for (; t < P.term_end; ++t) {
-      const BlockTerm T = terms[t];
-      v += T.alpha * (T.trans ? T.src[j + (int64_t)i * T.lds] : T.src[i + (int64_t)j * T.lds]);
-    }
+    for (; t < P.term_end; ++t) v += block_src(terms[t], i, j);
     if (P.add_eye && i == j) v += 1.0;
     *d = v;
   }
 }
 
-void launch_block(hipStream_t s, const BlockProblem* d_p, const BlockTerm* d_t, int nprob,
-                  int max_m, int max_n) {
-  if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
-  const int tiles = ceil_div(max_m, 64) * ceil_div(max_n, 64);
-  const int per = probs_per_launch(tiles, 256);
-  for (int p0 = 0; p0 < nprob; p0 += per)
-    hipLaunchKernelGGL(k_block, dim3((unsigned)std::min(per, nprob - p0) * tiles), dim3(256), 0, s,
-                       d_p + p0, d_t, tiles);
+void launch_block(hipStream_t s, const BlockProblem* d_p, const BlockTerm* d_t, const int* d_tiles,
+                  int ntiles, int max_n) {
+  if (ntiles <= 0 || max_n <= 0) return;
+  const int per = probs_per_launch(1, 256);  // workgroups per launch below 2^31 work-items
+  for (int t0 = 0; t0 < ntiles; t0 += per) {
+    const dim3 grid((unsigned)std::min(per, ntiles - t0));
+    if (block_tile_cols(max_n) == 16)
+      hipLaunchKernelGGL(k_block<16>, grid, dim3(256), 0, s, d_p, d_t, d_tiles, t0);
+    else
+      hipLaunchKernelGGL(k_block<64>, grid, dim3(256), 0, s, d_p, d_t, d_tiles, t0);
+  }
   SPD_HIP(hipGetLastError());
 }
 

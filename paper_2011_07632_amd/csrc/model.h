@@ -102,6 +102,8 @@ struct LaunchRec {
   int max_k = 1 << 30;  // bound on the terms' inner dimension (gemm records)
   int cap = 0;          // workgroup cap (symmetric-pair records), 0 = none
   int a_f32 = 0;        // FP32 A operands (gemm records)
+  const int* tiles = nullptr;  // tile list (block records)
+  int ntiles = 0;
 };
 // One block row of a symmetric product with at most 4 right-hand columns:
 // y = sum_t A_t B_t, and every mirrored term (an off-diagonal block A_ij of a

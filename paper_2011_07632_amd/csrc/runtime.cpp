@@ -285,10 +285,13 @@ void BlockBatch::term(const double* src, int lds, double alpha, int trans) {
 void BlockBatch::run(hipStream_t s, Stage& st) {
   if (probs.empty() || max_m == 0 || max_n == 0) return;
   const BlockTerm dummy{};
+  const std::vector<int> tl = block_tiles(probs, max_n);
+  if (tl.empty()) return;
   auto* dp = (const BlockProblem*)st.push(s, probs.data(), probs.size() * sizeof(BlockProblem));
   auto* dt = (const BlockTerm*)st.push(s, terms.empty() ? &dummy : terms.data(),
                                        std::max<size_t>(1, terms.size()) * sizeof(BlockTerm));
-  launch_block(s, dp, dt, (int)probs.size(), max_m, max_n);
+  auto* dl = (const int*)st.push(s, tl.data(), tl.size() * sizeof(int));
+  launch_block(s, dp, dt, dl, (int)tl.size(), max_n);
 }
 
 void TrsmBatch::add(const double* L, int ldl, double* B, int ldb, int n, int nrhs) {
@@ -663,10 +666,14 @@ void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, in
 
 void Recorder::block(Arena& a, hipStream_t s, const BlockBatch& b) {
   if (b.probs.empty() || b.max_m == 0 || b.max_n == 0) return;
+  std::vector<BlockProblem> p = b.probs;
+  const std::vector<int> tl = block_tiles(p, b.max_n);
+  if (tl.empty()) return;
   std::vector<BlockTerm> t = b.terms;
   if (t.empty()) t.push_back(BlockTerm{});
-  recs.push_back({1, keep(a, s, b.probs), keep(a, s, t), (int)b.probs.size(), b.max_m, b.max_n, 0,
-                  0, 0.0, -1});
+  recs.push_back({1, keep(a, s, p), keep(a, s, t), (int)p.size(), b.max_m, b.max_n, 0, 0, 0.0, -1});
+  recs.back().tiles = (const int*)keep(a, s, tl);
+  recs.back().ntiles = (int)tl.size();
 }
 
 void Recorder::trsm(Arena& a, hipStream_t s, const TrsmBatch& b, int trans) {
@@ -681,7 +688,7 @@ void Recorder::replay(hipStream_t s) const {
       launch_gemm(s, (const GemmProblem*)r.probs, (const GemmTerm*)r.terms, r.nprob, r.max_m,
                   r.max_n, r.transA, r.transB, r.max_k, r.a_f32);
     else if (r.type == 1)
-      launch_block(s, (const BlockProblem*)r.probs, (const BlockTerm*)r.terms, r.nprob, r.max_m,
+      launch_block(s, (const BlockProblem*)r.probs, (const BlockTerm*)r.terms, r.tiles, r.ntiles,
                    r.max_n);
     else if (r.type == 3)
       launch_symv(s, (const SymProblem*)r.probs, (const SymTerm*)r.terms, r.nprob, r.max_m, r.max_n,
