@@ -439,6 +439,14 @@ void h2_build_impl(H2Model& H, const double* points, int64_t npts) {
 // 416 -> 1.924, 448 -> 1.929, 512 (one row per workgroup) -> 1.939.
 static constexpr int kNearCap = 416;
 
+// Bytes of near blocks per part of a leaf row in the 5-16 column product.
+// Each part writes its own m x n partial result, which the block sum reads
+// back; leaf rows at N = 1M hold about 6.7 MB of blocks.  Measured there with
+// 16 columns (near-field launch + its block sum, ms): 1 MiB 5.09 + 0.45,
+// 2 MiB 5.02 + 0.40, 4 MiB 5.09 + 0.36.  The coupling rows keep 1 MiB
+// (2 MiB: 3.86 + 0.43 against 3.72 + 0.46).
+static double near_split(int ncols) { return ncols > 4 ? 2.0 * (1 << 20) : 0.0; }
+
 // FP32 copies of the blocks that the symmetric-pair product reads.
 static void make_f32_blocks(H2Model& H) {
   if (!H.Bh32.empty() || !H.nearA32.empty()) return;
@@ -638,7 +646,7 @@ static void build_plan(H2Model& H, int m, bool f32 = false) {
       }
     }
     Recorder near;
-    near.symv(a, s, rows, m, 1.0, f32);
+    near.symv(a, s, rows, m, 1.0, f32, near_split(m));
     near.tag_from(0, 400);
     // the product launch goes to the side stream, the block sum into y after the join
     pl->side.recs.push_back(near.recs[0]);
@@ -671,7 +679,7 @@ static void build_plan(H2Model& H, int m, bool f32 = false) {
                            (int)T.size(j), j == v ? -1 : j - lf});
       }
     }
-    rec.symv(a, s, rows, m, 1.0, f32);
+    rec.symv(a, s, rows, m, 1.0, f32, near_split(m));
     rec.tag_from(first, 400);
   } else {
     GemmBatch g(0, 0);

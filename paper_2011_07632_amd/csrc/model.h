@@ -135,8 +135,9 @@ struct Recorder {
   // launch that sums each row's partial results in a fixed order into
   // y = beta * y + sum)
   // (a_f32: the terms' A pointers address FP32 copies with the same layout)
+  // (split_bytes: bytes of A per part of a row, 0 = the default of 1 MiB)
   void symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n, double beta = 0.0,
-            bool a_f32 = false);
+            bool a_f32 = false, double split_bytes = 0.0);
   void block(Arena& a, hipStream_t s, const BlockBatch& b);
   void trsm(Arena& a, hipStream_t s, const TrsmBatch& b, int trans);
   void replay(hipStream_t s) const;

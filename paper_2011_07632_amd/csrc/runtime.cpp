@@ -528,7 +528,8 @@ void Recorder::gemm(Arena& a, hipStream_t s, const GemmBatch& b) {
 // every output row as the sum, in a fixed order, of its own parts and of the
 // mirrored products addressed to it.
 void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, int n, double beta,
-                    bool a_f32) {
+                    bool a_f32, double split_bytes) {
+  if (split_bytes <= 0) split_bytes = kSplitBytes;
   // the terms' A pointers address FP64 or (a_f32) FP32 elements
   const int64_t esz = a_f32 ? 4 : 8;
   auto a_at = [esz](const double* A, int64_t elems) {
@@ -592,7 +593,7 @@ void Recorder::symv(Arena& a, hipStream_t s, const std::vector<SymRow>& rows, in
     int64_t K = 0;
     for (const MT& q : mt) K += q.k;
     const int64_t nparts =
-        K == 0 ? 1 : std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)std::ceil(8.0 * R.m * K / kSplitBytes)));
+        K == 0 ? 1 : std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)std::ceil(8.0 * R.m * K / split_bytes)));
     size_t q = 0;
     int64_t off = 0;
     for (int64_t part = 0; part < nparts; ++part) {
