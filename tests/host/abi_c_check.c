@@ -14,13 +14,16 @@ static int fail(const char* what) {
 int main(void) {
   double stand_in = 0.0; /* never read: every call below fails its checks first */
   spd_kernel k = {SPD_K_MATERN32, 0.1, 1e-4};
-  spd_h2_opts o = {0, 1.0, 1e-8, 8, 128, 2048, 90.0, 1}; /* leaf_size 0 is invalid */
+  spd_h2_opts o = {0, 1.0, 1e-8, 8, 128, 2048, 90.0, 1, SPD_TREE_KD}; /* leaf_size 0 is invalid */
   spd_h2_t h = (spd_h2_t)&stand_in;
   if (h2_build(&stand_in, 100, k, &o, NULL, &h) != SPD_E_INVALID) return fail("h2_build status");
   if (h != NULL) return fail("h2_build clears *out");
   if (strstr(spd_last_error(), "leaf_size") == NULL) return fail("h2_build message");
 
   o.leaf_size = 64;
+  o.tree = 2;
+  if (h2_build(&stand_in, 100, k, &o, NULL, &h) != SPD_E_INVALID) return fail("unknown tree kind");
+  o.tree = SPD_TREE_BOX;
   k.ell = -1.0;
   if (h2_build(&stand_in, 100, k, &o, NULL, &h) != SPD_E_INVALID) return fail("negative ell");
 

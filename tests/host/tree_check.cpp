@@ -1,8 +1,8 @@
 // Host-only check of the partition tree and admissibility lists (TreeHost),
 // built with AddressSanitizer and UndefinedBehaviorSanitizer by
 // tests/test_host_sanitizers.py.  For seeded random point sets of several
-// sizes and leaf sizes it builds the tree and lists and checks, exiting
-// non-zero on the first violation:
+// sizes and leaf sizes it builds the tree (kd and box bisection) and lists and
+// checks, exiting non-zero on the first violation:
 //   - perm is a permutation and node ranges nest (children split the parent);
 //   - every leaf holds at most leaf_size points and the tree is perfect;
 //   - near and coupling lists are symmetric, sorted, and disjoint;
@@ -24,13 +24,18 @@ static int fail(const char* what, int n, int leaf) {
   return 1;
 }
 
-static int check(int n, int leaf, unsigned seed) {
+static int check(int n, int leaf, unsigned seed, int kind) {
   std::mt19937_64 rng(seed);
   std::uniform_real_distribution<double> U(0.0, 1.0);
   std::vector<double> pts((size_t)3 * n);
   for (double& x : pts) x = U(rng);
   TreeHost T;
-  T.build(pts.data(), n, leaf, 1.0);
+  try {
+    T.build(pts.data(), n, leaf, 1.0, kind);
+  } catch (const spd::Error&) {
+    return fail("build failed", n, leaf);
+  }
+  if (kind == SPD_TREE_BOX && T.D % 3 != 0) return fail("box tree depth not a multiple of 3", n, leaf);
   std::vector<int64_t> p(T.perm.begin(), T.perm.end());
   std::sort(p.begin(), p.end());
   for (int i = 0; i < n; ++i)
@@ -101,7 +106,10 @@ int main() {
   const int sizes[][2] = {{1, 4}, {5, 8}, {17, 4}, {600, 32}, {1000, 7}, {3001, 50}, {4096, 64}};
   unsigned seed = 1;
   for (const auto& s : sizes)
-    if (check(s[0], s[1], seed++)) return 1;
+    if (check(s[0], s[1], seed++, SPD_TREE_KD)) return 1;
+  const int box[][2] = {{1, 4}, {5, 8}, {600, 64}, {3001, 128}, {4096, 100}};
+  for (const auto& s : box)
+    if (check(s[0], s[1], seed++, SPD_TREE_BOX)) return 1;
   std::printf("tree_check ok\n");
   return 0;
 }
