@@ -133,7 +133,7 @@ def host_facts() -> dict:
     return {"nproc": aff, "cpu_model": model, "ram_bytes": ram}
 
 
-def cpu_baseline(w, n_sample: int, iters_gpu: int, iters_sample: int = 10) -> dict:
+def cpu_baseline(w, n_sample: int, iters_gpu: int, iters_sample: int = 40) -> dict:
     """The CPU oracle, unchanged, on a bounded sample of the workload: the same
     kernel, shift, tolerances and ranks on n_sample points of the same point
     set, run end to end (H^2 build, SPD-HSS build, iters_sample PCG

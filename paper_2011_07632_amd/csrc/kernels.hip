@@ -9,6 +9,7 @@
 #include <algorithm>
 
 #include <cmath>
+#include <type_traits>
 
 namespace spd {
 
@@ -818,6 +819,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int R = 1 << lgR, G = 4 >> lgR;
     const int st = w & (R - 1), g = w >> lgR;
     const int r0 = i0 + 64 * st;  // this wave's first row
+    // 16-row quads of this wave's strip that hold rows of the block (0 to 4;
+    // uniform per wave): quads past the last row take no loads, MFMAs or
+    // transposes
+    const int nq = min(4, max(0, (m - r0 + 15) >> 4));
     const bool colok = lr < n;
     // the mirrored product's right operand: this wave's own input rows,
     // X[r0 + 4r + l/16][l%16] for row quads r = 0..15
@@ -881,14 +886,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // zero rows of X in the mirrored product and give row sums that are never
     // stored, and columns past K give mirrored entries that are never stored;
     // values of columns past n reach only outputs that are never stored.
-    auto issue = [&](const Cur& c, int q, double (&ra)[4][4], double (&rb)[4]) {
+    auto issue = [&](auto nqc, const Cur& c, int q, double (&ra)[4][4], double (&rb)[4]) {
+      constexpr int NQ = decltype(nqc)::value;
+      if constexpr (NQ == 0) return;
       const int col0 = 16 * (c.it * G + g) + 4 * q, rem = c.K - col0;
       const __amdgpu_buffer_rsrc_t sa = __builtin_amdgcn_make_buffer_rsrc(
           (void*)(c.A + (int64_t)col0 * (c.ldab / ES)), (short)0, rem > 0 ? rem * c.ldab : 0, kBufWord3);
       const __amdgpu_buffer_rsrc_t sb = __builtin_amdgcn_make_buffer_rsrc(
           (void*)(c.B + col0), (short)0, rem > 0 ? c.bext - 8 * col0 : 0, kBufWord3);
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
+      for (int s4 = 0; s4 < NQ; ++s4) {
         if constexpr (ES == 8)
           ra[s4][q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sa, c.va[s4], 0, kBufNT));
         else
@@ -896,9 +903,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
       rb[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sb, c.vb, 0, 0));
     };
-    auto load = [&](const Cur& c, double (&ra)[4][4], double (&rb)[4]) {
+    auto load = [&](auto nqc, const Cur& c, double (&ra)[4][4], double (&rb)[4]) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) issue(c, q, ra, rb);
+      for (int q = 0; q < 4; ++q) issue(nqc, c, q, ra, rb);
     };
     // wait for every load issued so far (the current chunk's), before the
     // next chunk's loads are issued
@@ -909,35 +916,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // one step: the loads of chunk c have arrived in (ca, cb); the loads of
     // the next chunk nx go out between the row-sum MFMAs of c, and so do the
     // LDS transposes of c
-    auto process = [&](const Cur& c, const double (&ca)[4][4], const double (&cb)[4], const Cur& nx,
-                       double (&na)[4][4], double (&nb)[4], bool more) {
+    auto process = [&](auto nqc, const Cur& c, const double (&ca)[4][4], const double (&cb)[4],
+                       const Cur& nx, double (&na)[4][4], double (&nb)[4], bool more) {
+      constexpr int NQ = decltype(nqc)::value;
       const int c0 = 16 * (c.it * G + g);
       double bs[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) bs[q] = (c0 + 4 * q + lk < c.K) ? c.sc * cb[q] : 0.0;
+      for (int q = 0; q < 4; ++q) bs[q] = (NQ > 0 && c0 + 4 * q + lk < c.K) ? c.sc * cb[q] : 0.0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
+        for (int s4 = 0; s4 < NQ; ++s4)
           acc[s4] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[s4][q], bs[q], acc[s4], 0, 0, 0);
-        if (more) issue(nx, q, na, nb);
+        if (more) issue(nqc, nx, q, na, nb);
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) tr[w][16 * s4 + lr][4 * q + lk] = ca[s4][q];
+        for (int s4 = 0; s4 < NQ; ++s4) tr[w][16 * s4 + lr][4 * q + lk] = ca[s4][q];
       }
       // issue order per column quad: MFMAs alternating with the buffer loads
       // and LDS writes (scheduling-group masks: 0x008 MFMA, 0x020 vector
       // memory read, 0x200 LDS write)
+      if constexpr (NQ == 4) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
-        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        for (int i = 0; i < 4; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        }
+      } else if constexpr (NQ > 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int j = 0; j < NQ; ++j) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+          }
+          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x200, NQ, 0);
+        }
       }
       if (!c.pt) return;  // uniform across the workgroup (per term)
       // LDS-only ordering: the prefetched global loads of the next chunk
@@ -950,7 +971,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
       for (int u = 0; u < 4; ++u) pa[u] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
+      for (int r = 0; r < 4 * NQ; ++r)
         pa[r & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(tr[w][4 * r + lk][lr], xop[r], pa[r & 3], 0, 0, 0);
       // the chunk's mirrored result is stored after the next chunk's wait
       // (so that waiting for a chunk's loads never waits for a store just issued)
@@ -1012,24 +1033,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
       return open(c.t + 1, nx);
     };
-    // two operand buffers in turn
-    double a0[4][4], b0[4], a1[4][4], b1[4];
-    Cur c0s, c1s;
-    if (open(P.term_begin, c0s)) {
-      load(c0s, a0, b0);
-      while (true) {
-        ready();
+    // the chunk loop for this wave's quad count (a constant inside)
+    auto run = [&](auto nqc) {
+      // two operand buffers in turn
+      double a0[4][4], b0[4], a1[4][4], b1[4];
+      Cur c0s, c1s;
+      if (open(P.term_begin, c0s)) {
+        load(nqc, c0s, a0, b0);
+        while (true) {
+          ready();
+          flush();
+          const bool more0 = next(c0s, c1s);
+          process(nqc, c0s, a0, b0, c1s, a1, b1, more0);
+          if (!more0) break;
+          ready();
+          flush();
+          const bool more1 = next(c1s, c0s);
+          process(nqc, c1s, a1, b1, c0s, a0, b0, more1);
+          if (!more1) break;
+        }
         flush();
-        const bool more0 = next(c0s, c1s);
-        process(c0s, a0, b0, c1s, a1, b1, more0);
-        if (!more0) break;
-        ready();
-        flush();
-        const bool more1 = next(c1s, c0s);
-        process(c1s, a1, b1, c0s, a0, b0, more1);
-        if (!more1) break;
       }
-      flush();
+    };
+    switch (nq) {
+      case 0: run(std::integral_constant<int, 0>{}); break;
+      case 1: run(std::integral_constant<int, 1>{}); break;
+      case 2: run(std::integral_constant<int, 2>{}); break;
+      case 3: run(std::integral_constant<int, 3>{}); break;
+      default: run(std::integral_constant<int, 4>{}); break;
     }
     // row sums: D[l/16 + 4v][l%16] of strip s is row r0 + 16s + l/16 + 4v,
     // column l%16; with G > 1 the groups' sums are added in group order

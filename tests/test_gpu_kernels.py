@@ -152,9 +152,12 @@ def test_cpqr(B, m, n, which):
 # A_it is read once for S_ij x_j and S_ji x_i = A_it^T x_i.  Up to 4 columns
 # take the streaming kernel, 5-16 the FP64 MFMA kernel; rows span partial
 # waves (37), several waves (100), exactly one tile (256), a ragged second tile
-# (300) and the 1 MiB split of long rows (m = 512, 4 terms).
+# (300) and the 1 MiB split of long rows (m = 512, 4 terms).  In the MFMA
+# kernel a wave skips the 16-row quads of its 64-row strip past the last row:
+# m = 16 and 20 keep one and two quads, 37 three; m = 150 gives four strips of
+# which the third keeps two quads and the fourth none.
 @pytest.mark.parametrize("nblk,m,nterm", [(3, 37, 1), (7, 100, 3), (5, 256, 2), (9, 300, 4), (9, 512, 4),
-                                          (4, 16, 0)])
+                                          (4, 16, 0), (7, 20, 3), (5, 150, 2)])
 @pytest.mark.parametrize("n", [1, 3, 5, 16])
 def test_symmetric_pair_product(B, nblk, m, nterm, n):
     rng = np.random.default_rng(nblk * 1000 + m + 7 * nterm + n)
