@@ -477,11 +477,11 @@ spd_status spd_test_cpqr(double* A, double* Q, int32_t* piv, int32_t* rank, doub
     c.ldq = m;
     c.maxrank = mr;
     c.tol = tol;
-    c.nrm = which == 1 ? a.get_n<double>(n) : nullptr;
+    c.nrm = which == 1 ? a.get_n<double>(2 * (size_t)n + mr + 2) : nullptr;
   }
   auto* d = (const CpqrProblem*)st.push(s, p.data(), p.size() * sizeof(CpqrProblem));
   if (which == 0) launch_cpqr_reg(s, d, batch, m, n);
-  else launch_cpqr_glob(s, d, batch, m, n);
+  else cpqr_global(s, st, p, d, m, n);
   SPD_HIP(hipStreamSynchronize(s));
   SPD_API_END
 }

@@ -199,6 +199,19 @@ void launch_cpqr_formq(hipStream_t s, const CpqrProblem* d_p, int nprob);
 constexpr int kCpqrBigRows = 8000;
 void launch_cpqr_glob(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_m,
                       int max_n);
+// The wide form of the global-memory variant (one launch per step, columns
+// over many workgroups; same results as launch_cpqr_glob above 2048 rows).
+// Every problem's nrm workspace holds 2n + maxrank + 2 doubles and P.R is
+// set.  d_wg: workgroup table (problem, first column, end column, 0); d_done:
+// one flag per problem, set once the problem has stopped; d_fix: (problem,
+// step) for every step below the problem's min(m, n, maxrank); d_rc:
+// (problem, column) for every column.
+void launch_cpqr_wide_norms(hipStream_t s, const CpqrProblem* d_p, const int4* d_wg, int nwg,
+                            int* d_done);
+void launch_cpqr_wide_step(hipStream_t s, const CpqrProblem* d_p, const int4* d_wg, int nwg,
+                           int max_m, int t, int* d_done);
+void launch_cpqr_wide_finish(hipStream_t s, const CpqrProblem* d_p, int nprob, const int2* d_fix,
+                             int nfix, const int2* d_rc, int nrc);
 bool cpqr_reg_fits(int m, int n);
 
 // vector kernels

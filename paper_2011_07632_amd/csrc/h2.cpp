@@ -259,7 +259,7 @@ void h2_build_impl(H2Model& H, const double* points, int64_t npts) {
         cp.lda = jb.m;
         cp.maxrank = mr;
         cp.tol = H.opts.tol;
-        cp.nrm = tmp.get_n<double>(c);
+        cp.nrm = tmp.get_n<double>(2 * (size_t)c + mr + 2);  // the wide form's workspace
       }
       auto* dkb = (const KBlockProblem*)st.push(s, kb.data(), kb.size() * sizeof(KBlockProblem));
       launch_kblock(s, dkb, nj, maxM, maxc, H.pts, n, H.kern.kind, H.kern.ell, H.kern.shift, H.perm_d);
@@ -268,7 +268,7 @@ void h2_build_impl(H2Model& H, const double* points, int64_t npts) {
         sketch.run(s, st);
       }
       auto* dcq = (const CpqrProblem*)st.push(s, cq.data(), cq.size() * sizeof(CpqrProblem));
-      launch_cpqr_glob(s, dcq, nj, maxm, maxc);
+      cpqr_global(s, st, cq, dcq, maxm, maxc);
       std::vector<int> ranks(nj);
       SPD_HIP(hipMemcpyAsync(ranks.data(), d_rank, nj * sizeof(int), hipMemcpyDeviceToHost, s));
       SPD_HIP(hipStreamSynchronize(s));

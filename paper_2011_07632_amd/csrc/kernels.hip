@@ -2003,6 +2003,184 @@ __global__ __launch_bounds__(1024) void k_cpqr_big(const CpqrProblem* __restrict
   }
 }
 
+// Wide form of the global-memory variant, for a few large problems (the upper
+// levels of the H^2 construction, where one workgroup per problem leaves the
+// chip nearly idle): one launch per step t, the columns of every problem split
+// over many workgroups.  Each column is still updated by one wave with the
+// loops of k_cpqr_big, and every workgroup finds the pivot with the same
+// reduction, so pivots, norms and outputs are those of k_cpqr_big.  Workspace
+// (P.nrm, 2n + maxrank + 2 doubles): the squared trailing norms in two
+// buffers (step t reads buffer t mod 2 and writes the other, so no workgroup
+// reads a norm written in its own launch), alpha_t per step, the first
+// pivot's norm, and the problem's state (negative while running, else its
+// rank).  The pivot column itself is only read during its step; its R
+// diagonal and zeros below are written by k_cpqr_wide_fix at the end.
+// Workgroup table entry: (problem, first column, end column, 0).
+struct CpqrWs {
+  double *n0, *n1, *alpha, *ref, *state;
+};
+__device__ __forceinline__ CpqrWs cpqr_ws(const CpqrProblem& P) {
+  CpqrWs w;
+  w.n0 = P.nrm;
+  w.n1 = P.nrm + P.n;
+  w.alpha = P.nrm + 2 * (int64_t)P.n;
+  w.ref = w.alpha + P.maxrank;
+  w.state = w.ref + 1;
+  return w;
+}
+
+__global__ __launch_bounds__(1024) void k_cpqr_wide_norms(const CpqrProblem* __restrict__ probs,
+                                                          const int4* __restrict__ wg, int* done) {
+  constexpr int NW = 16;
+  const int4 g = wg[blockIdx.x];
+  const CpqrProblem P = probs[g.x];
+  const CpqrWs ws = cpqr_ws(P);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t lda = P.lda;
+  for (int col = g.y + w; col < g.z; col += NW) {
+    double s2 = 0.0;
+    for (int row = lane; row < P.m; row += 64) {
+      const double x = P.A[row + col * lda];
+      s2 += x * x;
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) ws.n0[col] = s2;
+  }
+  if (g.y == 0 && threadIdx.x == 0) {
+    *ws.state = -1.0;
+    done[g.x] = 0;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_cpqr_wide_step(const CpqrProblem* __restrict__ probs,
+                                                         const int4* __restrict__ wg, int t,
+                                                         int* done) {
+  constexpr int NW = 16;
+  extern __shared__ double vbuf[];  // m
+  const int4 g = wg[blockIdx.x];
+  const CpqrProblem P = probs[g.x];
+  const CpqrWs ws = cpqr_ws(P);
+  if (*ws.state >= 0.0) return;  // finished (uniform)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = P.m, n = P.n;
+  const int64_t lda = P.lda;
+  const double* nin = (t & 1) ? ws.n1 : ws.n0;
+  double* nout = (t & 1) ? ws.n0 : ws.n1;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int j = lane; j < n; j += 64) {
+    const double v = nin[j];
+    if (v > best) { best = v; bi = j; }
+  }
+  wave_argmax(best, bi);
+  const double nrm = sqrt(fmax(best, 0.0));
+  const double ref = (t == 0) ? nrm : *ws.ref;
+  const int kmax = min(min(m, n), P.maxrank);
+  if (t >= kmax || !(nrm > P.tol * ref) || nrm == 0.0) {
+    if (g.y == 0 && threadIdx.x == 0) {
+      *ws.state = (double)t;
+      done[g.x] = 1;
+    }
+    return;
+  }
+  const double xt = P.A[t + (int64_t)bi * lda];
+  const double alpha = (xt >= 0.0) ? -nrm : nrm;
+  const double beta = 1.0 / (nrm * (nrm + fabs(xt)));
+  const bool first = g.y == 0;  // the problem's first workgroup records the step
+  for (int row = threadIdx.x; row < m; row += 1024) {
+    const double v = row < t ? 0.0 : (row == t ? xt - alpha : P.A[row + (int64_t)bi * lda]);
+    vbuf[row] = v;
+    if (first && P.hbeta) P.V[row + (int64_t)t * m] = v;
+  }
+  if (first && threadIdx.x == 0) {
+    if (P.hbeta) P.hbeta[t] = beta;
+    P.piv[t] = bi;
+    if (P.diag) P.diag[t] = nrm;
+    ws.alpha[t] = alpha;
+    if (t == 0) *ws.ref = nrm;
+  }
+  __syncthreads();
+  for (int col = g.y + w; col < g.z; col += NW) {
+    if (col == bi || nin[col] < 0.0) {
+      if (lane == 0) nout[col] = -1.0;
+      continue;
+    }
+    double d = 0.0;
+    for (int row = lane; row < m; row += 64)
+      if (row >= t) d += vbuf[row] * P.A[row + col * lda];
+    d = wave_sum(d);
+    double s2 = 0.0;
+    for (int row = lane; row < m; row += 64) {
+      if (row < t) continue;
+      const double x = P.A[row + col * lda] - beta * d * vbuf[row];
+      P.A[row + col * lda] = x;
+      if (row > t) s2 += x * x;
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) nout[col] = s2;
+  }
+}
+
+// The pivot column of step s (one workgroup per (problem, s) entry of the
+// table, x: problem, y: s): R diagonal alpha_s in row s, zeros below.
+__global__ __launch_bounds__(256) void k_cpqr_wide_fix(const CpqrProblem* __restrict__ probs,
+                                                       const int2* __restrict__ fx) {
+  const int2 f = fx[blockIdx.x];
+  const CpqrProblem P = probs[f.x];
+  const CpqrWs ws = cpqr_ws(P);
+  const int rank = (int)*ws.state, s = f.y;
+  if (s >= rank) return;
+  double* col = P.A + (int64_t)P.piv[s] * P.lda;
+  for (int row = s + threadIdx.x; row < P.m; row += 256) col[row] = row == s ? ws.alpha[s] : 0.0;
+}
+
+// Rank, the unused columns after the pivots in ascending order (one
+// workgroup per problem).
+__global__ void k_cpqr_wide_perm(const CpqrProblem* __restrict__ probs) {
+  const CpqrProblem P = probs[blockIdx.x];
+  const CpqrWs ws = cpqr_ws(P);
+  if (threadIdx.x != 0) return;
+  const int rank = (int)*ws.state;
+  const double* fin = (rank & 1) ? ws.n1 : ws.n0;  // written by the last step (step rank - 1)
+  *P.rank = rank;
+  int pos = rank;
+  for (int j = 0; j < P.n; ++j)
+    if (fin[j] >= 0.0) P.piv[pos++] = j;
+}
+
+// R rows in pivot order (one workgroup per (problem, column) entry).
+__global__ __launch_bounds__(256) void k_cpqr_wide_r(const CpqrProblem* __restrict__ probs,
+                                                     const int2* __restrict__ rc) {
+  const int2 f = rc[blockIdx.x];
+  const CpqrProblem P = probs[f.x];
+  if (!P.R) return;
+  const int rank = *P.rank, j = f.y;
+  const double* col = P.A + (int64_t)P.piv[j] * P.lda;
+  for (int i = threadIdx.x; i < rank; i += 256) P.R[i + (int64_t)j * P.maxrank] = col[i];
+}
+
+void launch_cpqr_wide_norms(hipStream_t s, const CpqrProblem* d_p, const int4* d_wg, int nwg,
+                            int* d_done) {
+  if (nwg <= 0) return;
+  hipLaunchKernelGGL(k_cpqr_wide_norms, dim3(nwg), dim3(1024), 0, s, d_p, d_wg, d_done);
+  SPD_HIP(hipGetLastError());
+}
+void launch_cpqr_wide_step(hipStream_t s, const CpqrProblem* d_p, const int4* d_wg, int nwg,
+                           int max_m, int t, int* d_done) {
+  if (nwg <= 0) return;
+  SPD_REQUIRE(max_m <= kCpqrBigRows, SPD_E_INVALID, "cpqr: more than 8000 rows");
+  hipLaunchKernelGGL(k_cpqr_wide_step, dim3(nwg), dim3(1024), (size_t)max_m * sizeof(double), s, d_p,
+                     d_wg, t, d_done);
+  SPD_HIP(hipGetLastError());
+}
+void launch_cpqr_wide_finish(hipStream_t s, const CpqrProblem* d_p, int nprob, const int2* d_fix,
+                             int nfix, const int2* d_rc, int nrc) {
+  if (nfix > 0) hipLaunchKernelGGL(k_cpqr_wide_fix, dim3(nfix), dim3(256), 0, s, d_p, d_fix);
+  if (nprob > 0) hipLaunchKernelGGL(k_cpqr_wide_perm, dim3(nprob), dim3(64), 0, s, d_p);
+  if (nrc > 0) hipLaunchKernelGGL(k_cpqr_wide_r, dim3(nrc), dim3(256), 0, s, d_p, d_rc);
+  SPD_HIP(hipGetLastError());
+}
+
 // Q = H_0 H_1 ... H_{rank-1} [I; 0] by backward accumulation: start from the
 // first rank columns of the identity and apply H_t = I - beta_t v_t v_t^T for
 // t = rank-1 down to 0 (it touches rows >= t of columns >= t only); then flip

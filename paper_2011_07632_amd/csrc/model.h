@@ -56,6 +56,12 @@ class Stage {
   size_t cur_ = 0, off_ = 0;
 };
 
+// Pivoted QR of problems in global memory (launch_cpqr_glob), in the wide
+// form (one launch per step over many workgroups) above 2048 rows; h are the
+// host copies of the device descriptors d.
+void cpqr_global(hipStream_t s, Stage& st, const std::vector<CpqrProblem>& h, const CpqrProblem* d,
+                 int max_m, int max_n);
+
 struct GemmBatch {
   std::vector<GemmProblem> probs;
   std::vector<GemmTerm> terms;

@@ -294,6 +294,49 @@ void BlockBatch::run(hipStream_t s, Stage& st) {
   launch_block(s, dp, dt, dl, (int)tl.size(), max_n);
 }
 
+void cpqr_global(hipStream_t s, Stage& st, const std::vector<CpqrProblem>& h, const CpqrProblem* d,
+                 int max_m, int max_n) {
+  const int nprob = (int)h.size();
+  if (nprob == 0) return;
+  if (max_m <= 2048) {
+    launch_cpqr_glob(s, d, nprob, max_m, max_n);
+    return;
+  }
+  // about 768 workgroups over all columns, 16 columns (a column per wave) or more each
+  int64_t cols = 0;
+  int kmax = 0;
+  for (const CpqrProblem& p : h) {
+    cols += p.n;
+    kmax = std::max(kmax, std::min(std::min(p.m, p.n), p.maxrank));
+  }
+  const int cb = 16 * (int)std::max<int64_t>(1, (cols + 16 * 768 - 1) / (16 * 768));
+  std::vector<int4> wg;
+  std::vector<int2> fix, rc;
+  for (int q = 0; q < nprob; ++q) {
+    for (int c = 0; c < h[q].n; c += cb) wg.push_back(make_int4(q, c, std::min(h[q].n, c + cb), 0));
+    const int km = std::min(std::min(h[q].m, h[q].n), h[q].maxrank);
+    for (int t = 0; t < km; ++t) fix.push_back(make_int2(q, t));
+    for (int j = 0; j < h[q].n; ++j) rc.push_back(make_int2(q, j));
+  }
+  const std::vector<int> zero(nprob, 0);
+  auto* dwg = (const int4*)st.push(s, wg.data(), wg.size() * sizeof(int4));
+  auto* dfix = fix.empty() ? nullptr : (const int2*)st.push(s, fix.data(), fix.size() * sizeof(int2));
+  auto* drc = (const int2*)st.push(s, rc.data(), rc.size() * sizeof(int2));
+  auto* ddone = (int*)st.push(s, zero.data(), zero.size() * sizeof(int));
+  launch_cpqr_wide_norms(s, d, dwg, (int)wg.size(), ddone);
+  std::vector<int> done(nprob);
+  for (int t = 0; t <= kmax; ++t) {
+    launch_cpqr_wide_step(s, d, dwg, (int)wg.size(), max_m, t, ddone);
+    // every 32 steps: stop once every problem has stopped
+    if ((t & 31) == 31 && t < kmax) {
+      SPD_HIP(hipMemcpyAsync(done.data(), ddone, nprob * sizeof(int), hipMemcpyDeviceToHost, s));
+      SPD_HIP(hipStreamSynchronize(s));
+      if (std::all_of(done.begin(), done.end(), [](int x) { return x != 0; })) break;
+    }
+  }
+  launch_cpqr_wide_finish(s, d, nprob, dfix, (int)fix.size(), drc, (int)rc.size());
+}
+
 void TrsmBatch::add(const double* L, int ldl, double* B, int ldb, int n, int nrhs) {
   if (n <= 0 || nrhs <= 0) return;
   TrsmProblem p{};
