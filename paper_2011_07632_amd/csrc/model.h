@@ -57,8 +57,8 @@ class Stage {
 };
 
 // Pivoted QR of problems in global memory (launch_cpqr_glob), in the wide
-// form (one launch per step over many workgroups) above 2048 rows; h are the
-// host copies of the device descriptors d.
+// form (one launch per step over many workgroups) above 2048 rows or for fewer
+// than 128 problems; h are the host copies of the device descriptors d.
 void cpqr_global(hipStream_t s, Stage& st, const std::vector<CpqrProblem>& h, const CpqrProblem* d,
                  int max_m, int max_n);
 

@@ -298,7 +298,8 @@ void cpqr_global(hipStream_t s, Stage& st, const std::vector<CpqrProblem>& h, co
                  int max_m, int max_n) {
   const int nprob = (int)h.size();
   if (nprob == 0) return;
-  if (max_m <= 2048) {
+  // one workgroup per problem fills the chip only with many problems
+  if (max_m <= 2048 && nprob >= 128) {
     launch_cpqr_glob(s, d, nprob, max_m, max_n);
     return;
   }
