@@ -163,8 +163,10 @@ void launch_to_f32(hipStream_t s, const CvtProblem* d_p, int nprob);
 // cap > 0 bounds the number of workgroups (they then walk the problems with a
 // stride), so that the launch can run beside latency-bound work.  a_f32: the
 // terms' A operands are FP32 (same element layout), widened to FP64 on load.
+// mir = 0 declares that no term has a mirrored output (T.P null throughout):
+// 5-16 columns then take the plain-product form of the kernel.
 void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
-                 int max_n, int cap = 0, int a_f32 = 0);
+                 int max_n, int cap = 0, int a_f32 = 0, int mir = 1);
 // rows per workgroup of launch_symv for a launch whose largest problem has max_m rows
 int symv_row_tile(int max_m, int ncols);
 // max_k bounds the terms' inner dimension (used to pick the dot-form variant

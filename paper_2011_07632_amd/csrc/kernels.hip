@@ -796,9 +796,12 @@ static __device__ inline SymTerm sym_term(const SymTerm* t, int i) {
   return T;
 }
 
-template <typename TA>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_symm16(
-    const SymProblem* __restrict__ probs, const SymTerm* __restrict__ terms, int tiles_max, int nwork, int nprob) {
+// MIR = false: plain products (no term has a mirrored output), whose waves
+// keep no mirrored state and make no transposes.
+template <typename TA, bool MIR>
+__device__ __forceinline__ void symm16_body(const SymProblem* __restrict__ probs,
+                                            const SymTerm* __restrict__ terms, int tiles_max,
+                                            int nwork, int nprob) {
   constexpr int ES = (int)sizeof(TA);  // bytes of an A element (FP64, or FP32 copies widened on load)
   __shared__ double tr[4][64][17];      // per-wave transpose slot; row-sum exchange between groups
   __shared__ double red[2][4][16][17];  // per-wave mirrored partials, two chunks in flight
@@ -827,7 +830,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // the mirrored product's right operand: this wave's own input rows,
     // X[r0 + 4r + l/16][l%16] for row quads r = 0..15
     double xop[16];
-    {
+    if constexpr (MIR) {
       gdouble* Xg = (gdouble*)P.X;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -929,13 +932,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         for (int s4 = 0; s4 < NQ; ++s4)
           acc[s4] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[s4][q], bs[q], acc[s4], 0, 0, 0);
         if (more) issue(nqc, nx, q, na, nb);
+        if constexpr (MIR) {
 #pragma unroll
-        for (int s4 = 0; s4 < NQ; ++s4) tr[w][16 * s4 + lr][4 * q + lk] = ca[s4][q];
+          for (int s4 = 0; s4 < NQ; ++s4) tr[w][16 * s4 + lr][4 * q + lk] = ca[s4][q];
+        }
       }
       // issue order per column quad: MFMAs alternating with the buffer loads
       // and LDS writes (scheduling-group masks: 0x008 MFMA, 0x020 vector
       // memory read, 0x200 LDS write)
-      if constexpr (NQ == 4) {
+      if constexpr (MIR && NQ == 4) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -957,10 +962,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
           }
           __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(0x200, NQ, 0);
+          if constexpr (MIR) __builtin_amdgcn_sched_group_barrier(0x200, NQ, 0);
         }
       }
-      if (!c.pt) return;  // uniform across the workgroup (per term)
+      if (!MIR || !c.pt) return;  // uniform across the workgroup (per term)
       // LDS-only ordering: the prefetched global loads of the next chunk
       // stay in flight (a full fence would wait for them)
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
@@ -1104,24 +1109,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
+template <typename TA>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_symm16(
+    const SymProblem* __restrict__ probs, const SymTerm* __restrict__ terms, int tiles_max, int nwork, int nprob) {
+  symm16_body<TA, true>(probs, terms, tiles_max, nwork, nprob);
+}
+
+// The same for plain products: without the mirrored state three waves fit a SIMD.
+template <typename TA>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_rows16(
+    const SymProblem* __restrict__ probs, const SymTerm* __restrict__ terms, int tiles_max, int nwork, int nprob) {
+  symm16_body<TA, false>(probs, terms, tiles_max, nwork, nprob);
+}
+
 static void launch_symm16(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob,
-                          int max_m, int cap, int a_f32) {
+                          int max_m, int cap, int a_f32, int mir) {
   const int tiles = ceil_div(max_m, 256);
   const int nwork = ceil_div(nprob, 8) * 8 * tiles;
   const int capped = cap > 0 ? std::max(8, cap / 8 * 8) : nwork;
   const dim3 grid((unsigned)std::min(capped, nwork));
-  if (a_f32)
-    hipLaunchKernelGGL(k_symm16<float>, grid, dim3(256), 0, s, d_p, d_t, tiles, nwork, nprob);
-  else
-    hipLaunchKernelGGL(k_symm16<double>, grid, dim3(256), 0, s, d_p, d_t, tiles, nwork, nprob);
+  if (mir) {
+    if (a_f32)
+      hipLaunchKernelGGL(k_symm16<float>, grid, dim3(256), 0, s, d_p, d_t, tiles, nwork, nprob);
+    else
+      hipLaunchKernelGGL(k_symm16<double>, grid, dim3(256), 0, s, d_p, d_t, tiles, nwork, nprob);
+  } else {
+    if (a_f32)
+      hipLaunchKernelGGL(k_rows16<float>, grid, dim3(256), 0, s, d_p, d_t, tiles, nwork, nprob);
+    else
+      hipLaunchKernelGGL(k_rows16<double>, grid, dim3(256), 0, s, d_p, d_t, tiles, nwork, nprob);
+  }
 }
 
 void launch_symv(hipStream_t s, const SymProblem* d_p, const SymTerm* d_t, int nprob, int max_m,
-                 int max_n, int cap, int a_f32) {
+                 int max_n, int cap, int a_f32, int mir) {
   if (nprob <= 0 || max_m <= 0 || max_n <= 0) return;
   if (max_n > 16) throw Error(SPD_E_INVALID, "symmetric-pair product supports at most 16 columns");
   if (max_n > 4) {
-    launch_symm16(s, d_p, d_t, nprob, max_m, cap, a_f32);
+    launch_symm16(s, d_p, d_t, nprob, max_m, cap, a_f32, mir);
     SPD_HIP(hipGetLastError());
     return;
   }

@@ -108,6 +108,7 @@ struct LaunchRec {
   int max_k = 1 << 30;  // bound on the terms' inner dimension (gemm records)
   int cap = 0;          // workgroup cap (symmetric-pair records), 0 = none
   int a_f32 = 0;        // FP32 A operands (gemm records)
+  int mir = 1;          // symmetric-pair records: some term has a mirrored output
   const int* tiles = nullptr;  // tile list (block records)
   int ntiles = 0;
 };

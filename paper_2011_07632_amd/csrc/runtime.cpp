@@ -469,6 +469,7 @@ void Recorder::gemm_symm(Arena& a, hipStream_t s, const GemmBatch& b, double byt
   LaunchRec r{3, keep(a, s, probs), keep(a, s, terms), (int)probs.size(), b.max_m, b.max_n, 0, 0, bytes,
               -1};
   r.a_f32 = b.a_f32;
+  r.mir = 0;  // plain products: no mirrored outputs
   recs.push_back(r);
 }
 
@@ -737,7 +738,7 @@ void Recorder::replay(hipStream_t s) const {
                    r.max_n);
     else if (r.type == 3)
       launch_symv(s, (const SymProblem*)r.probs, (const SymTerm*)r.terms, r.nprob, r.max_m, r.max_n,
-                  r.cap, r.a_f32);
+                  r.cap, r.a_f32, r.mir);
     else
       launch_trsm(s, (const TrsmProblem*)r.probs, r.nprob, r.max_m, r.max_n, r.transA, 0);
   }
