@@ -315,6 +315,8 @@ void cpqr_global(hipStream_t s, Stage& st, const std::vector<CpqrProblem>& h, co
   std::vector<int2> fix, rc;
   for (int q = 0; q < nprob; ++q) {
     for (int c = 0; c < h[q].n; c += cb) wg.push_back(make_int4(q, c, std::min(h[q].n, c + cb), 0));
+    // a problem without columns still needs the workgroup that sets up its state
+    if (h[q].n <= 0) wg.push_back(make_int4(q, 0, 0, 0));
     const int km = std::min(std::min(h[q].m, h[q].n), h[q].maxrank);
     for (int t = 0; t < km; ++t) fix.push_back(make_int2(q, t));
     for (int j = 0; j < h[q].n; ++j) rc.push_back(make_int2(q, j));
