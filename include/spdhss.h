@@ -119,7 +119,7 @@ typedef enum {
  * exceed l = max(2c, c + 16) (c candidates), the proxy matrix is first
  * multiplied by an M x l standard normal sketch (entry (t, j): SplitMix64 on
  * the counter (t << 24) | j under sketch_seed, then Box-Muller), a randomized
- * interpolative decomposition.  c may not exceed 4000 (SPD_E_INVALID). */
+ * interpolative decomposition.  c may not exceed 8000 (SPD_E_INVALID). */
 typedef struct {
   int32_t leaf_size;            /* max points per leaf, in [1, 512] */
   double eta;                   /* admissibility: r_i + r_j <= eta * |c_i - c_j| */

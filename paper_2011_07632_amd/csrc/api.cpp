@@ -455,7 +455,7 @@ spd_status spd_test_cpqr(double* A, double* Q, int32_t* piv, int32_t* rank, doub
   SPD_REQUIRE(A && piv && rank && batch >= 1 && m >= 1 && n >= 1 && maxrank >= 0, SPD_E_INVALID,
               "bad args");
   if (which == 0) SPD_REQUIRE(cpqr_reg_fits(m, n) && Q, SPD_E_INVALID, "shape exceeds register kernel");
-  if (which == 1) SPD_REQUIRE(m <= kCpqrBigRows && n <= 4096, SPD_E_INVALID, "shape too large");
+  if (which == 1) SPD_REQUIRE(m <= kCpqrWideRows && n <= 4096, SPD_E_INVALID, "shape too large");
   hipStream_t s = as_stream(stream);
   Stage st;
   Arena a;

@@ -199,6 +199,9 @@ void launch_cpqr_formq(hipStream_t s, const CpqrProblem* d_p, int nprob);
 // Above 2048 rows (at most kCpqrBigRows) every problem must carry its nrm
 // workspace.
 constexpr int kCpqrBigRows = 8000;
+// rows of the wide form (cpqr_global above 2048 rows): the Householder vector
+// is staged in LDS up to kCpqrBigRows rows and read from the pivot column above
+constexpr int kCpqrWideRows = 16000;
 void launch_cpqr_glob(hipStream_t s, const CpqrProblem* d_p, int nprob, int max_m,
                       int max_n);
 // The wide form of the global-memory variant (one launch per step, columns

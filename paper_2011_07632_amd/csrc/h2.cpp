@@ -178,8 +178,8 @@ void h2_build_impl(H2Model& H, const double* points, int64_t npts) {
       const int l = std::max(2 * jb.c, jb.c + 16);
       jb.sk = jb.M > l;
       jb.m = jb.sk ? l : jb.M;
-      SPD_REQUIRE(jb.m <= kCpqrBigRows, SPD_E_INVALID,
-                  "H^2 proxy ID: more than 4000 candidates at node " + std::to_string(v) +
+      SPD_REQUIRE(jb.m <= kCpqrWideRows, SPD_E_INVALID,
+                  "H^2 proxy ID: more than 8000 candidates at node " + std::to_string(v) +
                       " (level " + std::to_string(lev) + ")");
       H.proxy_n[v] = jb.per;
       H.sketched[v] = jb.sk;

@@ -2077,11 +2077,14 @@ __global__ __launch_bounds__(1024) void k_cpqr_wide_norms(const CpqrProblem* __r
   }
 }
 
+// vlds: the Householder vector is staged in LDS (at most kCpqrBigRows rows);
+// otherwise every use reads it from the pivot column, which nobody writes
+// during the step.
 __global__ __launch_bounds__(1024) void k_cpqr_wide_step(const CpqrProblem* __restrict__ probs,
                                                          const int4* __restrict__ wg, int t,
-                                                         int* done) {
+                                                         int* done, int vlds) {
   constexpr int NW = 16;
-  extern __shared__ double vbuf[];  // m
+  extern __shared__ double vbuf[];  // m, when vlds
   const int4 g = wg[blockIdx.x];
   const CpqrProblem P = probs[g.x];
   const CpqrWs ws = cpqr_ws(P);
@@ -2112,11 +2115,17 @@ __global__ __launch_bounds__(1024) void k_cpqr_wide_step(const CpqrProblem* __re
   const double alpha = (xt >= 0.0) ? -nrm : nrm;
   const double beta = 1.0 / (nrm * (nrm + fabs(xt)));
   const bool first = g.y == 0;  // the problem's first workgroup records the step
-  for (int row = threadIdx.x; row < m; row += 1024) {
-    const double v = row < t ? 0.0 : (row == t ? xt - alpha : P.A[row + (int64_t)bi * lda]);
-    vbuf[row] = v;
-    if (first && P.hbeta) P.V[row + (int64_t)t * m] = v;
+  const double* pcol = P.A + (int64_t)bi * lda;
+  if (vlds || (first && P.hbeta)) {
+    for (int row = threadIdx.x; row < m; row += 1024) {
+      const double v = row < t ? 0.0 : (row == t ? xt - alpha : pcol[row]);
+      if (vlds) vbuf[row] = v;
+      if (first && P.hbeta) P.V[row + (int64_t)t * m] = v;
+    }
   }
+  auto vat = [&](int row) {  // the vector's entry in row >= t
+    return vlds ? vbuf[row] : (row == t ? xt - alpha : pcol[row]);
+  };
   if (first && threadIdx.x == 0) {
     if (P.hbeta) P.hbeta[t] = beta;
     P.piv[t] = bi;
@@ -2132,12 +2141,12 @@ __global__ __launch_bounds__(1024) void k_cpqr_wide_step(const CpqrProblem* __re
     }
     double d = 0.0;
     for (int row = lane; row < m; row += 64)
-      if (row >= t) d += vbuf[row] * P.A[row + col * lda];
+      if (row >= t) d += vat(row) * P.A[row + col * lda];
     d = wave_sum(d);
     double s2 = 0.0;
     for (int row = lane; row < m; row += 64) {
       if (row < t) continue;
-      const double x = P.A[row + col * lda] - beta * d * vbuf[row];
+      const double x = P.A[row + col * lda] - beta * d * vat(row);
       P.A[row + col * lda] = x;
       if (row > t) s2 += x * x;
     }
@@ -2193,9 +2202,10 @@ void launch_cpqr_wide_norms(hipStream_t s, const CpqrProblem* d_p, const int4* d
 void launch_cpqr_wide_step(hipStream_t s, const CpqrProblem* d_p, const int4* d_wg, int nwg,
                            int max_m, int t, int* d_done) {
   if (nwg <= 0) return;
-  SPD_REQUIRE(max_m <= kCpqrBigRows, SPD_E_INVALID, "cpqr: more than 8000 rows");
-  hipLaunchKernelGGL(k_cpqr_wide_step, dim3(nwg), dim3(1024), (size_t)max_m * sizeof(double), s, d_p,
-                     d_wg, t, d_done);
+  SPD_REQUIRE(max_m <= kCpqrWideRows, SPD_E_INVALID, "cpqr: more than 16000 rows");
+  const int vlds = max_m <= kCpqrBigRows ? 1 : 0;
+  hipLaunchKernelGGL(k_cpqr_wide_step, dim3(nwg), dim3(1024), vlds ? (size_t)max_m * sizeof(double) : 0, s,
+                     d_p, d_wg, t, d_done, vlds);
   SPD_HIP(hipGetLastError());
 }
 void launch_cpqr_wide_finish(hipStream_t s, const CpqrProblem* d_p, int nprob, const int2* d_fix,

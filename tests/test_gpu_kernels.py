@@ -121,8 +121,10 @@ def test_trsm(B, n, nrhs, trans, upper):
 
 @pytest.mark.parametrize("m,n,which", [(245, 110, 0), (63, 110, 0), (200, 110, 0), (300, 110, 0),
                                        (1024, 245, 1), (512, 300, 1),
-                                       # above 2048 rows: the LDS-staged variant (the sketched proxy ID)
-                                       (3000, 400, 1), (2100, 1200, 1)])
+                                       # above 2048 rows: the wide form with the Householder vector in
+                                       # LDS (the sketched proxy ID), and above 8000 rows read from the
+                                       # pivot column
+                                       (3000, 400, 1), (2100, 1200, 1), (9000, 300, 1)])
 def test_cpqr(B, m, n, which):
     from oracle.linalg import CPQR
     rng = np.random.default_rng(m + n)
