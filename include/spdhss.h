@@ -301,8 +301,9 @@ typedef struct {
  * ulv_factor_ex, pcg_solve, destroy) on `workers` host threads, each with its
  * own HIP stream on the calling thread's device, so that the GPU works on
  * several instances at once (the level-by-level rank read-backs of one
- * instance block only its worker).  Every instance gives the same result as
- * the same calls made alone.  Returns SPD_E_INVALID for bad arguments
+ * instance block only its worker).  Workers take the instances largest
+ * first (by rows).  Every instance gives the same result as the same calls
+ * made alone.  Returns SPD_E_INVALID for bad arguments
  * (count < 0, workers < 1, null pointers); otherwise SPD_OK, with each
  * instance's own status in results[i] (its message is not kept).  The
  * instances' device buffers must not overlap where they are written. */

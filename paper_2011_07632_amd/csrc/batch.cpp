@@ -95,6 +95,16 @@ extern "C" spd_status spd_solve_batch(const spd_instance* instances, int32_t cou
     spd::set_last_error("no current device");
     return SPD_E_DEVICE;
   }
+  // largest instances first (longest-processing-time order, with the rows
+  // as the cost estimate): a large instance taken last would otherwise run
+  // on after the others have finished
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  auto rows = [&](int i) {
+    const spd_instance& q = instances[i];
+    return (int64_t)(q.kernel.kind == SPD_K_RPY ? 3 : 1) * q.n;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return rows(a) > rows(b); });
   std::atomic<int> next{0};
   std::atomic<int> setup_fail{0};
   auto worker = [&]() {
@@ -107,7 +117,7 @@ extern "C" spd_status spd_solve_batch(const spd_instance* instances, int32_t cou
       setup_fail = 1;
       return;
     }
-    for (int i = next++; i < count; i = next++) spd::run_instance(instances[i], s, results[i]);
+    for (int j = next++; j < count; j = next++) spd::run_instance(instances[order[j]], s, results[order[j]]);
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
   };
@@ -122,7 +132,7 @@ extern "C" spd_status spd_solve_batch(const spd_instance* instances, int32_t cou
       spd::set_last_error("stream creation failed");
       return SPD_E_DEVICE;
     }
-    for (int i = next++; i < count; i = next++) spd::run_instance(instances[i], s, results[i]);
+    for (int j = next++; j < count; j = next++) spd::run_instance(instances[order[j]], s, results[order[j]]);
     (void)hipStreamDestroy(s);
   }
   return SPD_OK;
