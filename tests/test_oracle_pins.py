@@ -227,6 +227,25 @@ def test_h2_matches_dense_kernel_matrix():
     assert err <= 10 * h.tol
 
 
+@pytest.mark.parametrize("kind,pset,n,leaf,ell", [("gaussian", "cube", 1500, 64, 0.3), ("matern32", "ball", 1200, 100, 0.2),
+                                                   ("rpy", "ball1", 500, 120, 0.29)])
+def test_h2_on_the_box_tree_matches_dense(kind, pset, n, leaf, ell):
+    """The H^2 construction on the 2^d-ary box-bisection tree (ragged leaves;
+    for the RPY tensor the three rows of a particle stay in one box) still
+    reproduces sigma*I + K to the order of its tolerance."""
+    X = workloads.points(pset, n, 9)
+    h = H2(X, kind, ell, 0.0 if kind == "rpy" else 1e-2, leaf, 1e-8, shells=8, per_shell=128, tree_kind="box")
+    assert h.tree.kind == "box" and h.tree.D % 3 == 0
+    A, Ah = h.exact_dense(), h.dense()
+    assert np.linalg.norm(A - Ah) / np.linalg.norm(A) <= 10 * h.tol
+    if kind == "rpy":  # rows 3p, 3p+1, 3p+2 share a leaf
+        T = h.tree
+        for v in T.leaves():
+            parts = T.perm[T.rng(v)] // 3
+            for q in np.unique(parts):
+                assert np.count_nonzero(parts == q) == 3
+
+
 def test_h2_matvec_matches_assembled(h2s):
     Ah = dense_of(h2s)
     x = np.random.default_rng(2).standard_normal((h2s.tree.N, 3))
