@@ -84,6 +84,11 @@ CASES = {
                                                 kernel="matern32", ell=0.2, shift=1e-2, leaf=128, max_rank=40,
                                                 seed_base=13, tree="box"),
                         shells=6, per_shell=96),
+    # the RPY tensor on the box-bisection tree: 1,000 particles (3,000 rows),
+    # leaves of 12 to 96 rows, a particle's three rows in one leaf
+    "rpybox1000": dict(w=workloads.RPY_SMALL.with_(name="rpy-a0.29-N1000-ball1-box", n=1000, leaf=150,
+                                                   seed_base=14, tree="box"),
+                       shells=8, per_shell=128),
     # inverse multiquadric, fixed-rank form (tol = 0)
     "imq1200": dict(w=workloads.SMALL.with_(name="imq-c0.1-N1200", n=1200, kernel="imq", ell=0.1,
                                             shift=1e-3, leaf=30, max_rank=20, hss_tol=0.0, seed_base=9),
