@@ -140,7 +140,8 @@ def cpu_baseline(w, n_sample: int, iters_gpu: int, iters_sample: int = 40) -> di
     iterations), with BLAS on every host core.  The measured times are
     reported as they are; `value` extrapolates them to the full workload
     (SPD-HSS build by N log N, one iteration by N, times the GPU's iteration
-    count), so it is an estimate, labelled as such."""
+    count), so it is an estimate, labelled as such.  Beside it, the oracle is
+    timed unscaled, end to end, on the small configuration."""
     from threadpoolctl import threadpool_info
     from oracle.h2 import H2 as OH2
     from oracle.pcg import pcg as opcg
@@ -162,6 +163,7 @@ def cpu_baseline(w, n_sample: int, iters_gpu: int, iters_sample: int = 40) -> di
     scale_n = w.n / n_sample
     build_full = t_build * scale_n * np.log(w.n) / np.log(n_sample)
     solve_full = t_it * scale_n * iters_gpu
+    small = oracle_small_end_to_end()
     cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     return {"value": round(build_full + solve_full, 1), "unit": "s", "cores": cores, "kind": "oracle",
             "extrapolated": True,
@@ -171,7 +173,23 @@ def cpu_baseline(w, n_sample: int, iters_gpu: int, iters_sample: int = 40) -> di
                        f"iteration x (N ratio) x {iters_gpu} GPU iterations"),
             "sample_n": n_sample, "sample_seconds": round(t_h2 + t_build + t_pcg, 2),
             "sample_build_s": round(t_build, 3), "sample_iteration_s": round(t_it, 4),
-            "host": host_facts()}
+            "small_config_end_to_end": small, "host": host_facts()}
+
+
+def oracle_small_end_to_end() -> dict:
+    """The oracle, unchanged and unscaled, on the small configuration
+    (workloads.SMALL, N = 2,000): H^2 build, SPD-HSS build and PCG to its
+    tolerance, timed end to end."""
+    from oracle.h2 import H2 as OH2
+    from oracle.pcg import pcg as opcg
+    from oracle.spdhss import SPDHSS as OHSS
+    w = workloads.SMALL
+    t0 = time.perf_counter()
+    h = OH2(w.points(), w.kernel, w.ell, w.shift, w.leaf, w.h2_tol, eta=w.eta)
+    s = OHSS(h, w.omega()[h.tree.perm], w.hss_tol, w.max_rank, "chol")
+    _, it, res = opcg(h.matvec, s.solve, w.rhs()[h.tree.perm], w.pcg_tol, 5000)
+    return {"workload": w.name, "n": w.n, "nrhs": w.nrhs, "seconds": round(time.perf_counter() - t0, 3),
+            "pcg_iterations": int(np.max(it)), "relres_max": float(np.max(res))}
 
 
 def run_batch(args, torch, P):

@@ -71,3 +71,11 @@ def test_default_workload_is_the_1m_gaussian_configuration():
         (1_000_000, "gaussian", 0.2, 1e-3, 400, 1e-6, 1e-1, 16)
     src = open(os.path.join(ROOT, "bench.py")).read()
     assert 'ap.add_argument("--workload", default=workloads.HEADLINE.name' in src
+
+
+def test_oracle_small_configuration_end_to_end():
+    """The unscaled oracle leg of the CPU baseline solves the small
+    configuration to its tolerance."""
+    r = bench.oracle_small_end_to_end()
+    assert r["n"] == 2000 and r["seconds"] > 0
+    assert r["relres_max"] <= 1e-8 and 1 <= r["pcg_iterations"] < 5000
