@@ -179,7 +179,7 @@ SERVE_SEED = 100 * 1004
 
 
 def serve_requests(count: int = 64, rate: float = 20.0, seed: int = 4004, n_lo: int = 10_000,
-                   n_hi: int = 100_000, repeat: float = 0.0) -> list:
+                   n_hi: int = 1_000_000, repeat: float = 0.0) -> list:
     """[(arrival seconds, Workload, key)] sorted by arrival.  With probability
     `repeat` a request (after the first) solves new right-hand sides on the
     matrix of an earlier non-repeated request, drawn uniformly; `key` names
